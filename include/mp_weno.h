@@ -1,0 +1,182 @@
+/*
+ * mp_weno.h -- C ABI of the MI355X (gfx950) implementation of the consistent,
+ * bound-preserving finite-volume WENO scheme for compressible two-/N-phase
+ * flow of Huang, "Consistent and bound-preserving finite-volume WENO scheme
+ * for compressible two-/N-phase flows with Phase-Field mechanism".
+ *
+ * The library advances the hyperbolic step of the paper's fractional-step
+ * method (Sec. 2.2.1, Eq. (3)) on uniform grids:
+ *   WENO5 with the relative-smoothness weights of Eq. (15) on the primitive
+ *   variables, the coupled reconstruction of phase masses and volume fractions
+ *   (Eq. (16)), the positivity / unity / cell-admissibility limiters
+ *   (Eqs. (17)-(20)) or the consistent limiter (Eqs. (23)-(25)), the energy
+ *   limiter (Eq. (21)), the HLLC or HLL flux with the consistent face velocity
+ *   (Sec. 2.2.1), the source alpha_p (1 + K_p) div(u) of Eq. (1), third-order
+ *   SSP Runge-Kutta (Sec. 4), the stiffened-gas / Le Metayer EOS of Eq. (26)
+ *   with the pressure of Eq. (27), and the CFL time step.
+ *
+ * Plain C99.  No HIP or torch types appear here: device memory is passed as
+ * plain pointers, the HIP stream as void*.
+ *
+ * Conserved-state layout (Eq. (1), n_U = 2N + d + 1, Eq. (8)):
+ *   double U[n_U][n_z][n_y][n_x]  (structure of arrays, x fastest) with the
+ *   component order m_1..m_N (m_p = alpha_p rho_p), (rho u)_1..(rho u)_d,
+ *   rho E, alpha_1..alpha_N.  All N volume fractions are stored.
+ *
+ * Ownership: the caller owns every U and every output array and keeps them
+ * alive until the stream has completed the call.  The library owns the
+ * context and its scratch memory (RK stage buffers, reductions).  Contexts
+ * are independent (no global state); one context must not be used from two
+ * host threads at once.
+ *
+ * Errors: every entry point returns an mp_status.  On MP_ERR_HIP the HIP
+ * error text is kept in the context (mp_weno_last_error).  Input states must
+ * lie in the admissible set of Eq. (8) with rho > 0; without check_bounds the
+ * result for inadmissible input is unspecified (but every memory access stays
+ * inside the arrays described here).
+ */
+#ifndef MP_WENO_H
+#define MP_WENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MP_WENO_ABI_VERSION 1
+#define MP_MAXP 8        /* largest N this header describes                 */
+#define MP_DIAG_LEN 32   /* doubles per instance written by mp_weno_diag    */
+
+typedef enum {
+  MP_OK = 0,
+  MP_ERR_ARG = -1,          /* invalid argument (message in the context)   */
+  MP_ERR_HIP = -2,          /* a HIP runtime call failed                    */
+  MP_ERR_OOM = -3,          /* device allocation failed                     */
+  MP_ERR_INADMISSIBLE = -4, /* a state left the admissible set (Eq. (8))    */
+  MP_ERR_NONFINITE = -5,    /* a state holds NaN or Inf                     */
+  MP_ERR_SOLVER = -6,       /* reserved: iterative solver did not converge  */
+  MP_ERR_UNSUPPORTED = -7   /* valid but not built (e.g. N above the build) */
+} mp_status;
+
+enum { MP_BC_PERIODIC = 0, MP_BC_OUTFLOW = 1 };
+enum { MP_RECON_WENO_C = 0, MP_RECON_WENO_CL = 1 };
+enum { MP_FLUX_HLLC = 0, MP_FLUX_HLL = 1 };
+enum { MP_MODEL_ALLAIRE = 0, MP_MODEL_KAPILA = 1 };
+enum { MP_PREC_FP64 = 0, MP_PREC_MIXED = 1 };
+enum { MP_WHERE_DEVICE = 0, MP_WHERE_HOST = 1 };
+
+/* One uniform-grid problem instance (Sec. 2.1 and Eq. (26)). */
+typedef struct {
+  int32_t ndim;            /* 1 or 2                                         */
+  int32_t n[3];            /* cells per direction, n[k] >= 1; unused = 1     */
+  double dx[3];            /* uniform cell size per direction, > 0           */
+  int32_t bc[3][2];        /* MP_BC_* at the low/high end of each direction  */
+  int32_t nphase;          /* N, 1 <= N <= mp_weno_max_phases()              */
+  double gamma[MP_MAXP];   /* gamma_p > 1 (Eq. (26))                         */
+  double pinf[MP_MAXP];    /* P^inf_p (Eq. (26))                             */
+  double D[MP_MAXP];       /* D_p (Eq. (26))                                 */
+  double pmin[MP_MAXP];    /* (P_min)_p of the energy functional, Eq. (9)    */
+  double cT[MP_MAXP];      /* C^T_p (Eq. (26)); diagnostics only, may be 0   */
+  double t_end;            /* end time: the CFL step is clipped to reach it;
+                              0 disables the clipping                        */
+  double *U;               /* device pointer to the caller-owned state       */
+} mp_weno_instance;
+
+/* Scheme switches shared by all instances of a context. */
+typedef struct {
+  int32_t recon;           /* MP_RECON_WENO_C (Sec. 3.4) or _WENO_CL (3.4.1) */
+  int32_t flux;            /* MP_FLUX_HLLC (Sec. 4.1) or MP_FLUX_HLL (4.2)   */
+  int32_t model;           /* MP_MODEL_ALLAIRE (K_p = 0) or _KAPILA (Sec. 2.1)*/
+  int32_t precision;       /* MP_PREC_FP64 or MP_PREC_MIXED                  */
+  int32_t energy_limiter;  /* 1: apply Eq. (21) (default); 0: skip it       */
+  int32_t phase_field;     /* must be 0 (the Phase-Field step is not built)  */
+  double cfl;              /* CFL number of the time step (> 0)              */
+  double eta_over_dx;      /* reserved (Phase-Field interface thickness)     */
+  double cg_rtol;          /* reserved                                       */
+  int32_t cg_maxit;        /* reserved                                       */
+  int32_t check_bounds;    /* 1: mp_weno_step checks the result (see below)  */
+  int32_t use_graph;       /* 1: replay mp_weno_step as a captured HIP graph */
+} mp_weno_opts;
+
+typedef struct mp_weno_ctx mp_weno_ctx;
+
+/* MP_WENO_ABI_VERSION of the built library. */
+int32_t mp_weno_abi_version(void);
+/* Largest number of phases the built kernels support. */
+int32_t mp_weno_max_phases(void);
+
+/* Create a context for n_inst >= 1 instances.  inst[] and opt are copied;
+ * the instances' U pointers are kept (not owned).  hip_stream is a
+ * hipStream_t (NULL: the null stream; not allowed with use_graph, which
+ * captures on the stream); every later call is ordered on it.
+ * Allocates the scratch: two RK stage buffers and one direction accumulator
+ * per instance (3 n_U doubles per cell) plus small reduction buffers.
+ * Errors: MP_ERR_ARG (bad sizes, gamma <= 1, dx <= 0, ...), MP_ERR_UNSUPPORTED
+ * (N or ndim beyond the build, phase_field != 0), MP_ERR_OOM, MP_ERR_HIP.
+ * On error *ctx is NULL. */
+mp_status mp_weno_init(mp_weno_ctx **ctx, int32_t n_inst,
+                       const mp_weno_instance *inst, const mp_weno_opts *opt,
+                       void *hip_stream);
+
+/* The hyperbolic semi-discrete operator L(U) of Eq. (3) (summed over the
+ * directions) for every instance.  U_in: host array of n_inst device
+ * pointers (NULL: use the instances' U); dUdt: host array of n_inst device
+ * pointers to caller-owned outputs in the U layout.  Asynchronous on the
+ * context's stream.  This is the parity entry point. */
+mp_status mp_weno_rhs(mp_weno_ctx *ctx, const double *const *U_in,
+                      double *const *dUdt);
+
+/* CFL time step per instance: dt = cfl / max_cells sum_d (|u_d| + c)/dx_d,
+ * clipped so that t + dt <= t_end (t is the instance's time, advanced by
+ * mp_weno_step).  where = MP_WHERE_DEVICE: dt is a device array of n_inst
+ * doubles (asynchronous); MP_WHERE_HOST: a host array (synchronises the
+ * stream). */
+mp_status mp_weno_dt(mp_weno_ctx *ctx, double *dt, int32_t where);
+
+/* Advance every instance by one third-order SSP Runge-Kutta step, in place in
+ * the instances' U.  dt_dev: device array of n_inst time steps, or NULL to
+ * use the CFL step computed on the device inside the same call.  Each
+ * instance's time and step counter advance on the device.  Asynchronous,
+ * except with check_bounds = 1: then the call synchronises, checks the new
+ * states for non-finite values (MP_ERR_NONFINITE) and for violations of the
+ * bounds of Eq. (8) (MP_ERR_INADMISSIBLE); on either error every U is
+ * restored to its value before the step and the time is not advanced. */
+mp_status mp_weno_step(mp_weno_ctx *ctx, const double *dt_dev);
+
+/* Diagnostics per instance, MP_DIAG_LEN doubles each (out[i*MP_DIAG_LEN+k]):
+ *   k = 0 .. n_U-1 : sum over cells of U_c times the cell volume
+ *   k = 20         : max over cells |sum_p alpha_p - 1|
+ *   k = 21, 22, 23 : min m_p, min alpha_p, max alpha_p over cells and phases
+ *   k = 24         : min over cells of psi(U) (Eq. (9))
+ *   k = 25         : number of non-finite entries
+ *   k = 26, 27     : instance time t and number of steps taken
+ * where = MP_WHERE_HOST (synchronises) or MP_WHERE_DEVICE. */
+mp_status mp_weno_diag(mp_weno_ctx *ctx, double *out, int32_t where);
+
+/* Set the time of every instance (host values; asynchronous copy). */
+mp_status mp_weno_set_time(mp_weno_ctx *ctx, const double *t);
+
+/* Profiling: which = 0 off; 1, 2, 3 record a HIP event pair on the context's
+ * stream around every launch of the x-sweep kernel, the y-sweep kernel, or
+ * the whole RK stage (both sweeps) made by mp_weno_step (graph replay is
+ * bypassed while profiling).  Resets the recorded launches. */
+mp_status mp_weno_profile(mp_weno_ctx *ctx, int32_t which);
+
+/* Total elapsed milliseconds and number of the launches recorded since the
+ * last reset (synchronises the stream); reset = 1 starts a new window. */
+mp_status mp_weno_timing(mp_weno_ctx *ctx, int32_t reset, double *ms,
+                         int64_t *launches);
+
+/* Free the context and its scratch; never touches U.  NULL is accepted. */
+mp_status mp_weno_destroy(mp_weno_ctx *ctx);
+
+/* Static text for a status code. */
+const char *mp_weno_strerror(mp_status s);
+/* Text of the last error recorded in ctx ("" if none). */
+const char *mp_weno_last_error(const mp_weno_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

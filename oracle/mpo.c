@@ -226,13 +226,33 @@ void mpo_wenojs_weights(const double beta[3], const double d[3], double eps,
   for (int k = 0; k < 3; ++k) w[k] = a[k] / s;
 }
 
-/* Eq. (10) with the weights of Eq. (15). */
+/* Candidate increments f^(s) - fbar_i at both faces, written with the
+ * differences a = q_{i-2} - q_i, b = q_{i-1} - q_i, c = q_{i+1} - q_i,
+ * e = q_{i+2} - q_i, so that a constant sub-stencil gives an exact zero. */
+void mpo_weno5_increments(const double q[5], double dL[3], double dR[3]) {
+  const double a = q[0] - q[2], b = q[1] - q[2], c = q[3] - q[2],
+               e = q[4] - q[2];
+  dL[0] = (2.0 * a - 7.0 * b) / 6.0;
+  dL[1] = (2.0 * c - b) / 6.0;
+  dL[2] = (5.0 * c - e) / 6.0;
+  dR[0] = (5.0 * b - a) / 6.0;
+  dR[1] = (2.0 * b - c) / 6.0;
+  dR[2] = (2.0 * e - 7.0 * c) / 6.0;
+}
+
+/* Eq. (10) with the weights of Eq. (15).  Reading: the weighted sum is
+ * evaluated as fbar + sum_s w_s (f^(s) - fbar), equal to sum_s w_s f^(s)
+ * since the weights sum to one, but exact on a constant stencil.  The
+ * plain sum returns fbar (1 +- ulp) there, which the consistent limiter of
+ * Eq. (25) reads as a slope and answers by limiting that phase to first
+ * order; the paper's limiter leaves zero-gradient fractions untouched
+ * (Sec. 3.4.1). */
 static void weno5w_with(const double q[5], const double wL[3],
                         const double wR[3], double *qL, double *qR) {
-  double cL[3], cR[3];
-  mpo_weno5_candidates(q, cL, cR);
-  *qL = wL[0] * cL[0] + wL[1] * cL[1] + wL[2] * cL[2];
-  *qR = wR[0] * cR[0] + wR[1] * cR[1] + wR[2] * cR[2];
+  double dL[3], dR[3];
+  mpo_weno5_increments(q, dL, dR);
+  *qL = q[2] + (wL[0] * dL[0] + wL[1] * dL[1] + wL[2] * dL[2]);
+  *qR = q[2] + (wR[0] * dR[0] + wR[1] * dR[1] + wR[2] * dR[2]);
 }
 
 void mpo_weno5w(const double q[5], double *qL, double *qR) {

@@ -66,6 +66,9 @@ void mpo_weno5_beta(const double q[5], double beta[3]);
 /* Candidate values of the three sub-stencil polynomials at x_{i+1/2} (cL) and
  * at x_{i-1/2} (cR). */
 void mpo_weno5_candidates(const double q[5], double cL[3], double cR[3]);
+/* Candidate increments f^(s) - fbar_i (same faces as above), computed from
+ * differences of the stencil so that constant data gives exact zeros. */
+void mpo_weno5_increments(const double q[5], double dL[3], double dR[3]);
 /* Ideal weights d^(s) of the left-of-face (x_{i+1/2}) and right-of-face
  * (x_{i-1/2}) reconstructions. */
 void mpo_weno5_ideal(double dL[3], double dR[3]);

@@ -65,6 +65,7 @@ def lib():
         L.mpo_weno5_beta.argtypes = [dp, dp]
         L.mpo_weno5_candidates.argtypes = [dp, dp, dp]
         L.mpo_weno5_ideal.argtypes = [dp, dp]
+        L.mpo_weno5_increments.argtypes = [dp, dp, dp]
         L.mpo_wenow_weights.argtypes = [dp, dp, dp]
         L.mpo_wenojs_weights.argtypes = [dp, dp, C.c_double, dp]
         L.mpo_weno5w.argtypes = [dp, dp, dp]
@@ -217,6 +218,13 @@ def weno5_candidates(q):
     cl, cr = np.zeros(3), np.zeros(3)
     lib().mpo_weno5_candidates(_ptr(q), _ptr(cl), _ptr(cr))
     return cl, cr
+
+
+def weno5_increments(q):
+    q = _arr(q, 5)
+    dl, dr = np.zeros(3), np.zeros(3)
+    lib().mpo_weno5_increments(_ptr(q), _ptr(dl), _ptr(dr))
+    return dl, dr
 
 
 def weno5_ideal():

@@ -1,0 +1,249 @@
+"""Thin ctypes binding of libmpweno.so (include/mp_weno.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels
+of the library.  PyTorch provides device memory and the stream.  The binding
+raises if the library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpweno.so")
+MAXP = 8
+DIAG_LEN = 32
+
+OK, ERR_ARG, ERR_HIP, ERR_OOM, ERR_INADMISSIBLE, ERR_NONFINITE, ERR_SOLVER, \
+    ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+WHERE_DEVICE, WHERE_HOST = 0, 1
+
+
+class MpWenoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mp_weno status {status}: {msg}")
+        self.status = status
+
+
+class Instance(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int32), ("n", C.c_int32 * 3), ("dx", C.c_double * 3),
+        ("bc", (C.c_int32 * 2) * 3), ("nphase", C.c_int32),
+        ("gamma", C.c_double * MAXP), ("pinf", C.c_double * MAXP),
+        ("D", C.c_double * MAXP), ("pmin", C.c_double * MAXP),
+        ("cT", C.c_double * MAXP), ("t_end", C.c_double),
+        ("U", C.c_void_p),
+    ]
+
+
+class Opts(C.Structure):
+    _fields_ = [
+        ("recon", C.c_int32), ("flux", C.c_int32), ("model", C.c_int32),
+        ("precision", C.c_int32), ("energy_limiter", C.c_int32),
+        ("phase_field", C.c_int32), ("cfl", C.c_double),
+        ("eta_over_dx", C.c_double), ("cg_rtol", C.c_double),
+        ("cg_maxit", C.c_int32), ("check_bounds", C.c_int32),
+        ("use_graph", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (build it with paper_2608_00746_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.mp_weno_abi_version.restype = C.c_int32
+        L.mp_weno_max_phases.restype = C.c_int32
+        L.mp_weno_init.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(Instance),
+                                   C.POINTER(Opts), vp]
+        L.mp_weno_init.restype = C.c_int
+        L.mp_weno_rhs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp)]
+        L.mp_weno_rhs.restype = C.c_int
+        L.mp_weno_dt.argtypes = [vp, vp, C.c_int32]
+        L.mp_weno_dt.restype = C.c_int
+        L.mp_weno_step.argtypes = [vp, vp]
+        L.mp_weno_step.restype = C.c_int
+        L.mp_weno_diag.argtypes = [vp, vp, C.c_int32]
+        L.mp_weno_diag.restype = C.c_int
+        L.mp_weno_set_time.argtypes = [vp, C.POINTER(C.c_double)]
+        L.mp_weno_set_time.restype = C.c_int
+        L.mp_weno_destroy.argtypes = [vp]
+        L.mp_weno_destroy.restype = C.c_int
+        L.mp_weno_strerror.argtypes = [C.c_int]
+        L.mp_weno_strerror.restype = C.c_char_p
+        L.mp_weno_last_error.argtypes = [vp]
+        L.mp_weno_last_error.restype = C.c_char_p
+        L.mp_weno_profile.argtypes = [vp, C.c_int32]
+        L.mp_weno_profile.restype = C.c_int
+        L.mp_weno_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int64)]
+        L.mp_weno_timing.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["mp_weno_abi_version", "mp_weno_max_phases", "mp_weno_init",
+            "mp_weno_rhs", "mp_weno_dt", "mp_weno_step", "mp_weno_diag",
+            "mp_weno_set_time", "mp_weno_destroy", "mp_weno_strerror",
+            "mp_weno_last_error", "mp_weno_profile", "mp_weno_timing"]
+
+
+def make_instance(w, U_ptr):
+    """Fill the C instance struct from an inputs.Workload and a device pointer."""
+    s = Instance()
+    s.ndim = w.ndim
+    nn = list(w.n) + [1] * (3 - len(w.n))
+    dd = list(w.dx) + [1.0] * (3 - len(w.dx))
+    for k in range(3):
+        s.n[k] = int(nn[k])
+        s.dx[k] = float(dd[k])
+    bcl = list(w.bc) + [(0, 0)] * (3 - len(w.bc))
+    for k in range(3):
+        s.bc[k][0], s.bc[k][1] = int(bcl[k][0]), int(bcl[k][1])
+    s.nphase = w.N
+    for name, vals in (("gamma", w.gamma), ("pinf", w.pinf), ("D", w.D),
+                       ("pmin", w.pmin), ("cT", w.cT)):
+        arr = getattr(s, name)
+        for p in range(w.N):
+            arr[p] = float(vals[p])
+    s.t_end = float(w.t_end)
+    s.U = C.c_void_p(int(U_ptr))
+    return s
+
+
+def make_opts(o, check_bounds=False, use_graph=False):
+    x = Opts()
+    x.recon, x.flux, x.model = int(o.recon), int(o.flux), int(o.model)
+    x.precision, x.energy_limiter = int(o.precision), int(o.energy_limiter)
+    x.phase_field = int(o.phase_field)
+    x.cfl = float(o.cfl)
+    x.eta_over_dx = float(o.eta_over_dx)
+    x.cg_rtol, x.cg_maxit = 1e-12, 1000
+    x.check_bounds, x.use_graph = int(check_bounds), int(use_graph)
+    return x
+
+
+class Solver:
+    """Instances advanced together by one context.
+
+    workloads: list of inputs.Workload (same Options for all); their states
+    are copied to the GPU once and stay resident (self.U[i], torch float64).
+    """
+
+    def __init__(self, workloads, opts=None, device="cuda:0", stream=None,
+                 check_bounds=False, use_graph=False):
+        import torch
+        if not isinstance(workloads, (list, tuple)):
+            workloads = [workloads]
+        self.torch = torch
+        self.w = list(workloads)
+        self.opts = opts or self.w[0].opts
+        self.device = torch.device(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self.U = [torch.from_numpy(np.ascontiguousarray(w.U)).to(self.device)
+                  for w in self.w]
+        self._inst = (Instance * len(self.w))(
+            *[make_instance(w, u.data_ptr()) for w, u in zip(self.w, self.U)])
+        self._opts = make_opts(self.opts, check_bounds, use_graph)
+        self.ctx = C.c_void_p()
+        st = lib().mp_weno_init(C.byref(self.ctx), len(self.w), self._inst,
+                                C.byref(self._opts), C.c_void_p(self.stream.cuda_stream))
+        self._check(st)
+        torch.cuda.synchronize(self.device)
+
+    def _enter(self):
+        """Order the context stream after work queued on torch's stream."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _leave(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
+    def _check(self, st):
+        if st != OK:
+            msg = lib().mp_weno_strerror(st).decode()
+            if self.ctx:
+                extra = lib().mp_weno_last_error(self.ctx).decode()
+                if extra:
+                    msg += ": " + extra
+            raise MpWenoError(st, msg)
+
+    def rhs(self, U_in=None):
+        """L(U) per instance (list of torch tensors)."""
+        torch = self.torch
+        outs = [torch.empty_like(u) for u in self.U]
+        n = len(self.U)
+        ins = (C.c_void_p * n)(*[C.c_void_p((U_in[i] if U_in else self.U[i]).data_ptr())
+                                 for i in range(n)])
+        ptrs = (C.c_void_p * n)(*[C.c_void_p(o.data_ptr()) for o in outs])
+        self._enter()
+        self._check(lib().mp_weno_rhs(self.ctx, ins, ptrs))
+        self._leave()
+        return outs
+
+    def dt(self):
+        out = np.zeros(len(self.U))
+        self._check(lib().mp_weno_dt(self.ctx, out.ctypes.data_as(C.c_void_p), WHERE_HOST))
+        return out
+
+    def step(self, dt=None):
+        """One SSP-RK3 step; dt: None (CFL on device) or a float / sequence."""
+        if dt is None:
+            self._enter()
+            self._check(lib().mp_weno_step(self.ctx, None))
+            self._leave()
+            return
+        torch = self.torch
+        d = torch.as_tensor(np.broadcast_to(np.asarray(dt, dtype=np.float64),
+                                            (len(self.U),)).copy(), device=self.device)
+        self._dt_keep = d
+        self._enter()
+        self._check(lib().mp_weno_step(self.ctx, C.c_void_p(d.data_ptr())))
+        self._leave()
+
+    def diag(self):
+        out = np.zeros(len(self.U) * DIAG_LEN)
+        self._check(lib().mp_weno_diag(self.ctx, out.ctypes.data_as(C.c_void_p), WHERE_HOST))
+        return out.reshape(len(self.U), DIAG_LEN)
+
+    def set_time(self, t):
+        arr = (C.c_double * len(self.U))(*np.broadcast_to(np.asarray(t, float),
+                                                           (len(self.U),)))
+        self._check(lib().mp_weno_set_time(self.ctx, arr))
+
+    def profile(self, which):
+        """Record events around stage kernels: 0 off, 1 x, 2 y, 3 stage."""
+        self._check(lib().mp_weno_profile(self.ctx, int(which)))
+
+    def timing(self, reset=False):
+        """(total ms, launches) of the stage kernel since the last reset."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(lib().mp_weno_timing(self.ctx, int(reset), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def host(self, i=0):
+        self.torch.cuda.synchronize(self.device)
+        return self.U[i].cpu().numpy()
+
+    def close(self):
+        if self.ctx:
+            lib().mp_weno_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,39 @@
+"""Build the HIP library libmpweno.so in-tree for gfx950 with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "csrc", "mp_weno.hip")
+LIB = os.path.join(HERE, "libmpweno.so")
+ARCH = os.environ.get("MPWENO_ARCH", "gfx950")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def flags():
+    return [
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        # packed FP32 instructions stay off on the test machines
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-fno-fast-math", "-ffp-contract=fast-honor-pragmas",
+        "-munsafe-fp-atomics",
+        "-I", os.path.join(ROOT, "include"),
+    ]
+
+
+def build(verbose: bool = True, extra=None) -> str:
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC] + flags() + (extra or []) + ["-o", tmp, SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True, extra=sys.argv[1:])

@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Metrics (per conserved component c):
+* states after a window of steps: max_cells |U_gpu - U_orc| / max_cells |U_orc|
+  <= 1e-12;
+* L(U) from mp_weno_rhs, gated as the state increment of one stage:
+  dt_cfl * max_cells |L_gpu - L_orc| / max_cells |U_orc| <= 1e-12, and raw
+  max |L_gpu - L_orc| / max |L_orc| <= 1e-10.  The raw bound is looser because
+  L is a difference of fluxes that can be ~1e3 times larger than L itself
+  (the HLLC contact speed sums rho c terms of 1.4e6 in water while the
+  momentum RHS of an advected interface is ~1e3), so two correct FP64
+  evaluation orders differ there by ~1e3 ulp of L.
+Bitwise checks: absent phases, N vs N-1, graph replay and run-to-run
+determinism.
+"""
+import numpy as np
+import pytest
+
+from paper_2608_00746_amd import inputs as I
+from conftest import oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+TOL_RAW_RHS = 1e-10
+
+
+def _solver(w, **kw):
+    from paper_2608_00746_amd.binding import Solver
+    return Solver([w], **kw)
+
+
+def _scales(w, U=None):
+    """Per-component scales: each mass by its own max (the largest mass if
+    the phase is absent), momenta by the largest momentum magnitude (or
+    sqrt(rho rhoE) if the fluid is at rest), energy by max |rho E|, volume
+    fractions by 1."""
+    U = (w.U if U is None else U).reshape(w.nU, -1)
+    N, d = w.N, w.ndim
+    m = np.abs(U[:N]).max(axis=1)
+    mall = m.max()
+    mom = np.abs(U[N:N + d]).max()
+    E = np.abs(U[N + d]).max()
+    if mom == 0:
+        mom = np.sqrt(mall * E)
+    sc = np.empty(w.nU)
+    sc[:N] = np.where(m > 0, m, mall)
+    sc[N:N + d] = mom
+    sc[N + d] = E
+    sc[N + d + 1:] = 1.0
+    return sc
+
+
+def _rel_err(a, b, nU, scale=None):
+    a = a.reshape(nU, -1)
+    b = b.reshape(nU, -1)
+    d = np.abs(a - b).max(axis=1)
+    sc = np.abs(b).max(axis=1) if scale is None else scale
+    return d / np.where(sc > 0, sc, 1.0)
+
+
+def _check_rhs(oracle, w, tol=TOL):
+    s = _solver(w)
+    Lg = s.rhs()[0].cpu().numpy().reshape(-1)
+    s.close()
+    pb = oracle_problem(oracle, w)
+    U = w.U.reshape(-1)
+    Lo = pb.rhs(U)
+    dt = pb.dt(U, 0.0)
+    sc = _scales(w)
+    inc = dt * np.abs((Lg - Lo).reshape(w.nU, -1)).max(axis=1) / sc
+    Lmax = np.abs(Lo.reshape(w.nU, -1)).max(axis=1)
+    raw = _rel_err(Lg, Lo, w.nU)
+    # the raw relative error is meaningful only where L is above round-off
+    significant = dt * Lmax > 1e-10 * sc
+    print(w.name, "rhs raw rel err:", np.array2string(raw, precision=2),
+          "| dt-scaled:", np.array2string(inc, precision=2))
+    if not (inc <= tol).all():
+        D = np.abs((Lg - Lo).reshape(w.nU, -1))
+        c = int(np.argmax(D.max(axis=1)))
+        i = int(np.argmax(D[c]))
+        print("  worst component", c, "cell", i, "gpu", Lg.reshape(w.nU, -1)[:, i],
+              "orc", Lo.reshape(w.nU, -1)[:, i])
+    assert np.isfinite(Lg).all()
+    assert (inc <= tol).all(), inc
+    assert (raw[significant] <= TOL_RAW_RHS).all(), raw
+    return raw
+
+
+def test_rhs_advection_1d(oracle):
+    _check_rhs(oracle, I.advection_1d(200))
+
+
+CASES_1D = [
+    # N, flux, recon, energy, bc, seed
+    (1, 0, 0, 1, 0, 1), (2, 0, 0, 1, 0, 2), (2, 1, 1, 1, 1, 3), (3, 1, 0, 1, 0, 4),
+    (3, 0, 1, 0, 1, 5), (4, 1, 0, 1, 1, 6), (5, 0, 0, 1, 0, 7), (5, 1, 1, 1, 1, 8),
+]
+
+
+@pytest.mark.parametrize("N,flux,recon,energy,bc,seed", CASES_1D)
+def test_rhs_random_1d(oracle, N, flux, recon, energy, bc, seed):
+    w = I.random_state((300,), nphase=N, seed=seed, bc=bc,
+                       opts=I.Options(flux=flux, recon=recon, energy_limiter=energy))
+    _check_rhs(oracle, w)
+
+
+CASES_2D = [
+    # shape (ny, nx), N, flux, recon, bc, seed
+    ((37, 300), 2, 0, 0, 0, 11), ((70, 259), 2, 1, 0, 1, 12), ((33, 129), 3, 1, 1, 0, 13),
+    ((65, 64), 3, 0, 0, 1, 14), ((5, 600), 4, 1, 0, 0, 15), ((41, 41), 5, 0, 1, 1, 16),
+    ((1, 7), 2, 1, 0, 0, 17), ((9, 3), 2, 0, 0, 1, 18),
+]
+
+
+@pytest.mark.parametrize("shape,N,flux,recon,bc,seed", CASES_2D)
+def test_rhs_random_2d(oracle, shape, N, flux, recon, bc, seed):
+    w = I.random_state(shape, nphase=N, seed=seed, bc=bc,
+                       opts=I.Options(flux=flux, recon=recon))
+    _check_rhs(oracle, w)
+
+
+def test_rhs_kapila(oracle):
+    w = I.random_state((40, 130), nphase=3, seed=21, lowp=0.0,
+                       opts=I.Options(flux=1, model=1))
+    _check_rhs(oracle, w)
+
+
+def _fp64(w):
+    w.opts.precision = I.PREC_FP64
+    return w
+
+
+@pytest.mark.parametrize("make", [
+    lambda: I.advection_2d(64), lambda: I.shock_bubble_2d(256, 128),
+    lambda: I.shock_interface_n3(128), lambda: I.paper_five_phase(50),
+    lambda: I.paper_four_phase_miscible(50), lambda: I.air_helium_shock_tube(0.01),
+    lambda: I.smooth_2d(32), lambda: I.batched_instance(200, 3, 0.12, 1.2e9)])
+def test_rhs_paper_workloads(oracle, make):
+    _check_rhs(oracle, _fp64(make()))
+
+
+def test_rhs_full_size_shock_bubble(oracle):
+    """The 2048 x 1024 shock-bubble grid in the benchmark's launch shape,
+    every cell compared."""
+    _check_rhs(oracle, I.shock_bubble_2d(2048, 1024))
+
+
+def test_rhs_full_size_advection(oracle):
+    _check_rhs(oracle, I.advection_2d(512))
+
+
+WINDOWS = [
+    # workloads whose limiter decisions are well conditioned over the window
+    (lambda: I.advection_1d(200), 20),
+    (lambda: I.air_helium_shock_tube(0.01), 20),
+    (lambda: I.shock_bubble_2d(256, 128), 6),
+    (lambda: I.shock_interface_n3(128), 6),
+    (lambda: I.advection_2d(64), 4),
+    (lambda: I.paper_four_phase_miscible(50), 6),
+    (lambda: I.random_state((24, 280), nphase=2, seed=31, bc=1, lowp=0.0,
+                            opts=I.Options(flux=1, cfl=0.2)), 4),
+]
+
+
+@pytest.mark.parametrize("make,K", WINDOWS)
+def test_steps_window(oracle, make, K):
+    """States after K SSP-RK3 steps with the CFL step computed on each side.
+    The rough random states and the five-phase problem are left out of the
+    windows: there the positivity limiter of a phase with zero mean and a
+    face value at round-off level switches between 0 and 1 (Eq. (18)), so two
+    correct FP64 evaluation orders part ways; they are covered by the
+    single-evaluation parity above and by the invariant tests."""
+    w = _fp64(make())
+    pb = oracle_problem(oracle, w, t_end=0.0)
+    w.t_end = 0.0
+    s = _solver(w)
+    U = w.U.reshape(-1).copy()
+    for k in range(K):
+        dt_o = pb.dt(U, 0.0)
+        dt_g = s.dt()[0]
+        assert abs(dt_g - dt_o) <= 1e-12 * dt_o
+        U = pb.step(U, dt_o)
+        s.step()
+    Ug = s.host(0)
+    err = _rel_err(Ug, U, w.nU, _scales(w, U))
+    print(w.name, "state rel err after", K, "steps:", np.array2string(err, precision=2))
+    assert (err <= TOL).all(), err
+    d = s.diag()[0]
+    do = pb.diag(U)
+    assert d[27] == K
+    assert d[26] > 0
+    vol = np.prod(w.dx) * w.ncells
+    sc = _scales(w, U)
+    for c in range(w.nU):
+        assert abs(d[c] - do[c]) <= 1e-12 * sc[c] * vol, c
+    for k, ko in ((21, 1), (22, 2), (23, 3)):
+        assert abs(d[k] - do[w.nU + ko]) <= 1e-12 * (abs(do[w.nU + ko]) + 1e-300)
+    s.close()
+
+
+def test_absent_phase_and_reduction_bitwise(oracle):
+    """Sec. 3.4: N = 3 with phase 3 absent reproduces N = 2 bitwise on the GPU
+    and phase 3 stays exactly zero."""
+    w3 = I.random_state((30, 270), nphase=3, seed=41, absent=(2,), lowp=0.0,
+                        opts=I.Options(flux=1, cfl=0.2))
+    keep = [0, 1, 3, 4, 5, 6, 7]
+    w2 = w3.copy()
+    w2.gamma, w2.pinf, w2.D, w2.pmin, w2.cT = (x[:2] for x in
+                                               (w3.gamma, w3.pinf, w3.D, w3.pmin, w3.cT))
+    w2.U = w3.U[keep].copy()
+    s3, s2 = _solver(w3), _solver(w2)
+    for _ in range(3):
+        s3.step()
+        s2.step()
+    a, b = s3.host(0), s2.host(0)
+    assert (a[2] == 0).all() and (a[-1] == 0).all()
+    assert np.array_equal(a[keep], b)
+    s3.close(); s2.close()
+
+
+def test_determinism_and_graph_replay():
+    import torch
+    w = I.random_state((50, 300), nphase=2, seed=51, lowp=0.0, opts=I.Options(flux=1, cfl=0.2))
+    st = torch.cuda.Stream()
+    a = _solver(w, stream=st)
+    b = _solver(w, stream=st, use_graph=True)
+    for k in range(4):
+        a.step()
+        b.step()
+        # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(a.host(0), b.host(0)), k
+    c = _solver(w, stream=st)
+    for _ in range(4):
+        c.step()
+    assert np.array_equal(a.host(0), c.host(0))
+    for s in (a, b, c):
+        s.close()
+
+
+def test_check_bounds_restores_state():
+    """An inadmissible input (negative volume fraction) is reported and the
+    state is restored (failure handling forced from the host)."""
+    from paper_2608_00746_amd.binding import MpWenoError, ERR_INADMISSIBLE, ERR_NONFINITE
+    w = I.random_state((20, 64), nphase=2, seed=61, lowp=0.0, opts=I.Options(flux=1, cfl=0.2))
+    w.U[-1, 0, 5, 5] = -0.5
+    w.U[-2, 0, 5, 5] = 1.5
+    s = _solver(w, check_bounds=True)
+    before = s.host(0).copy()
+    with pytest.raises(MpWenoError) as ei:
+        s.step()
+    assert ei.value.status in (ERR_INADMISSIBLE, ERR_NONFINITE)
+    assert np.array_equal(s.host(0), before)
+    assert s.diag()[0][27] == 0
+    s.close()
+
+
+def test_invalid_arguments():
+    from paper_2608_00746_amd.binding import MpWenoError, ERR_ARG, ERR_UNSUPPORTED
+    w = I.random_state((16,), nphase=2, seed=1)
+    w.gamma = np.array([1.0, 6.12])
+    with pytest.raises(MpWenoError) as ei:
+        _solver(w)
+    assert ei.value.status == ERR_ARG
+    w = I.random_state((16,), nphase=2, seed=1)
+    o = I.Options(phase_field=1)
+    with pytest.raises(MpWenoError) as ei:
+        _solver(w, opts=o)
+    assert ei.value.status == ERR_UNSUPPORTED
