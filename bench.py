@@ -1,0 +1,169 @@
+"""Throughput of the WENO-C hyperbolic step on one MI355X.
+
+A step is one full third-order SSP Runge-Kutta step (CFL time step on the
+device, three RK stages) of every instance.  Default workload: the 2D
+two-phase advection problem, 512 x 512 periodic, air bubble in water (SI),
+FP64, WENO-C + HLLC, CFL 0.5.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME]
+                  [--precision fp64|mixed] [--cpu-seconds S]
+
+Inputs are synthetic and seeded (paper_2608_00746_amd.inputs) and resident in
+HBM before the timed region.  The roofline entry reports the stage kernel:
+algorithmic bytes per launch (8 n_U bytes per cell read of the stage state,
+8 n_U per cell read of the step-start state in stages 2 and 3, 8 n_U per cell
+written) over its average launch time, measured with HIP events recorded on
+the kernel's stream over the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name, precision):
+    from paper_2608_00746_amd import inputs as I
+    prec = I.PREC_MIXED if precision == "mixed" else I.PREC_FP64
+    if name == "advection_2d_512":
+        ws = [I.advection_2d(512)]
+    elif name == "shock_bubble_2048x1024":
+        ws = [I.shock_bubble_2d(2048, 1024)]
+    elif name == "shock_interface_n3_1024":
+        ws = [I.shock_interface_n3(1024)]
+    elif name == "advection_1d_200":
+        ws = [I.advection_1d(200)]
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    for w in ws:
+        w.opts.precision = prec
+    return ws
+
+
+def cpu_baseline(ws, seconds):
+    """The oracle as it stands, on the host cores, on a bounded sample: the
+    first instance, whole steps until `seconds` have elapsed."""
+    from oracle import mpo
+    w = ws[0]
+    o = w.opts
+    pb = mpo.Problem(w.ndim, w.n, w.dx, w.bc, list(w.gamma), list(w.pinf), list(w.D),
+                     list(w.pmin), list(w.cT), recon=o.recon, flux=o.flux, model=o.model,
+                     energy_limiter=o.energy_limiter, cfl=o.cfl, t_end=0.0)
+    U = w.U.reshape(-1).copy()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        U = pb.step(U, pb.dt(U, 0.0))
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": steps * w.ncells / el, "unit": "cell-updates/s",
+            "cores": mpo.num_threads(), "kind": "oracle",
+            "sample": f"{steps} full RK3 steps of {w.name} ({w.ncells} cells), "
+                      f"{el:.1f} s, OpenMP over grid lines"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="advection_2d_512")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see the design notes on sharding)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2608_00746_amd.binding import Solver
+
+    ws = workload(args.workload, args.precision)
+    stream = torch.cuda.Stream()
+    s = Solver(ws, stream=stream, use_graph=not args.no_graph)
+    cells = sum(w.ncells for w in ws)
+
+    for _ in range(args.warmup):
+        s.step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps bracketed by synchronisation; the stage
+    # kernel of every RK stage is bracketed by HIP events on its stream
+    s.profile(3)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        s.step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    k_ms, k_n = s.timing(reset=True)
+    s.profile(0)
+
+    # sanity: the state stayed finite and admissible
+    d = s.diag()
+    if (d[:, 25] > 0).any():
+        raise SystemExit("non-finite state after the timed steps")
+
+    ms_step = ms / args.steps
+    value = cells * args.steps / (ms / 1e3)
+    nU = ws[0].nU
+    bytes_launch = sum(8 * w.nU * w.ncells for w in ws) * (2 + 3 + 3) / 3.0
+    avg_launch_s = (k_ms / 1e3) / max(k_n, 1)
+    achieved = bytes_launch / avg_launch_s / 1e9
+    w0 = ws[0]
+    out = {
+        "metric": "cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "grid": list(w0.n), "nphase": w0.N, "instances": len(ws),
+            "precision": args.precision,
+            "recon": ["WENO-C", "WENO-CL"][w0.opts.recon],
+            "flux": ["HLLC", "HLL"][w0.opts.flux],
+            "cfl": w0.opts.cfl, "graph": not args.no_graph,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "RK stage (x sweep + y sweep)",
+            "avg_launch_ms": avg_launch_s * 1e3, "launches": k_n,
+            "bytes_per_launch": bytes_launch,
+        },
+        "wall_s": wall,
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_seconds)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

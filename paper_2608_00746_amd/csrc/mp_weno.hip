@@ -9,10 +9,9 @@
 //               flux of its plus-side face, trades fluxes, and writes the x
 //               part of L(U) to a direction accumulator (1D: finishes the RK
 //               stage directly).
-//   k_sweep_y : one lane per column x marching H rows in y with a five-row
-//               register window (coalesced row loads, no LDS, no barriers);
-//               the face state and flux of the previous row are carried in
-//               registers.  It adds the accumulator and applies the RK stage.
+//   k_sweep_y : the same exchange pattern on 16 x 16 tiles of lanes (one
+//               cell per lane, neighbours in y through LDS, 128-byte row
+//               segments); it adds the accumulator and applies the RK stage.
 // Both sweeps read the same stage state (unsplit, dimension by dimension).
 // The CFL step and the diagnostics are two-pass reductions with a fixed
 // order (no floating-point atomics), so results are deterministic.
@@ -33,8 +32,6 @@ namespace mpw {
 
 constexpr int kMaxN = 5;          // phases built
 constexpr int kBX = 256;          // lanes of the x sweep (254 output cells)
-constexpr int kBY = 64;           // lanes of the y sweep
-constexpr int kHY = 32;           // rows marched by one y-sweep lane
 constexpr int kRedBlock = 256;    // reduction workgroup
 constexpr int kRedMaxBlocks = 1024;
 constexpr int kDiagSlots = 32;    // per-block partials of the diagnostics
@@ -233,61 +230,118 @@ __global__ __launch_bounds__(kBX) void k_sweep_x(const Grid g, const Eos e,
 // ---------------------------------------------------------------------------
 // y sweep (2D) + RK epilogue
 // ---------------------------------------------------------------------------
+// A workgroup is a tile of kTX columns x kTY rows of lanes, one cell per lane
+// (lane (tx, ty) holds cell (x0 + tx, y0 - 1 + ty)); rows y0 .. y0 + kTY - 3
+// are its outputs.  Primitives of rows y0 - 3 .. y0 + kTY go to LDS (each row
+// segment is kTX contiguous doubles per component, one 128-byte line), every
+// lane reconstructs its cell along y from its column, and face states and
+// fluxes are traded with the neighbour row through LDS, as in the x sweep.
+constexpr int kTX = 16;
+constexpr int kTY = 16;
+constexpr int kOY = kTY - 2;      // output rows per tile
+
 template <int N, typename W>
-__global__ __launch_bounds__(kBY) void k_sweep_y(const Grid g, const Eos e,
-                                                 const StageArgs a) {
+__global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Grid g, const Eos e,
+                                                       const StageArgs a) {
   constexpr int D = 2;
-  constexpr int NU = 2 * N + D + 1;
-  const int x = blockIdx.x * kBY + threadIdx.x;
-  const bool active = x < g.nx;
-  const int xc = active ? x : g.nx - 1;
-  const int y0 = blockIdx.y * kHY;
-  const int y1 = min(y0 + kHY, g.ny);
+  constexpr int NV = 2 * N + D + 1;
+  constexpr int NU = NV;
+  constexpr int NF = 2 * N + 2 * D + 4;
+  constexpr int NFL = NU + 1;
+  __shared__ double sprim[NV][kTY + 4][kTX];
+  __shared__ double sface[NF][kTY][kTX];
+  __shared__ double sflux[NFL][kTY][kTX];
+
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int x = blockIdx.x * kTX + tx;
+  const bool colok = x < g.nx;
+  const int xc = colok ? x : g.nx - 1;
+  const int y0 = blockIdx.y * kOY;
+  const int yi = y0 - 1 + ty;
   const int64_t nc = g.nc;
 
-  auto load_row = [&](int y, Prim<N, D>& v) {
+  auto put_prim = [&](int y, int slot) {
     const int ym = bc_map(y, g.ny, g.bcy0, g.bcy1);
     Cons<N, D> c;
     load_cons<N, D>(a.Uk, nc, (int64_t)ym * g.nx + xc, c);
+    Prim<N, D> v;
     cons_to_prim<N, D>(c, e, v);
+#pragma unroll
+    for (int p = 0; p < N; ++p) { sprim[p][slot][tx] = v.m[p]; sprim[N + p][slot][tx] = v.a[p]; }
+#pragma unroll
+    for (int k = 0; k < D; ++k) sprim[2 * N + k][slot][tx] = v.u[k];
+    sprim[2 * N + D][slot][tx] = v.P;
   };
 
-  Prim<N, D> win[5];
+  const int ym = bc_map(yi, g.ny, g.bcy0, g.bcy1);
+  Cons<N, D> ub;
+  load_cons<N, D>(a.Uk, nc, (int64_t)ym * g.nx + xc, ub);
+  {
+    Prim<N, D> v;
+    cons_to_prim<N, D>(ub, e, v);
 #pragma unroll
-  for (int j = 0; j < 5; ++j) load_row(y0 - 3 + j, win[j]);
+    for (int p = 0; p < N; ++p) { sprim[p][ty + 2][tx] = v.m[p]; sprim[N + p][ty + 2][tx] = v.a[p]; }
+#pragma unroll
+    for (int k = 0; k < D; ++k) sprim[2 * N + k][ty + 2][tx] = v.u[k];
+    sprim[2 * N + D][ty + 2][tx] = v.P;
+  }
+  if (ty < 2) put_prim(y0 - 3 + ty, ty);
+  if (ty >= kTY - 2) put_prim(yi + 2, ty + 4);
+  __syncthreads();
 
-  Face<N, D> carry;
-  Flux<N, D> Fprev;
-  Cons<N, D> ubprev;
-  for (int j = y0 - 1; j <= y1; ++j) {
-    Cons<N, D> ub;
-    const int jm = bc_map(j, g.ny, g.bcy0, g.bcy1);
-    load_cons<N, D>(a.Uk, nc, (int64_t)jm * g.nx + xc, ub);
-    Face<N, D> fm, fp;
-    reconstruct<N, D, W>(win, ub, e, g, g.hdy, fm, fp);
-    if (j > y0 - 1) {
-      Flux<N, D> F;
-      riemann<N, D>(carry, fm, 1, g.flux, F);
-      if (active && j - 1 >= y0) {
-        const int64_t idx = (int64_t)(j - 1) * g.nx + x;
-        double L[NU];
-        double opk[N];
-        one_plus_k<N, D>(ubprev, e, g.model, opk);
+  Prim<N, D> s[5];
 #pragma unroll
-        for (int c = 0; c < NU; ++c)
-          L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - Fprev.f[c]) * g.rdy;
-        const double du = (F.uh - Fprev.uh) * g.rdy;
+  for (int j = 0; j < 5; ++j) {
 #pragma unroll
-        for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ubprev.a[p] * opk[p] * du;
-        finish_cell<N, D>(a, nc, idx, ubprev, L);
-      }
-      Fprev = F;
-    }
-    carry = fp;
-    ubprev = ub;
+    for (int p = 0; p < N; ++p) { s[j].m[p] = sprim[p][ty + j][tx]; s[j].a[p] = sprim[N + p][ty + j][tx]; }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) win[k] = win[k + 1];
-    load_row(j + 3, win[4]);
+    for (int k = 0; k < D; ++k) s[j].u[k] = sprim[2 * N + k][ty + j][tx];
+    s[j].P = sprim[2 * N + D][ty + j][tx];
+  }
+  Face<N, D> fm, fp;
+  reconstruct<N, D, W>(s, ub, e, g, g.hdy, fm, fp);
+
+#pragma unroll
+  for (int p = 0; p < N; ++p) { sface[p][ty][tx] = fm.m[p]; sface[N + p][ty][tx] = fm.a[p]; }
+#pragma unroll
+  for (int k = 0; k < D; ++k) { sface[2 * N + k][ty][tx] = fm.mom[k]; sface[2 * N + D + k][ty][tx] = fm.u[k]; }
+  sface[2 * N + 2 * D][ty][tx] = fm.E;
+  sface[2 * N + 2 * D + 1][ty][tx] = fm.P;
+  sface[2 * N + 2 * D + 2][ty][tx] = fm.rho;
+  sface[2 * N + 2 * D + 3][ty][tx] = fm.c;
+  __syncthreads();
+
+  Flux<N, D> F;
+  if (ty < kTY - 1) {
+    Face<N, D> R;
+    const int r = ty + 1;
+#pragma unroll
+    for (int p = 0; p < N; ++p) { R.m[p] = sface[p][r][tx]; R.a[p] = sface[N + p][r][tx]; }
+#pragma unroll
+    for (int k = 0; k < D; ++k) { R.mom[k] = sface[2 * N + k][r][tx]; R.u[k] = sface[2 * N + D + k][r][tx]; }
+    R.E = sface[2 * N + 2 * D][r][tx];
+    R.P = sface[2 * N + 2 * D + 1][r][tx];
+    R.rho = sface[2 * N + 2 * D + 2][r][tx];
+    R.c = sface[2 * N + 2 * D + 3][r][tx];
+    riemann<N, D>(fp, R, 1, g.flux, F);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) sflux[c][ty][tx] = F.f[c];
+    sflux[NU][ty][tx] = F.uh;
+  }
+  __syncthreads();
+
+  if (ty >= 1 && ty < kTY - 1 && colok && yi < g.ny) {
+    const int64_t idx = (int64_t)yi * g.nx + x;
+    double L[NU];
+    double opk[N];
+    one_plus_k<N, D>(ub, e, g.model, opk);
+#pragma unroll
+    for (int c = 0; c < NU; ++c)
+      L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
+    const double du = (F.uh - sflux[NU][ty - 1][tx]) * g.rdy;
+#pragma unroll
+    for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
+    finish_cell<N, D>(a, nc, idx, ub, L);
   }
 }
 
@@ -472,9 +526,9 @@ void launch_stage(const Inst& I, const StageArgs& a, hipStream_t s, const Bracke
   hipLaunchKernelGGL((k_sweep_x<N, D, W>), gx, dim3(kBX), 0, s, I.g, I.e, a);
   if (w == 1 || (w == 3 && D == 1)) (void)hipEventRecord(b->ev[1], s);
   if constexpr (D == 2) {
-    dim3 gy((I.g.nx + kBY - 1) / kBY, (I.g.ny + kHY - 1) / kHY);
+    dim3 gy((I.g.nx + kTX - 1) / kTX, (I.g.ny + kOY - 1) / kOY);
     if (w == 2) (void)hipEventRecord(b->ev[0], s);
-    hipLaunchKernelGGL((k_sweep_y<N, W>), gy, dim3(kBY), 0, s, I.g, I.e, a);
+    hipLaunchKernelGGL((k_sweep_y<N, W>), gy, dim3(kTX * kTY), 0, s, I.g, I.e, a);
     if (w == 2 || w == 3) (void)hipEventRecord(b->ev[1], s);
   }
 }

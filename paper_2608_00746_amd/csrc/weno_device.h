@@ -200,15 +200,32 @@ __device__ __forceinline__ void increments(const Diff& d, double l[3],
 // definition: a zero b_k with b_s > 0 gives w_s = 0, and stencils with
 // b = 0 share the weight in the ratio of their d (IS^(s,k) = 1).
 template <typename W>
-__device__ __forceinline__ void wenow_weights(const W b[3], W wl[3], W wr[3]) {
-  const W bm = fmax(b[0], fmax(b[1], b[2]));
+__device__ __forceinline__ void wenow_weights(const W bin[3], W wl[3], W wr[3]) {
+  W b[3] = {bin[0], bin[1], bin[2]};
+  W bm = fmax(b[0], fmax(b[1], b[2]));
   if (!(bm > W(0))) {             // every stencil equally smooth
     wl[0] = W(0.1); wl[1] = W(0.6); wl[2] = W(0.3);
     wr[0] = W(0.3); wr[1] = W(0.6); wr[2] = W(0.1);
     return;
   }
+  // a (sub)normal-range maximum would overflow 1/bm: rescale the set by an
+  // exact power of two first, which leaves every ratio unchanged
+  constexpr bool DBL = sizeof(W) == 8;
+  const W small = DBL ? W(0x1p-900) : W(0x1p-100);
+  if (bm < small) {
+    const W up = DBL ? W(0x1p700) : W(0x1p80);
+    b[0] *= up; b[1] *= up; b[2] *= up; bm *= up;
+  }
   const W r = W(1) / bm;
+  // Scaled indicators below tau join the zero set: this keeps every product
+  // below (and the reciprocal of their sum) inside the normal range; the
+  // face value moves by at most the spread of those candidates, which is
+  // O(tau) relative to the stencil's variation.
+  const W tau = DBL ? W(1e-70) : W(1e-8);
   W s0 = b[0] * r, s1 = b[1] * r, s2 = b[2] * r;
+  s0 = s0 < tau ? W(0) : s0;
+  s1 = s1 < tau ? W(0) : s1;
+  s2 = s2 < tau ? W(0) : s2;
   s0 *= s0; s1 *= s1; s2 *= s2;
   const W p0 = s1 * s2, p1 = s0 * s2, p2 = s0 * s1;
   const W l0 = W(0.1) * p0, l1 = W(0.6) * p1, l2 = W(0.3) * p2;

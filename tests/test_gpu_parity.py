@@ -269,3 +269,17 @@ def test_invalid_arguments():
     with pytest.raises(MpWenoError) as ei:
         _solver(w, opts=o)
     assert ei.value.status == ERR_UNSUPPORTED
+
+
+def test_shock_bubble_stays_finite():
+    """Regression: indicator sets whose largest value is subnormal, or whose
+    scaled squares underflow, once overflowed the single reciprocal of the
+    weight sum (NaN face velocities after ~11 steps of this problem)."""
+    w = _fp64(I.shock_bubble_2d(512, 256))
+    s = _solver(w)
+    for k in range(40):
+        s.step()
+    d = s.diag()[0]
+    assert d[25] == 0 and np.isfinite(d[:w.nU]).all()
+    assert d[21] >= 0 and d[22] >= 0 and d[23] <= 1 + 1e-12 and d[24] > 0
+    s.close()
