@@ -126,9 +126,13 @@ __global__ __launch_bounds__(kBX) void k_sweep_x(const Grid g, const Eos e,
   constexpr int NU = NV;
   constexpr int NF = 2 * N + 2 * D + 4;
   constexpr int NFL = NU + 1;
-  __shared__ double sprim[NV][kBX + 4];
+  // the flux rows reuse the primitive rows: the stencil is in registers and
+  // a barrier (after the face exchange) separates the two uses
+  constexpr int NPRIM = NV * (kBX + 4), NFLX = NFL * kBX;
+  __shared__ double sraw[NPRIM > NFLX ? NPRIM : NFLX];
   __shared__ double sface[NF][kBX];
-  __shared__ double sflux[NFL][kBX];
+  double (*sprim)[kBX + 4] = reinterpret_cast<double (*)[kBX + 4]>(sraw);
+  double (*sflux)[kBX] = reinterpret_cast<double (*)[kBX]>(sraw);
 
   const int l = threadIdx.x;
   const int y = blockIdx.y;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(kBX) void k_sweep_x(const Grid g, const Eos e,
     R.P = sface[2 * N + 2 * D + 1][r];
     R.rho = sface[2 * N + 2 * D + 2][r];
     R.c = sface[2 * N + 2 * D + 3][r];
-    riemann<N, D>(fp, R, 0, g.flux, F);
+    riemann<N, D, W>(fp, R, 0, g.flux, F);
 #pragma unroll
     for (int c = 0; c < NU; ++c) sflux[c][l] = F.f[c];
     sflux[NU][l] = F.uh;
@@ -248,9 +252,11 @@ __global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Grid g, const Eos e
   constexpr int NU = NV;
   constexpr int NF = 2 * N + 2 * D + 4;
   constexpr int NFL = NU + 1;
-  __shared__ double sprim[NV][kTY + 4][kTX];
+  constexpr int NPRIM = NV * (kTY + 4) * kTX, NFLX = NFL * kTY * kTX;
+  __shared__ double sraw[NPRIM > NFLX ? NPRIM : NFLX];
   __shared__ double sface[NF][kTY][kTX];
-  __shared__ double sflux[NFL][kTY][kTX];
+  double (*sprim)[kTY + 4][kTX] = reinterpret_cast<double (*)[kTY + 4][kTX]>(sraw);
+  double (*sflux)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(sraw);
 
   const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
   const int x = blockIdx.x * kTX + tx;
@@ -323,7 +329,7 @@ __global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Grid g, const Eos e
     R.P = sface[2 * N + 2 * D + 1][r][tx];
     R.rho = sface[2 * N + 2 * D + 2][r][tx];
     R.c = sface[2 * N + 2 * D + 3][r][tx];
-    riemann<N, D>(fp, R, 1, g.flux, F);
+    riemann<N, D, W>(fp, R, 1, g.flux, F);
 #pragma unroll
     for (int c = 0; c < NU; ++c) sflux[c][ty][tx] = F.f[c];
     sflux[NU][ty][tx] = F.uh;

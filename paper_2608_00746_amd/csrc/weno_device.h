@@ -148,6 +148,11 @@ __device__ __forceinline__ double psi(const double* m, const double* a,
   return E - ke - emin;
 }
 
+// Reciprocal: IEEE division in FP64; the hardware reciprocal (1 ulp) in FP32,
+// where only the nonlinear weights and wave-speed coefficients use it.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // -------------------------------------------------------------------------
 // WENO5 with the relative-smoothness weights (Sec. 3.1, 3.3)
 // -------------------------------------------------------------------------
@@ -216,7 +221,7 @@ __device__ __forceinline__ void wenow_weights(const W bin[3], W wl[3], W wr[3]) 
     const W up = DBL ? W(0x1p700) : W(0x1p80);
     b[0] *= up; b[1] *= up; b[2] *= up; bm *= up;
   }
-  const W r = W(1) / bm;
+  const W r = rcp(bm);
   // Scaled indicators below tau join the zero set: this keeps every product
   // below (and the reciprocal of their sum) inside the normal range; the
   // face value moves by at most the spread of those candidates, which is
@@ -232,7 +237,7 @@ __device__ __forceinline__ void wenow_weights(const W bin[3], W wl[3], W wr[3]) 
   const W r0 = W(0.3) * p0, r1 = W(0.6) * p1, r2 = W(0.1) * p2;
   const W dl = l0 + l1 + l2, dr = r0 + r1 + r2;
   if (dl > W(0)) {
-    const W il = W(1) / dl, ir = W(1) / dr;
+    const W il = rcp(dl), ir = rcp(dr);
     wl[0] = l0 * il; wl[1] = l1 * il; wl[2] = l2 * il;
     wr[0] = r0 * ir; wr[1] = r1 * ir; wr[2] = r2 * ir;
   } else {
@@ -513,11 +518,18 @@ __device__ __forceinline__ void reconstruct(const Prim<N, D> (&s)[5],
     }
   }
 
-  // sound speeds at both faces
+  // sound speeds at both faces (FP32 on the mixed path: they only set the
+  // wave-speed estimates of the flux)
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     Face<N, D>& f = side == 0 ? fp : fm;
-    f.c = sound_speed(mix_rc2<N>(f.a, f.P, e, g.model), f.rho);
+    if constexpr (MIXED) {
+      const float rc2 = float(mix_rc2<N>(f.a, f.P, e, g.model));
+      const float rho = float(f.rho);
+      f.c = (rc2 > 0.f && rho > 0.f) ? double(__builtin_sqrtf(rc2 * rcp(rho))) : 0.0;
+    } else {
+      f.c = sound_speed(mix_rc2<N>(f.a, f.P, e, g.model), f.rho);
+    }
   }
 }
 
@@ -529,13 +541,21 @@ __device__ __forceinline__ void reconstruct(const Prim<N, D> (&s)[5],
 // alpha_p by the same chi_K, so the mass and volume-fraction fluxes are the
 // same linear map of their face values; uhat is the alpha flux with
 // alpha = 1 on both sides.
-template <int N, int D>
+template <int N, int D, typename W = double>
 __device__ __forceinline__ void riemann(const Face<N, D>& L,
                                         const Face<N, D>& R, int dir,
                                         int kind, Flux<N, D>& F) {
+  constexpr bool MIXED = sizeof(W) == 4;
   const double uL = L.u[dir], uR = R.u[dir];
-  const double SL = fmin(uL - L.c, uR - R.c);
-  const double SR = fmax(uL + L.c, uR + R.c);
+  double SL, SR;
+  if constexpr (MIXED) {
+    const float fuL = float(uL), fuR = float(uR), fcL = float(L.c), fcR = float(R.c);
+    SL = double(fminf(fuL - fcL, fuR - fcR));
+    SR = double(fmaxf(fuL + fcL, fuR + fcR));
+  } else {
+    SL = fmin(uL - L.c, uR - R.c);
+    SR = fmax(uL + L.c, uR + R.c);
+  }
   constexpr int NE = N + D;
 
   auto phys = [&](const Face<N, D>& S, double* f) {
@@ -564,8 +584,22 @@ __device__ __forceinline__ void riemann(const Face<N, D>& L,
     double fl[nU<N, D>()], fr[nU<N, D>()];
     phys(L, fl);
     phys(R, fr);
-    const double inv = 1.0 / (SR - SL);
-    const double cl = SR * inv, cr = -SL * inv, clr = SL * SR * inv;
+    double cl, cr, clr;
+    if constexpr (MIXED) {
+      // FP32 coefficients with c_R := 1 - c_L formed in FP64 (exact for an
+      // FP32 c_L in [0, 1]): c_L + c_R = 1 holds exactly at every face, so a
+      // uniform velocity and pressure stay uniform
+      const float fSL = float(SL), fSR = float(SR);
+      const float inv = rcp(fSR - fSL);
+      cl = double(fSR * inv);
+      cr = 1.0 - cl;
+      clr = double(fSL * fSR * inv);
+    } else {
+      const double inv = 1.0 / (SR - SL);
+      cl = SR * inv;
+      cr = -SL * inv;
+      clr = SL * SR * inv;
+    }
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       F.f[p] = cl * fl[p] + cr * fr[p] + clr * (R.m[p] - L.m[p]);
