@@ -1,25 +1,33 @@
 // mp_weno.hip -- kernels, host runtime and C ABI of the MI355X WENO-C / WENO-CL
 // hyperbolic step (declared in include/mp_weno.h).
 //
-// One RK stage of a 2D instance is two launches:
-//   k_sweep_x : one workgroup per (row, 254-cell strip).  Each lane converts
-//               one cell to primitives into an LDS row, reconstructs its cell
-//               along x from the five LDS neighbours, trades its minus-side
-//               face state with the left neighbour through LDS, computes the
-//               flux of its plus-side face, trades fluxes, and writes the x
-//               part of L(U) to a direction accumulator (1D: finishes the RK
-//               stage directly).
+// Instances with the same (N, d) form a group.  Each group has a device table
+// of instance descriptors (grid, EOS, buffer pointers), and every kernel
+// launch covers all tiles of all instances of the group: a workgroup finds its
+// instance by binary search over per-instance tile offsets, so a batch of
+// uneven instances is one launch per sweep.  One RK stage of a 2D group is two
+// launches:
+//   k_sweep_x : one workgroup per (instance, row, 254-cell strip).  Each lane
+//               converts one cell to primitives into an LDS row, reconstructs
+//               its cell along x from the five LDS neighbours, trades its
+//               minus-side face state with the left neighbour through LDS,
+//               computes the flux of its plus-side face, trades fluxes, and
+//               writes the x part of L(U) to a direction accumulator (1D:
+//               finishes the RK stage directly).
 //   k_sweep_y : the same exchange pattern on 16 x 16 tiles of lanes (one
 //               cell per lane, neighbours in y through LDS, 128-byte row
 //               segments); it adds the accumulator and applies the RK stage.
 // Both sweeps read the same stage state (unsplit, dimension by dimension).
-// The CFL step and the diagnostics are two-pass reductions with a fixed
-// order (no floating-point atomics), so results are deterministic.
+// Workgroup indices can be remapped so that consecutive tiles (which share
+// halo rows) run on the same XCD and its L2.  The CFL step and the
+// diagnostics are per-instance reductions with a fixed order (no
+// floating-point atomics), so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -33,18 +41,72 @@ namespace mpw {
 constexpr int kMaxN = 5;          // phases built
 constexpr int kBX = 256;          // lanes of the x sweep (254 output cells)
 constexpr int kRedBlock = 256;    // reduction workgroup
-constexpr int kRedMaxBlocks = 1024;
 constexpr int kDiagSlots = 32;    // per-block partials of the diagnostics
 
+// The state pointers come from a table in device memory, so the compiler
+// cannot tell their address space and would emit flat loads and stores (which
+// also count against the LDS wait counter).  They always point to global
+// memory; these types say so.
+using gdouble = __attribute__((address_space(1))) double;
+__device__ __forceinline__ const gdouble* gptr(const double* p) { return (const gdouble*)p; }
+__device__ __forceinline__ gdouble* gptr(double* p) { return (gdouble*)p; }
+
 struct StageArgs {
-  const double* Uk;   // stage state (stencils)
-  const double* Un;   // state at the start of the step (RK base)
-  double* out;        // U^(k+1), or L(U) when mode == 0
-  double* acc;        // x part of L (2D)
-  const double* dt;   // device time step of this instance
+  const gdouble* Uk;  // stage state (stencils)
+  const gdouble* Un;  // state at the start of the step (RK base)
+  gdouble* out;       // U^(k+1), or L(U) when mode == 0
+  gdouble* acc;       // x part of L (2D)
+  const gdouble* dt;  // device time step of this instance
   double a, b;        // out = a Un + b (Uk + dt L)
   int mode;           // 0: write L, 1: RK stage
 };
+
+// One instance as the kernels see it (device memory, read with scalar loads).
+struct Desc {
+  Grid g;
+  Eos e;
+  double* U;                 // caller state U^n (updated in place)
+  double* U1;                // RK stage buffers
+  double* U2;
+  double* acc;               // x part of L (2D)
+  const double* rin;         // mp_weno_rhs input / output
+  double* rout;
+  double* dt;                // this instance's time step, time, step count
+  double* t;
+  double* steps;
+  double* diag;              // MP_DIAG_LEN results
+  double t_end, vol;
+};
+
+// RK stage s of Shu and Osher's third-order scheme (s = 0, 1, 2), or the
+// plain operator L(U) (s = 3).
+__device__ __forceinline__ StageArgs stage_args(const Desc& d, int s) {
+  StageArgs a;
+  a.acc = gptr(d.acc);
+  a.dt = gptr(d.dt);
+  a.Un = gptr(d.U);
+  a.mode = 1;
+  if (s == 0) { a.Uk = gptr(d.U); a.out = gptr(d.U1); a.a = 0.0; a.b = 1.0; }
+  else if (s == 1) { a.Uk = gptr(d.U1); a.out = gptr(d.U2); a.a = 0.75; a.b = 0.25; }
+  else if (s == 2) { a.Uk = gptr(d.U2); a.out = gptr(d.U); a.a = 1.0 / 3.0; a.b = 2.0 / 3.0; }
+  else { a.Uk = gptr(d.rin); a.out = gptr(d.rout); a.a = 0.0; a.b = 0.0; a.mode = 0; }
+  return a;
+}
+
+// (instance, tile within the instance) of work item `item`: one load from
+// the group's tile map, none for a group of one instance
+__device__ __forceinline__ int2 locate(const int2* __restrict__ map, int n, int item) {
+  return n == 1 ? make_int2(0, item) : map[item];
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; with swz set,
+// logical tile j runs on XCD floor(j / (G/8)) so that neighbouring tiles
+// share an L2.  A bijection of [0, G) for any G.
+__device__ __forceinline__ int xcd_item(int b, int G, int swz) {
+  if (!swz) return b;
+  const int x = b & 7, slot = b >> 3, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + slot;
+}
 
 __device__ __forceinline__ int bc_map(int i, int n, int lo, int hi) {
   if (i < 0) return lo == MP_BC_PERIODIC ? ((i % n) + n) % n : 0;
@@ -53,7 +115,7 @@ __device__ __forceinline__ int bc_map(int i, int n, int lo, int hi) {
 }
 
 template <int N, int D>
-__device__ __forceinline__ void load_cons(const double* __restrict__ U,
+__device__ __forceinline__ void load_cons(const gdouble* __restrict__ U,
                                           int64_t nc, int64_t idx,
                                           Cons<N, D>& c) {
 #pragma unroll
@@ -120,8 +182,17 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
 // x sweep
 // ---------------------------------------------------------------------------
 template <int N, int D, typename W>
-__global__ __launch_bounds__(kBX) void k_sweep_x(const Grid g, const Eos e,
-                                                 const StageArgs a) {
+__global__ __launch_bounds__(kBX) void k_sweep_x(const Desc* __restrict__ descs,
+                                                 const int2* __restrict__ map,
+                                                 int ninst, int stage, int swz) {
+  const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));
+  const Desc d = descs[it.x];   // by value: loaded once, kept in registers
+  const Grid& g = d.g;
+  const Eos& e = d.e;
+  const StageArgs a = stage_args(d, stage);
+  const int ns = (g.nx + kBX - 3) / (kBX - 2);
+  const int local = it.y;
+  const int y = local / ns;
   constexpr int NV = 2 * N + D + 1;
   constexpr int NU = NV;
   constexpr int NF = 2 * N + 2 * D + 4;
@@ -135,8 +206,7 @@ __global__ __launch_bounds__(kBX) void k_sweep_x(const Grid g, const Eos e,
   double (*sflux)[kBX] = reinterpret_cast<double (*)[kBX]>(sraw);
 
   const int l = threadIdx.x;
-  const int y = blockIdx.y;
-  const int x0 = blockIdx.x * (kBX - 2);
+  const int x0 = (local - y * ns) * (kBX - 2);
   const int xi = x0 - 1 + l;
   const int64_t row = (int64_t)y * g.nx;
   const int64_t nc = g.nc;
@@ -245,8 +315,17 @@ constexpr int kTY = 16;
 constexpr int kOY = kTY - 2;      // output rows per tile
 
 template <int N, typename W>
-__global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Grid g, const Eos e,
-                                                       const StageArgs a) {
+__global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Desc* __restrict__ descs,
+                                                       const int2* __restrict__ map,
+                                                       int ninst, int stage, int swz) {
+  const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));
+  const Desc d = descs[it.x];
+  const Grid& g = d.g;
+  const Eos& e = d.e;
+  const StageArgs a = stage_args(d, stage);
+  const int ntx = (g.nx + kTX - 1) / kTX;
+  const int local = it.y;
+  const int tyb = local / ntx, txb = local - tyb * ntx;
   constexpr int D = 2;
   constexpr int NV = 2 * N + D + 1;
   constexpr int NU = NV;
@@ -259,10 +338,10 @@ __global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Grid g, const Eos e
   double (*sflux)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(sraw);
 
   const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-  const int x = blockIdx.x * kTX + tx;
+  const int x = txb * kTX + tx;
   const bool colok = x < g.nx;
   const int xc = colok ? x : g.nx - 1;
-  const int y0 = blockIdx.y * kOY;
+  const int y0 = tyb * kOY;
   const int yi = y0 - 1 + ty;
   const int64_t nc = g.nc;
 
@@ -374,17 +453,24 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return r;
 }
 
-// per-block max over cells of sum_d (|u_d| + c)/dx_d
+constexpr int kRedChunk = kRedBlock * 4;    // cells per reduction workgroup
+
+// per-workgroup max over its chunk of cells of sum_d (|u_d| + c)/dx_d
 template <int N, int D>
-__global__ __launch_bounds__(kRedBlock) void k_dt(const Grid g, const Eos e,
-                                                  const double* __restrict__ U,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(kRedBlock) void k_dt(const Desc* __restrict__ descs,
+                                                  const int2* __restrict__ map,
+                                                  int ninst, double* __restrict__ part) {
   __shared__ double sh[kRedBlock / 64];
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const Grid& g = d.g;
+  const Eos& e = d.e;
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < g.nc ? c0 + kRedChunk : g.nc;
   double smax = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nc;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     Cons<N, D> c;
-    load_cons<N, D>(U, g.nc, i, c);
+    load_cons<N, D>(gptr(d.U), g.nc, i, c);
     Prim<N, D> v;
     cons_to_prim<N, D>(c, e, v);
     double rho = 0.0;
@@ -399,44 +485,54 @@ __global__ __launch_bounds__(kRedBlock) void k_dt(const Grid g, const Eos e,
   if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
-// dt = cfl / max, clipped to t_end - t
+// one workgroup per instance: dt = cfl / max, clipped to t_end - t
 __global__ __launch_bounds__(kRedBlock) void k_dt_finish(
-    const double* __restrict__ part, int np, double cfl, double t_end,
-    const double* __restrict__ t, double* __restrict__ dt) {
+    const Desc* __restrict__ descs, const int* __restrict__ start,
+    const double* __restrict__ part, double cfl) {
   __shared__ double sh[kRedBlock / 64];
+  const Desc& d = descs[blockIdx.x];
   double m = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) m = fmax(m, part[i]);
+  for (int i = start[blockIdx.x] + threadIdx.x; i < start[blockIdx.x + 1]; i += kRedBlock)
+    m = fmax(m, part[i]);
   const double r = block_max(m, sh);
   if (threadIdx.x == 0) {
-    double d = cfl / r;
-    if (t_end > 0.0 && *t + d > t_end) d = t_end - *t;
-    *dt = d;
+    const double t = *gptr(d.t);
+    double dt = cfl / r;
+    if (d.t_end > 0.0 && t + dt > d.t_end) dt = d.t_end - t;
+    *gptr(d.dt) = dt;
   }
 }
 
-__global__ void k_advance_time(double* t, double* steps, const double* dt) {
-  if (threadIdx.x == 0) {
-    *t = *t + *dt;
-    *steps = *steps + 1.0;
+__global__ void k_advance_time(double* t, double* steps, const double* dt, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    t[i] = t[i] + dt[i];
+    steps[i] = steps[i] + 1.0;
   }
 }
 
-// per-block diagnostics: slots 0..nU-1 sums, then
+// per-workgroup diagnostics: slots 0..nU-1 sums, then
 // [20] max|sum a - 1|, [21] min m, [22] min a, [23] max a, [24] min psi,
 // [25] non-finite count, [28] max |rho E|
 template <int N, int D>
-__global__ __launch_bounds__(kRedBlock) void k_diag(const Grid g, const Eos e,
-                                                    const double* __restrict__ U,
-                                                    double* __restrict__ part) {
+__global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ descs,
+                                                    const int2* __restrict__ map,
+                                                    int ninst, double* __restrict__ part) {
   constexpr int NU = 2 * N + D + 1;
   __shared__ double sh[kRedBlock];
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const Grid& g = d.g;
+  const Eos& e = d.e;
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < g.nc ? c0 + kRedChunk : g.nc;
+  const gdouble* U = gptr(d.U);
   double acc[kDiagSlots];
 #pragma unroll
   for (int k = 0; k < kDiagSlots; ++k) acc[k] = 0.0;
   acc[21] = acc[22] = acc[24] = INFINITY;
   acc[23] = -INFINITY;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nc;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     double u[NU];
     double nonfin = 0.0;
 #pragma unroll
@@ -478,25 +574,28 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Grid g, const Eos e,
     __syncthreads();
   }
 }
-__global__ void k_diag_finish(const double* __restrict__ part, int np,
-                              int nU, double vol, const double* t,
-                              const double* steps, double* __restrict__ out) {
+
+// one workgroup of kDiagSlots lanes per instance, lane k reduces slot k in
+// block order
+__global__ void k_diag_finish(const Desc* __restrict__ descs, const int* __restrict__ start,
+                              const double* __restrict__ part) {
   const int k = threadIdx.x;
+  const Desc& d = descs[blockIdx.x];
   if (k >= kDiagSlots) return;
   double r;
   if (k == 21 || k == 22 || k == 24) r = INFINITY;
   else if (k == 23) r = -INFINITY;
   else r = 0.0;
-  for (int b = 0; b < np; ++b) {
+  for (int b = start[blockIdx.x]; b < start[blockIdx.x + 1]; ++b) {
     const double x = part[(int64_t)b * kDiagSlots + k];
     if (k == 21 || k == 22 || k == 24) r = fmin(r, x);
     else if (k == 20 || k == 23 || k == 28) r = fmax(r, x);
     else r = r + x;
   }
-  if (k < nU) r *= vol;
-  if (k == 26) r = *t;
-  if (k == 27) r = *steps;
-  out[k] = r;
+  if (k < 20) r *= d.vol;
+  if (k == 26) r = *gptr(d.t);
+  if (k == 27) r = *gptr(d.steps);
+  gptr(d.diag)[k] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -504,63 +603,80 @@ __global__ void k_diag_finish(const double* __restrict__ part, int np,
 // ---------------------------------------------------------------------------
 struct Inst {
   mp_weno_instance in;
-  Grid g;
-  Eos e;
   int N, D, nU;
   int64_t nc;
   double* U1 = nullptr;
   double* U2 = nullptr;
   double* acc = nullptr;
   double* backup = nullptr;
-  int nred = 1;          // reduction blocks
 };
 
-// Optional event pair recorded around one of the stage kernels (profiling).
+// Instances of one (N, d): device descriptor table and tile offsets.
+struct Group {
+  int N = 0, D = 0;
+  std::vector<int> ids;            // context instance indices
+  std::vector<Desc> hdesc;         // host copy of the descriptors
+  std::vector<int> xs, ys, rs;     // tile / reduction-chunk offsets (n + 1)
+  Desc* desc = nullptr;
+  int2* xmap = nullptr;            // work item -> (instance, local tile)
+  int2* ymap = nullptr;
+  int2* rmap = nullptr;
+  int* rstart = nullptr;           // reduction-chunk offsets on the device
+  size_t part_off = 0;             // this group's reduction partials
+};
+
+// Optional event pair recorded around one stage (profiling).
 struct Bracket {
-  int which = 0;                  // 0 none, 1 x sweep, 2 y sweep, 3 whole stage
+  int which = 0;                   // 0 none, 1 x sweep, 2 y sweep, 3 whole stage
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
-using StageFn = void (*)(const Inst&, const StageArgs&, hipStream_t, const Bracket*);
-using RedFn = void (*)(const Inst&, const double*, double*, hipStream_t);
+using StageFn = void (*)(const Group&, int stage, int swz, hipStream_t);
+using RedFn = void (*)(const Group&, double* part, hipStream_t);
 
 template <int N, int D, typename W>
-void launch_stage(const Inst& I, const StageArgs& a, hipStream_t s, const Bracket* b) {
-  const int w = b ? b->which : 0;
-  dim3 gx((I.g.nx + kBX - 3) / (kBX - 2), D == 1 ? 1 : I.g.ny);
-  if (w == 1 || w == 3) (void)hipEventRecord(b->ev[0], s);
-  hipLaunchKernelGGL((k_sweep_x<N, D, W>), gx, dim3(kBX), 0, s, I.g, I.e, a);
-  if (w == 1 || (w == 3 && D == 1)) (void)hipEventRecord(b->ev[1], s);
-  if constexpr (D == 2) {
-    dim3 gy((I.g.nx + kTX - 1) / kTX, (I.g.ny + kOY - 1) / kOY);
-    if (w == 2) (void)hipEventRecord(b->ev[0], s);
-    hipLaunchKernelGGL((k_sweep_y<N, W>), gy, dim3(kTX * kTY), 0, s, I.g, I.e, a);
-    if (w == 2 || w == 3) (void)hipEventRecord(b->ev[1], s);
-  }
+void launch_x(const Group& G, int stage, int swz, hipStream_t s) {
+  const int n = (int)G.ids.size();
+  hipLaunchKernelGGL((k_sweep_x<N, D, W>), dim3(G.xs[n]), dim3(kBX), 0, s, G.desc,
+                     G.xmap, n, stage, swz);
+}
+
+template <int N, typename W>
+void launch_y(const Group& G, int stage, int swz, hipStream_t s) {
+  const int n = (int)G.ids.size();
+  hipLaunchKernelGGL((k_sweep_y<N, W>), dim3(G.ys[n]), dim3(kTX * kTY), 0, s, G.desc,
+                     G.ymap, n, stage, swz);
 }
 
 template <int N, int D>
-void launch_dt(const Inst& I, const double* U, double* part, hipStream_t s) {
-  hipLaunchKernelGGL((k_dt<N, D>), dim3(I.nred), dim3(kRedBlock), 0, s, I.g, I.e, U, part);
+void launch_dt(const Group& G, double* part, hipStream_t s) {
+  const int n = (int)G.ids.size();
+  hipLaunchKernelGGL((k_dt<N, D>), dim3(G.rs[n]), dim3(kRedBlock), 0, s, G.desc, G.rmap,
+                     n, part + G.part_off);
 }
 
 template <int N, int D>
-void launch_diag(const Inst& I, const double* U, double* part, hipStream_t s) {
-  hipLaunchKernelGGL((k_diag<N, D>), dim3(I.nred), dim3(kRedBlock), 0, s, I.g, I.e, U, part);
+void launch_diag(const Group& G, double* part, hipStream_t s) {
+  const int n = (int)G.ids.size();
+  hipLaunchKernelGGL((k_diag<N, D>), dim3(G.rs[n]), dim3(kRedBlock), 0, s, G.desc, G.rmap,
+                     n, part + G.part_off * kDiagSlots);
 }
 
 struct Table {
-  StageFn stage[kMaxN + 1][3][2] = {};
+  StageFn sx[kMaxN + 1][3][2] = {};
+  StageFn sy[kMaxN + 1][2] = {};
   RedFn dt[kMaxN + 1][3] = {};
   RedFn diag[kMaxN + 1][3] = {};
 };
 
 template <int N>
 void fill(Table& t) {
-  t.stage[N][1][0] = launch_stage<N, 1, double>;
-  t.stage[N][1][1] = launch_stage<N, 1, float>;
-  t.stage[N][2][0] = launch_stage<N, 2, double>;
-  t.stage[N][2][1] = launch_stage<N, 2, float>;
+  t.sx[N][1][0] = launch_x<N, 1, double>;
+  t.sx[N][1][1] = launch_x<N, 1, float>;
+  t.sx[N][2][0] = launch_x<N, 2, double>;
+  t.sx[N][2][1] = launch_x<N, 2, float>;
+  t.sy[N][0] = launch_y<N, double>;
+  t.sy[N][1] = launch_y<N, float>;
   t.dt[N][1] = launch_dt<N, 1>;
   t.dt[N][2] = launch_dt<N, 2>;
   t.diag[N][1] = launch_diag<N, 1>;
@@ -582,16 +698,21 @@ using namespace mpw;
 
 struct mp_weno_ctx {
   std::vector<Inst> inst;
+  std::vector<Group> groups;
   mp_weno_opts opt;
   hipStream_t stream = nullptr;
   double* dt = nullptr;       // n_inst
   double* t = nullptr;        // n_inst
   double* steps = nullptr;    // n_inst
-  double* part = nullptr;     // reduction partials
+  double* part = nullptr;     // reduction partials (kDiagSlots per chunk)
   double* diag = nullptr;     // n_inst * MP_DIAG_LEN
+  int swz = -1;               // XCD-aware tile order: 1 on, 0 off, -1 on for
+                              // groups of several instances (measured: it
+                              // keeps each small instance on one L2 and costs
+                              // a few percent on a single grid)
   hipGraphExec_t graph[2] = {nullptr, nullptr};   // [external dt?]
   std::string err;
-  int profile = 0;                           // Bracket::which
+  int profile = 0;            // Bracket::which
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t ev_used = 0;
 
@@ -623,54 +744,54 @@ static mp_status fail(mp_weno_ctx* c, mp_status s, const std::string& msg) {
                                          hipGetErrorString(e_));              \
   } while (0)
 
+// one RK stage (s = 0, 1, 2) or L(U) (s = 3) of every group
+static mp_status enqueue_stage(mp_weno_ctx* c, int s) {
+  const Table& T = table();
+  const int prec = c->opt.precision;
+  Bracket br;
+  const Bracket* b = s < 3 ? c->next_bracket(br) : nullptr;
+  const int w = b ? b->which : 0;
+  if (w == 1 || w == 3) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
+  auto swz = [c](const Group& G) { return c->swz < 0 ? (G.ids.size() > 1 ? 1 : 0) : c->swz; };
+  for (const Group& G : c->groups) T.sx[G.N][G.D][prec](G, s, swz(G), c->stream);
+  if (w == 1) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
+  if (w == 2) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
+  for (const Group& G : c->groups)
+    if (G.D == 2) T.sy[G.N][prec](G, s, swz(G), c->stream);
+  if (w == 2 || w == 3) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
+  HIPCHK(c, hipGetLastError());
+  return MP_OK;
+}
+
 static mp_status enqueue_dt(mp_weno_ctx* c) {
   const Table& T = table();
-  for (size_t i = 0; i < c->inst.size(); ++i) {
-    const Inst& I = c->inst[i];
-    T.dt[I.N][I.D](I, I.in.U, c->part, c->stream);
-    hipLaunchKernelGGL(k_dt_finish, dim3(1), dim3(kRedBlock), 0, c->stream, c->part,
-                       I.nred, c->opt.cfl, I.in.t_end, c->t + i, c->dt + i);
+  for (const Group& G : c->groups) {
+    T.dt[G.N][G.D](G, c->part, c->stream);
+    hipLaunchKernelGGL(k_dt_finish, dim3(G.ids.size()), dim3(kRedBlock), 0, c->stream,
+                       G.desc, G.rstart, c->part + G.part_off, c->opt.cfl);
   }
   HIPCHK(c, hipGetLastError());
   return MP_OK;
 }
 
 static mp_status enqueue_rk(mp_weno_ctx* c) {
-  const Table& T = table();
-  for (size_t i = 0; i < c->inst.size(); ++i) {
-    const Inst& I = c->inst[i];
-    StageFn f = T.stage[I.N][I.D][c->opt.precision];
-    StageArgs a{};
-    a.dt = c->dt + i;
-    a.acc = I.acc;
-    a.mode = 1;
-    a.Un = I.in.U;
-    // U1 = Un + dt L(Un)
-    a.Uk = I.in.U; a.out = I.U1; a.a = 0.0; a.b = 1.0;
-    Bracket br;
-    f(I, a, c->stream, c->next_bracket(br));
-    // U2 = 3/4 Un + 1/4 (U1 + dt L(U1))
-    a.Uk = I.U1; a.out = I.U2; a.a = 0.75; a.b = 0.25;
-    f(I, a, c->stream, c->next_bracket(br));
-    // Un+1 = 1/3 Un + 2/3 (U2 + dt L(U2)), in place (pointwise in Un)
-    a.Uk = I.U2; a.out = I.in.U; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
-    f(I, a, c->stream, c->next_bracket(br));
-    hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, c->stream, c->t + i,
-                       c->steps + i, c->dt + i);
+  for (int s = 0; s < 3; ++s) {
+    mp_status st = enqueue_stage(c, s);
+    if (st != MP_OK) return st;
   }
+  const int n = (int)c->inst.size();
+  hipLaunchKernelGGL(k_advance_time, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->t,
+                     c->steps, c->dt, n);
   HIPCHK(c, hipGetLastError());
   return MP_OK;
 }
 
 static mp_status enqueue_diag(mp_weno_ctx* c) {
   const Table& T = table();
-  for (size_t i = 0; i < c->inst.size(); ++i) {
-    const Inst& I = c->inst[i];
-    T.diag[I.N][I.D](I, I.in.U, c->part, c->stream);
-    double vol = 1.0;
-    for (int d = 0; d < I.D; ++d) vol *= I.in.dx[d];
-    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(64), 0, c->stream, c->part, I.nred,
-                       I.nU, vol, c->t + i, c->steps + i, c->diag + i * MP_DIAG_LEN);
+  for (const Group& G : c->groups) {
+    T.diag[G.N][G.D](G, c->part, c->stream);
+    hipLaunchKernelGGL(k_diag_finish, dim3(G.ids.size()), dim3(64), 0, c->stream, G.desc,
+                       G.rstart, c->part + G.part_off * kDiagSlots);
   }
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -710,22 +831,25 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
   for (auto& I : c->inst) {
     (void)hipFree(I.U1); (void)hipFree(I.U2); (void)hipFree(I.acc); (void)hipFree(I.backup);
   }
-  (void)hipFree(c->dt); (void)hipFree(c->t); (void)hipFree(c->steps); (void)hipFree(c->part); (void)hipFree(c->diag);
+  for (auto& G : c->groups) {
+    (void)hipFree(G.desc); (void)hipFree(G.xmap); (void)hipFree(G.ymap);
+    (void)hipFree(G.rmap); (void)hipFree(G.rstart);
+  }
+  (void)hipFree(c->dt); (void)hipFree(c->t); (void)hipFree(c->steps); (void)hipFree(c->part);
+  (void)hipFree(c->diag);
   delete c;
   return MP_OK;
 }
 
-mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
-                       const mp_weno_instance* inst, const mp_weno_opts* opt,
-                       void* hip_stream) {
-  if (!out) return MP_ERR_ARG;
-  *out = nullptr;
+static mp_status validate(int32_t n_inst, const mp_weno_instance* inst,
+                          const mp_weno_opts* opt, void* hip_stream) {
   if (n_inst < 1 || !inst || !opt) return MP_ERR_ARG;
   if (opt->phase_field != 0) return MP_ERR_UNSUPPORTED;
   if (opt->precision != MP_PREC_FP64 && opt->precision != MP_PREC_MIXED) return MP_ERR_ARG;
   if (opt->recon < 0 || opt->recon > 1 || opt->flux < 0 || opt->flux > 1 ||
       opt->model < 0 || opt->model > 1 || !(opt->cfl > 0.0))
     return MP_ERR_ARG;
+  if (opt->use_graph && !hip_stream) return MP_ERR_ARG;   // no capture on the null stream
   for (int i = 0; i < n_inst; ++i) {
     const mp_weno_instance& s = inst[i];
     if (s.ndim < 1 || s.ndim > 3 || !s.U) return MP_ERR_ARG;
@@ -742,70 +866,156 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           !std::isfinite(s.pmin[p]))
         return MP_ERR_ARG;
     const int64_t nc = (int64_t)s.n[0] * (s.ndim > 1 ? s.n[1] : 1);
-    if (nc > (int64_t)1 << 31) return MP_ERR_UNSUPPORTED;
+    if (nc > ((int64_t)1 << 31) - 1) return MP_ERR_UNSUPPORTED;
   }
+  return MP_OK;
+}
 
-  if (opt->use_graph && !hip_stream) return MP_ERR_ARG;   // no capture on the null stream
+mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
+                       const mp_weno_instance* inst, const mp_weno_opts* opt,
+                       void* hip_stream) {
+  if (!out) return MP_ERR_ARG;
+  *out = nullptr;
+  const mp_status v = validate(n_inst, inst, opt, hip_stream);
+  if (v != MP_OK) return v;
+
   mp_weno_ctx* c = new (std::nothrow) mp_weno_ctx();
   if (!c) return MP_ERR_OOM;
   c->opt = *opt;
   c->stream = (hipStream_t)hip_stream;
-  size_t maxred = 1;
-  for (int i = 0; i < n_inst; ++i) {
-    Inst I;
-    I.in = inst[i];
-    const mp_weno_instance& s = inst[i];
-    I.N = s.nphase;
-    I.D = s.ndim;
-    I.nU = 2 * I.N + I.D + 1;
-    I.nc = (int64_t)s.n[0] * (s.ndim > 1 ? s.n[1] : 1);
-    Grid& g = I.g;
-    g.nx = s.n[0];
-    g.ny = s.ndim > 1 ? s.n[1] : 1;
-    g.nc = I.nc;
-    g.rdx = 1.0 / s.dx[0];
-    g.hdx = 0.5 * s.dx[0];
-    g.rdy = s.ndim > 1 ? 1.0 / s.dx[1] : 0.0;
-    g.hdy = s.ndim > 1 ? 0.5 * s.dx[1] : 1.0;
-    g.bcx0 = s.bc[0][0]; g.bcx1 = s.bc[0][1];
-    g.bcy0 = s.ndim > 1 ? s.bc[1][0] : 0;
-    g.bcy1 = s.ndim > 1 ? s.bc[1][1] : 0;
-    g.recon = opt->recon;
-    g.flux = opt->flux;
-    g.model = opt->model;
-    g.energy = opt->energy_limiter ? 1 : 0;
-    std::memset(&I.e, 0, sizeof(I.e));
-    for (int p = 0; p < I.N; ++p) {
-      const double gm = s.gamma[p], pi = s.pinf[p];
-      I.e.A[p] = 1.0 / (gm - 1.0);
-      I.e.B[p] = gm * pi / (gm - 1.0);
-      I.e.Dp[p] = s.D[p];
-      I.e.gam[p] = gm;
-      I.e.pinf[p] = pi;
-      I.e.EB[p] = I.e.A[p] * s.pmin[p] + I.e.B[p];
-    }
-    I.nred = (int)std::min<int64_t>(kRedMaxBlocks, (I.nc + kRedBlock - 1) / kRedBlock);
-    maxred = std::max<size_t>(maxred, (size_t)I.nred);
-    const size_t bytes = sizeof(double) * (size_t)I.nU * (size_t)I.nc;
-    if (hipMalloc(&I.U1, bytes) != hipSuccess || hipMalloc(&I.U2, bytes) != hipSuccess ||
-        (I.D > 1 && hipMalloc(&I.acc, bytes) != hipSuccess) ||
-        (opt->check_bounds && hipMalloc(&I.backup, bytes) != hipSuccess)) {
-      c->inst.push_back(I);
-      mp_weno_destroy(c);
-      return MP_ERR_OOM;
-    }
-    c->inst.push_back(I);
-  }
+  const char* sw = std::getenv("MPWENO_XCD_SWIZZLE");
+  if (sw) c->swz = std::atoi(sw) ? 1 : 0;
   const size_t n = (size_t)n_inst;
   if (hipMalloc(&c->dt, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&c->t, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&c->steps, sizeof(double) * n) != hipSuccess ||
-      hipMalloc(&c->part, sizeof(double) * maxred * kDiagSlots) != hipSuccess ||
       hipMalloc(&c->diag, sizeof(double) * n * MP_DIAG_LEN) != hipSuccess) {
     mp_weno_destroy(c);
     return MP_ERR_OOM;
   }
-  std::vector<double> zeros(n * MP_DIAG_LEN, 0.0);
+  for (int i = 0; i < n_inst; ++i) {
+    Inst I;
+    I.in = inst[i];
+    I.N = inst[i].nphase;
+    I.D = inst[i].ndim;
+    I.nU = 2 * I.N + I.D + 1;
+    I.nc = (int64_t)inst[i].n[0] * (I.D > 1 ? inst[i].n[1] : 1);
+    const size_t bytes = sizeof(double) * (size_t)I.nU * (size_t)I.nc;
+    const bool ok = hipMalloc(&I.U1, bytes) == hipSuccess &&
+                    hipMalloc(&I.U2, bytes) == hipSuccess &&
+                    (I.D == 1 || hipMalloc(&I.acc, bytes) == hipSuccess) &&
+                    (!opt->check_bounds || hipMalloc(&I.backup, bytes) == hipSuccess);
+    c->inst.push_back(I);
+    if (!ok) {
+      mp_weno_destroy(c);
+      return MP_ERR_OOM;
+    }
+  }
+
+  // group by (N, d); larger instances first inside a group
+  size_t part_total = 0;
+  for (int D = 1; D <= 2; ++D)
+    for (int N = 1; N <= kMaxN; ++N) {
+      Group G;
+      G.N = N;
+      G.D = D;
+      for (int i = 0; i < n_inst; ++i)
+        if (c->inst[i].N == N && c->inst[i].D == D) G.ids.push_back(i);
+      if (G.ids.empty()) continue;
+      std::stable_sort(G.ids.begin(), G.ids.end(), [&](int a, int b) {
+        return c->inst[a].nc > c->inst[b].nc;
+      });
+      G.xs.push_back(0); G.ys.push_back(0); G.rs.push_back(0);
+      for (int id : G.ids) {
+        const Inst& I = c->inst[id];
+        const mp_weno_instance& s = I.in;
+        Desc d;
+        std::memset(&d, 0, sizeof(d));
+        Grid& g = d.g;
+        g.nx = s.n[0];
+        g.ny = I.D > 1 ? s.n[1] : 1;
+        g.nc = I.nc;
+        g.rdx = 1.0 / s.dx[0];
+        g.hdx = 0.5 * s.dx[0];
+        g.rdy = I.D > 1 ? 1.0 / s.dx[1] : 0.0;
+        g.hdy = I.D > 1 ? 0.5 * s.dx[1] : 1.0;
+        g.bcx0 = s.bc[0][0]; g.bcx1 = s.bc[0][1];
+        g.bcy0 = I.D > 1 ? s.bc[1][0] : 0;
+        g.bcy1 = I.D > 1 ? s.bc[1][1] : 0;
+        g.recon = opt->recon;
+        g.flux = opt->flux;
+        g.model = opt->model;
+        g.energy = opt->energy_limiter ? 1 : 0;
+        for (int p = 0; p < I.N; ++p) {
+          const double gm = s.gamma[p], pi = s.pinf[p];
+          d.e.A[p] = 1.0 / (gm - 1.0);
+          d.e.B[p] = gm * pi / (gm - 1.0);
+          d.e.Dp[p] = s.D[p];
+          d.e.gam[p] = gm;
+          d.e.pinf[p] = pi;
+          d.e.EB[p] = d.e.A[p] * s.pmin[p] + d.e.B[p];
+        }
+        d.U = s.U;
+        d.U1 = I.U1;
+        d.U2 = I.U2;
+        d.acc = I.acc;
+        d.dt = c->dt + id;
+        d.t = c->t + id;
+        d.steps = c->steps + id;
+        d.diag = c->diag + (size_t)id * MP_DIAG_LEN;
+        d.t_end = s.t_end;
+        d.vol = 1.0;
+        for (int k = 0; k < I.D; ++k) d.vol *= s.dx[k];
+        G.hdesc.push_back(d);
+        const int64_t nstrip = (g.nx + kBX - 3) / (kBX - 2);
+        const int64_t nty = I.D > 1 ? (int64_t)((g.nx + kTX - 1) / kTX) * ((g.ny + kOY - 1) / kOY) : 0;
+        const int64_t nx = G.xs.back() + g.ny * nstrip;
+        const int64_t ny = G.ys.back() + nty;
+        const int64_t nr = G.rs.back() + (I.nc + kRedChunk - 1) / kRedChunk;
+        if (std::max(nx, std::max(ny, nr)) > (int64_t)INT32_MAX) {
+          mp_weno_destroy(c);
+          return MP_ERR_UNSUPPORTED;     // more tiles than one launch can index
+        }
+        G.xs.push_back((int)nx);
+        G.ys.push_back((int)ny);
+        G.rs.push_back((int)nr);
+      }
+      G.part_off = part_total;
+      part_total += (size_t)G.rs.back();
+      const size_t m = G.ids.size();
+      auto tile_map = [m](const std::vector<int>& st) {
+        std::vector<int2> v((size_t)st[m]);
+        for (size_t k = 0; k < m; ++k)
+          for (int j = st[k]; j < st[k + 1]; ++j) v[(size_t)j] = make_int2((int)k, j - st[k]);
+        return v;
+      };
+      const std::vector<int2> xm = tile_map(G.xs), ym = tile_map(G.ys), rm = tile_map(G.rs);
+      bool ok = hipMalloc(&G.desc, sizeof(Desc) * m) == hipSuccess &&
+                hipMalloc(&G.xmap, sizeof(int2) * std::max<size_t>(xm.size(), 1)) == hipSuccess &&
+                hipMalloc(&G.ymap, sizeof(int2) * std::max<size_t>(ym.size(), 1)) == hipSuccess &&
+                hipMalloc(&G.rmap, sizeof(int2) * std::max<size_t>(rm.size(), 1)) == hipSuccess &&
+                hipMalloc(&G.rstart, sizeof(int) * (m + 1)) == hipSuccess;
+      c->groups.push_back(G);
+      if (!ok) {
+        mp_weno_destroy(c);
+        return MP_ERR_OOM;
+      }
+      Group& H = c->groups.back();
+      if (hipMemcpy(H.desc, H.hdesc.data(), sizeof(Desc) * m, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(H.xmap, xm.data(), sizeof(int2) * xm.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          (!ym.empty() &&
+           hipMemcpy(H.ymap, ym.data(), sizeof(int2) * ym.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+          hipMemcpy(H.rmap, rm.data(), sizeof(int2) * rm.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(H.rstart, H.rs.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        mp_weno_destroy(c);
+        return MP_ERR_HIP;
+      }
+    }
+  if (hipMalloc(&c->part, sizeof(double) * std::max<size_t>(part_total, 1) * kDiagSlots) != hipSuccess) {
+    mp_weno_destroy(c);
+    return MP_ERR_OOM;
+  }
+  std::vector<double> zeros(n, 0.0);
   if (hipMemcpy(c->t, zeros.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->steps, zeros.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->dt, zeros.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) {
@@ -826,20 +1036,20 @@ mp_status mp_weno_set_time(mp_weno_ctx* c, const double* t) {
 
 mp_status mp_weno_rhs(mp_weno_ctx* c, const double* const* U_in, double* const* dUdt) {
   if (!c || !dUdt) return fail(c, MP_ERR_ARG, "null argument");
-  const Table& T = table();
-  for (size_t i = 0; i < c->inst.size(); ++i) {
-    const Inst& I = c->inst[i];
+  for (size_t i = 0; i < c->inst.size(); ++i)
     if (!dUdt[i]) return fail(c, MP_ERR_ARG, "null output pointer");
-    StageArgs a{};
-    a.Uk = (U_in && U_in[i]) ? U_in[i] : I.in.U;
-    a.out = dUdt[i];
-    a.acc = I.acc;
-    a.mode = 0;
-    a.dt = c->dt + i;
-    T.stage[I.N][I.D][c->opt.precision](I, a, c->stream, nullptr);
+  // the descriptor tables carry the input/output pointers of this call
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (Group& G : c->groups) {
+    for (size_t k = 0; k < G.ids.size(); ++k) {
+      const int id = G.ids[k];
+      G.hdesc[k].rin = (U_in && U_in[id]) ? U_in[id] : c->inst[id].in.U;
+      G.hdesc[k].rout = dUdt[id];
+    }
+    HIPCHK(c, hipMemcpy(G.desc, G.hdesc.data(), sizeof(Desc) * G.ids.size(),
+                        hipMemcpyHostToDevice));
   }
-  HIPCHK(c, hipGetLastError());
-  return MP_OK;
+  return enqueue_stage(c, 3);
 }
 
 mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
