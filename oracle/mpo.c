@@ -792,3 +792,274 @@ int mpo_diag(const mpo_problem *pb, const double *U, double *out) {
   out[nU + 5] = nonfin;
   return MPO_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Phase-Field step                                                         */
+/* ---------------------------------------------------------------------- */
+
+/* g(phi) = phi^2 (1 - phi)^2  =>  g'(phi) = 2 phi (1 - phi)(1 - 2 phi). */
+double mpo_pf_gprime(double phi) {
+  return 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi);
+}
+
+/* Dense Gaussian elimination with partial pivoting, n <= MPO_MAXP; returns
+ * 0 if a pivot is exactly zero. */
+static int small_solve(int n, double A[MPO_MAXP][MPO_MAXP], double *b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
+    if (A[piv][k] == 0.0) return 0;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) {
+        double t = A[k][j]; A[k][j] = A[piv][j]; A[piv][j] = t;
+      }
+      double t = b[k]; b[k] = b[piv]; b[piv] = t;
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = A[i][k] / A[k][k];
+      for (int j = k; j < n; ++j) A[i][j] = A[i][j] - f * A[k][j];
+      b[i] = b[i] - f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int j = k + 1; j < n; ++j) s = s - A[k][j] * b[j];
+    b[k] = s / A[k][k];
+  }
+  return 1;
+}
+
+/* W_{p,q} of Eq. (28) */
+static double pf_W(const double *phi, int p, int q) {
+  return p == q ? phi[p] * (1.0 - phi[q]) : -phi[p] * phi[q];
+}
+
+int mpo_pf_divj(const mpo_problem *pb, const double *U, double eta,
+                double *divj, double *info) {
+  int st = check_problem(pb);
+  if (st != MPO_OK) return st;
+  if (!(eta > 0.0)) return MPO_ERR_ARG;
+  const int N = pb->nphase, nd = pb->ndim;
+  const long nc = mpo_ncells(pb);
+  long n3[3] = {1, 1, 1};
+  for (int d = 0; d < nd; ++d) n3[d] = pb->n[d];
+  const long sx[3] = {1, n3[0], n3[0] * n3[1]};
+  double vol = 1.0;
+  for (int d = 0; d < nd; ++d) vol *= pb->dx[d];
+
+  /* mobility M = 0.5 eta max |u| over the cells */
+  double umax = 0.0;
+  for (long i = 0; i < nc; ++i) {
+    double rho = 0.0, u2 = 0.0;
+    for (int p = 0; p < N; ++p) rho = rho + U[IM(p) * nc + i];
+    for (int k = 0; k < nd; ++k) {
+      const double u = U[IMOM(pb, k) * nc + i] / rho;
+      u2 = u2 + u * u;
+    }
+    const double s = sqrt(u2);
+    if (s > umax) umax = s;
+  }
+  const double M = 0.5 * eta * umax;
+  const double Me2 = M / (eta * eta);
+
+  /* R_p = M/eta^2 (g'(phi_p) - phi_p sum_q g'(phi_q)) and the integrals */
+  double *R = malloc(sizeof(double) * (size_t)N * (size_t)nc);
+  if (!R) return MPO_ERR_ARG;
+  double Wint[MPO_MAXP][MPO_MAXP], Rint[MPO_MAXP], phint[MPO_MAXP];
+  for (int p = 0; p < N; ++p) {
+    Rint[p] = 0.0;
+    phint[p] = 0.0;
+    for (int q = 0; q < N; ++q) Wint[p][q] = 0.0;
+  }
+  for (long i = 0; i < nc; ++i) {
+    double phi[MPO_MAXP], sg = 0.0;
+    for (int p = 0; p < N; ++p) phi[p] = U[IA(pb, p) * nc + i];
+    for (int q = 0; q < N; ++q) sg = sg + mpo_pf_gprime(phi[q]);
+    for (int p = 0; p < N; ++p) {
+      const double r = Me2 * (mpo_pf_gprime(phi[p]) - phi[p] * sg);
+      R[p * nc + i] = r;
+      Rint[p] = Rint[p] + r * vol;
+      phint[p] = phint[p] + phi[p] * vol;
+      for (int q = 0; q < N; ++q) Wint[p][q] = Wint[p][q] + pf_W(phi, p, q) * vol;
+    }
+  }
+
+  /* multipliers over the present phases, gauge B_last = 0 */
+  int pres[MPO_MAXP], np = 0;
+  for (int p = 0; p < N; ++p)
+    if (phint[p] > 0.0) pres[np++] = p;
+  double B[MPO_MAXP];
+  for (int q = 0; q < N; ++q) B[q] = 0.0;
+  if (np > 1) {
+    const int n = np - 1;
+    double A[MPO_MAXP][MPO_MAXP], b[MPO_MAXP];
+    for (int a = 0; a < n; ++a) {
+      for (int c = 0; c < n; ++c) A[a][c] = Wint[pres[a]][pres[c]];
+      b[a] = Rint[pres[a]];
+    }
+    if (small_solve(n, A, b))
+      for (int a = 0; a < n; ++a) B[pres[a]] = b[a];
+  }
+
+  /* [div J_p] = M lap(phi_p) - R_p + sum_q W_pq B_q */
+  for (long i = 0; i < nc; ++i) {
+    long idx[3] = {i % n3[0], (i / n3[0]) % n3[1], i / (n3[0] * n3[1])};
+    double phi[MPO_MAXP];
+    for (int p = 0; p < N; ++p) phi[p] = U[IA(pb, p) * nc + i];
+    for (int p = 0; p < N; ++p) {
+      const double *f = U + IA(pb, p) * nc;
+      double lap = 0.0;
+      for (int d = 0; d < nd; ++d) {
+        const long base = i - idx[d] * sx[d];
+        const long lo = ghost_index(idx[d] - 1, n3[d], pb->bc[d][0], pb->bc[d][1]);
+        const long hi = ghost_index(idx[d] + 1, n3[d], pb->bc[d][0], pb->bc[d][1]);
+        const double h2 = pb->dx[d] * pb->dx[d];
+        lap = lap + (f[base + hi * sx[d]] - 2.0 * f[i] + f[base + lo * sx[d]]) / h2;
+      }
+      double Lc = 0.0;
+      for (int q = 0; q < N; ++q) Lc = Lc + pf_W(phi, p, q) * B[q];
+      divj[p * nc + i] = M * lap - R[p * nc + i] + Lc;
+    }
+  }
+  free(R);
+  if (info) {
+    info[0] = M;
+    info[1] = (double)np;
+    for (int q = 0; q < N; ++q) info[2 + q] = B[q];
+  }
+  return MPO_OK;
+}
+
+void mpo_pf_flux(const mpo_problem *pb, int dir, const double *VL,
+                 const double *VR, const double *G, double *F) {
+  (void)dir;
+  const int N = pb->nphase, nd = pb->ndim, nU = mpo_nU(pb);
+  const double *mL = VL, *uL = VL + N, PL = VL[N + nd], *aL = VL + N + nd + 1;
+  const double *mR = VR, *uR = VR + N, PR = VR[N + nd], *aR = VR + N + nd + 1;
+  for (int c = 0; c < nU; ++c) F[c] = 0.0;
+  double keL = 0.0, keR = 0.0;
+  for (int k = 0; k < nd; ++k) {
+    keL = keL + uL[k] * uL[k];
+    keR = keR + uR[k] * uR[k];
+  }
+  keL = 0.5 * keL;
+  keR = 0.5 * keR;
+  double S = 0.0;
+  for (int p = 0; p < N; ++p) {
+    const double gm = G[p] < 0.0 ? G[p] : 0.0;
+    const double gp = G[p] > 0.0 ? G[p] : 0.0;
+    const double dl = gm * (1.0 - aR[p]);   /* left cell gives  (G < 0) */
+    const double dr = gp * (1.0 - aL[p]);   /* right cell gives (G > 0) */
+    const double A = eos_A(pb, p), B = eos_B(pb, p), D = pb->D[p];
+    const double fa = dl * aL[p] + dr * aR[p];
+    const double fm = dl * mL[p] + dr * mR[p];
+    F[IA(pb, p)] = fa;
+    F[IM(p)] = fm;
+    for (int k = 0; k < nd; ++k)
+      F[IMOM(pb, k)] = F[IMOM(pb, k)] + (dl * mL[p] * uL[k] + dr * mR[p] * uR[k]);
+    F[IE(pb)] = F[IE(pb)] +
+                (dl * (mL[p] * keL + aL[p] * (A * PL + B) + mL[p] * D) +
+                 dr * (mR[p] * keR + aR[p] * (A * PR + B) + mR[p] * D));
+    S = S + fa;
+  }
+  /* sum_p J_p = 0 at the face */
+  double ub[3] = {0.0, 0.0, 0.0}, keb = 0.0;
+  for (int k = 0; k < nd; ++k) {
+    ub[k] = 0.5 * (uL[k] + uR[k]);
+    keb = keb + ub[k] * ub[k];
+  }
+  keb = 0.5 * keb;
+  const double Pb = 0.5 * (PL + PR);
+  for (int p = 0; p < N; ++p) {
+    const double ca = 0.5 * (aL[p] + aR[p]) * S;
+    const double cm = 0.5 * (mL[p] + mR[p]) * S;
+    F[IA(pb, p)] = F[IA(pb, p)] - ca;
+    F[IM(p)] = F[IM(p)] - cm;
+    for (int k = 0; k < nd; ++k) F[IMOM(pb, k)] = F[IMOM(pb, k)] - cm * ub[k];
+    F[IE(pb)] = F[IE(pb)] - (cm * (keb + pb->D[p]) +
+                             ca * (eos_A(pb, p) * Pb + eos_B(pb, p)));
+  }
+}
+
+/* L^PF(U): per direction, WENO-C/CL face states of cells -1..n of every line
+ * (the reconstruction of the hyperbolic step), the PF flux at faces
+ * -1/2..n-1/2 with the frozen gradient of that face, and
+ *   +(F_{i+1/2} - F_{i-1/2}) / dx   (Eq. (5): dU/dt = +div F^PF). */
+int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
+               double *L) {
+  int st = check_problem(pb);
+  if (st != MPO_OK) return st;
+  const int N = pb->nphase, nU = mpo_nU(pb), nd = pb->ndim;
+  const long nc = mpo_ncells(pb);
+  long n3[3] = {1, 1, 1};
+  for (int d = 0; d < nd; ++d) n3[d] = pb->n[d];
+  const long sx[3] = {1, n3[0], n3[0] * n3[1]};
+  memset(L, 0, sizeof(double) * (size_t)nU * (size_t)nc);
+
+  for (int dir = 0; dir < nd; ++dir) {
+    const long n = n3[dir], s = sx[dir];
+    const int o1 = (dir + 1) % 3, o2 = (dir + 2) % 3;
+    const long nl = n3[o1] * n3[o2];
+    const double dx = pb->dx[dir];
+    const int periodic = pb->bc[dir][0] == MPO_BC_PERIODIC;
+#pragma omp parallel
+    {
+      double *UL = malloc(sizeof(double) * (size_t)(n + 2) * nU);
+      double *UR = malloc(sizeof(double) * (size_t)(n + 2) * nU);
+      double *VL = malloc(sizeof(double) * (size_t)(n + 2) * nU);
+      double *VR = malloc(sizeof(double) * (size_t)(n + 2) * nU);
+      double *F = malloc(sizeof(double) * (size_t)(n + 1) * nU);
+      double Us[5 * (4 * MPO_MAXP + 4)], Gf[MPO_MAXP];
+#pragma omp for schedule(static)
+      for (long line = 0; line < nl; ++line) {
+        const long j1 = line % n3[o1], j2 = line / n3[o1];
+        const long base = j1 * sx[o1] + j2 * sx[o2];
+        for (long i = -1; i <= n; ++i) {
+          for (int j = 0; j < 5; ++j) {
+            long g = ghost_index(i - 2 + j, n, pb->bc[dir][0], pb->bc[dir][1]);
+            for (int c = 0; c < nU; ++c) Us[j * nU + c] = U[c * nc + base + g * s];
+          }
+          mpo_reconstruct_cell(pb, Us, dir, UL + (i + 1) * nU, UR + (i + 1) * nU,
+                               VL + (i + 1) * nU, VR + (i + 1) * nU, NULL);
+        }
+        for (long f = 0; f <= n; ++f) { /* face between cells f-1 and f */
+          /* the upper face of cell f-1; face -1/2 is face n-1/2 when periodic
+           * and carries no gradient at an outflow end */
+          const long owner = f > 0 ? f - 1 : (periodic ? n - 1 : -1);
+          for (int p = 0; p < N; ++p)
+            Gf[p] = owner >= 0 ? G[(long)(dir * N + p) * nc + base + owner * s] : 0.0;
+          mpo_pf_flux(pb, dir, VL + f * nU, VR + (f + 1) * nU, Gf, F + f * nU);
+        }
+        for (long i = 0; i < n; ++i) {
+          const long cell = base + i * s;
+          for (int c = 0; c < nU; ++c)
+            L[c * nc + cell] =
+                L[c * nc + cell] + (F[(i + 1) * nU + c] - F[i * nU + c]) / dx;
+        }
+      }
+      free(UL); free(UR); free(VL); free(VR); free(F);
+    }
+  }
+  return MPO_OK;
+}
+
+int mpo_pf_rk3(const mpo_problem *pb, double *U, const double *G, double dt) {
+  int st = check_problem(pb);
+  if (st != MPO_OK) return st;
+  const long nt = (long)mpo_nU(pb) * mpo_ncells(pb);
+  double *L = malloc(sizeof(double) * (size_t)nt);
+  double *U1 = malloc(sizeof(double) * (size_t)nt);
+  double *U2 = malloc(sizeof(double) * (size_t)nt);
+  if (!L || !U1 || !U2) { free(L); free(U1); free(U2); return MPO_ERR_ARG; }
+  mpo_pf_rhs(pb, U, G, L);
+  for (long k = 0; k < nt; ++k) U1[k] = U[k] + dt * L[k];
+  mpo_pf_rhs(pb, U1, G, L);
+  for (long k = 0; k < nt; ++k)
+    U2[k] = 0.75 * U[k] + 0.25 * U1[k] + 0.25 * (dt * L[k]);
+  mpo_pf_rhs(pb, U2, G, L);
+  for (long k = 0; k < nt; ++k)
+    U[k] = U[k] / 3.0 + 2.0 * U2[k] / 3.0 + 2.0 * (dt * L[k]) / 3.0;
+  free(L); free(U1); free(U2);
+  return MPO_OK;
+}

@@ -129,6 +129,48 @@ int mpo_step(const mpo_problem *pb, double *U, double dt);
  * [n_U+5] = count of non-finite entries. */
 int mpo_diag(const mpo_problem *pb, const double *U, double *out);
 
+/* ---- Phase-Field step (Sec. 2.2.1, Eqs. (4)-(5); Sec. 4, Eq. (28)) ------ */
+
+/* g'(phi) of the double well g(phi) = phi^2 (1 - phi)^2 of Eq. (28). */
+double mpo_pf_gprime(double phi);
+
+/* [div J_p] of the reduction-consistent conservative Allen-Cahn model,
+ * Eq. (28), with the volume fractions of U as the order parameters phi_p:
+ * second-order central Laplacian (ghost cells by the boundary rule),
+ * mid-point integrals, mobility M = eta max_cells |u| / 2.
+ * The multipliers B_q solve the integral system of Eq. (28); that system is
+ * singular (its rows and columns sum to zero when sum_p phi_p = 1), so it is
+ * solved over the present phases (integral of phi_p > 0) with B of the last
+ * present phase set to 0 (reading; L^c does not depend on the choice).
+ * divj: N fields, divj[p * ncells + cell].
+ * info (may be NULL; 2 + MPO_MAXP entries): [0] = M, [1] = number of present
+ * phases, [2 + q] = B_q. */
+int mpo_pf_divj(const mpo_problem *pb, const double *U, double eta,
+                double *divj, double *info);
+
+/* Phase-Field numerical flux across a face normal to dir (reading of the
+ * bound-preserving flux the paper cites): from the face primitives VL, VR
+ * (m, u, P, alpha) and the face gradients G_p = dQ_p/dx_dir,
+ *   F^alpha_p = min(G_p,0) alpha_p^L (1 - alpha_p^R)
+ *             + max(G_p,0) alpha_p^R (1 - alpha_p^L)
+ * (the donor side gives, the receiver needs room), F^m_p the same with m_p
+ * as the donor factor, momentum and energy carried with the donor's u and
+ * (|u|^2/2, A_p P + B_p, D_p) as in F^PF of Eq. (1); then
+ * S = sum_p F^alpha_p is removed in proportion to the face-average alpha_p
+ * (mass in proportion to the face-average m_p, with face-average u and P), so
+ * that sum_p F^alpha_p = 0 at every face. */
+void mpo_pf_flux(const mpo_problem *pb, int dir, const double *VL,
+                 const double *VR, const double *G, double *F);
+
+/* The Phase-Field operator of Eq. (5), L^PF(U) = div F^PF, with WENO-C/CL
+ * face states and frozen face gradients G: G[(d * N + p) * ncells + cell]
+ * is dQ_p/dx_d at the upper face (x_{i+1/2}) of the cell. */
+int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
+               double *L);
+/* Third-order SSP Runge-Kutta of the Phase-Field step with G frozen, in
+ * place (Sec. 4: the same time stepping as the hyperbolic step). */
+int mpo_pf_rk3(const mpo_problem *pb, double *U, const double *G, double dt);
+
 /* threads the OpenMP loops use (1 when built without OpenMP) */
 int mpo_num_threads(void);
 void mpo_set_num_threads(int n);

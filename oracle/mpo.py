@@ -81,6 +81,12 @@ def lib():
         L.mpo_flux.argtypes = [pp, C.c_int, dp, dp, dp, dp, dp, dp]
         L.mpo_gl_interior.argtypes = [C.c_double] * 3
         L.mpo_gl_interior.restype = C.c_double
+        L.mpo_pf_gprime.argtypes = [C.c_double]
+        L.mpo_pf_gprime.restype = C.c_double
+        L.mpo_pf_divj.argtypes = [pp, dp, C.c_double, dp, dp]
+        L.mpo_pf_flux.argtypes = [pp, C.c_int, dp, dp, dp, dp]
+        L.mpo_pf_rhs.argtypes = [pp, dp, dp, dp]
+        L.mpo_pf_rk3.argtypes = [pp, dp, dp, C.c_double]
         L.mpo_num_threads.restype = C.c_int
         L.mpo_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -132,6 +138,8 @@ class Problem:
         p.t_end = float(t_end)
         self._p = p
         self.ndim, self.N = ndim, N
+        self.dx = tuple(float(dd[k]) for k in range(ndim))
+        self.bc = tuple((int(bcl[k][0]), int(bcl[k][1])) for k in range(ndim))
         self.nU = 2 * N + ndim + 1
         self.shape = tuple(int(nn[k]) for k in range(ndim))
 
@@ -167,6 +175,134 @@ class Problem:
         out = np.zeros(self.nU + 6)
         lib().mpo_diag(self.ref(), _ptr(U), _ptr(out))
         return out
+
+    # ---- Phase-Field step ----------------------------------------------
+    def pf_divj(self, U, eta):
+        """[div J_p] of Eq. (28) on the volume fractions of U: (N, ncells)
+        and info = (M, number of present phases, B_1..B_N)."""
+        U = _arr(U, self.nU * self.ncells)
+        out = np.zeros(self.N * self.ncells)
+        info = np.zeros(2 + MAXP)
+        st = lib().mpo_pf_divj(self.ref(), _ptr(U), float(eta), _ptr(out), _ptr(info))
+        if st != 0:
+            raise RuntimeError(f"mpo_pf_divj status {st}")
+        return out.reshape(self.N, self.ncells), {
+            "M": info[0], "present": int(info[1]), "B": info[2:2 + self.N].copy()}
+
+    def _faces(self):
+        """Upper-face pairs (i, j) per direction: j is the neighbour of cell i
+        at x_{i+1/2}; an outflow end has no face (zero flux)."""
+        shape = self.shape[::-1]            # (ny, nx) / (nx,)
+        idx = np.arange(self.ncells).reshape(shape)
+        out = []
+        for d in range(self.ndim):
+            ax = self.ndim - 1 - d
+            j = np.roll(idx, -1, axis=ax)
+            i = idx
+            if self.bc[d][1] != BC_PERIODIC:
+                sl = [slice(None)] * self.ndim
+                sl[ax] = slice(0, shape[ax] - 1)
+                i, j = i[tuple(sl)], j[tuple(sl)]
+            out.append((i.reshape(-1), j.reshape(-1)))
+        return out
+
+    def q_operator(self, phi):
+        """The matrix of the discrete left side of Eq. (4):
+        (A Q)_i = sum_d [k_{i+1/2}(Q_{i+1} - Q_i) - k_{i-1/2}(Q_i - Q_{i-1})]/dx_d^2
+        with k = phi (1 - phi) and the face k the mean of its two cells
+        (reading: second order, as the other discrete operators of Eq. (28))."""
+        import scipy.sparse as sp
+        k = phi * (1.0 - phi)
+        rows, cols, vals = [], [], []
+        for d, (i, j) in enumerate(self._faces()):
+            c = 0.5 * (k[i] + k[j]) / self.dx[d] ** 2
+            rows += [i, i, j, j]
+            cols += [i, j, j, i]
+            vals += [-c, c, -c, c]
+        n = self.ncells
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows),
+                                                     np.concatenate(cols))), shape=(n, n))
+
+    def pf_gradients(self, U, divj):
+        """Solve Eq. (4) for each phase by a sparse direct solve (the
+        definition: the solution of the discrete system) and return the face
+        gradients G (ndim, N, ncells): dQ_p/dx_d at the upper face of each
+        cell (0 at an outflow end and where the face k is 0), plus the
+        relative residuals.  Q is fixed
+        up to a constant on each connected set of cells joined by faces with
+        k > 0; one cell of each set is held at 0, cells with no such face
+        keep Q = 0."""
+        import scipy.sparse.csgraph as cg
+        import scipy.sparse.linalg as sla
+        U = _arr(U, self.nU * self.ncells).reshape(self.nU, self.ncells)
+        faces = self._faces()
+        G = np.zeros((self.ndim, self.N, self.ncells))
+        res = np.zeros(self.N)
+        for p in range(self.N):
+            phi = U[self.N + self.ndim + 1 + p]
+            r = np.asarray(divj[p], dtype=np.float64)
+            Q = np.zeros(self.ncells)
+            if np.any(r != 0.0):
+                A = self.q_operator(phi)
+                off = A.copy()
+                off.setdiag(0.0)
+                off.eliminate_zeros()
+                ncomp, lab = cg.connected_components(off != 0, directed=False)
+                deg = np.asarray((off != 0).sum(axis=1)).ravel()
+                keep = np.ones(self.ncells, dtype=bool)
+                keep[deg == 0] = False
+                for c in range(ncomp):
+                    cells = np.nonzero((lab == c) & keep)[0]
+                    if cells.size:
+                        keep[cells[0]] = False
+                ix = np.nonzero(keep)[0]
+                if ix.size:
+                    Q[ix] = sla.spsolve(A[ix][:, ix].tocsc(), r[ix])
+                nr = np.linalg.norm(r)
+                res[p] = np.linalg.norm(A @ Q - r) / nr
+            k = phi * (1.0 - phi)
+            for d, (i, j) in enumerate(faces):
+                # no gradient across a face with k = 0: Q on its two sides
+                # belongs to separate sets (reading)
+                kf = 0.5 * (k[i] + k[j])
+                G[d, p, i] = np.where(kf > 0.0, (Q[j] - Q[i]) / self.dx[d], 0.0)
+        return G, res
+
+    def pf_rhs(self, U, G):
+        U = _arr(U, self.nU * self.ncells)
+        G = _arr(G, self.ndim * self.N * self.ncells)
+        L = np.empty_like(U)
+        st = lib().mpo_pf_rhs(self.ref(), _ptr(U), _ptr(G), _ptr(L))
+        if st != 0:
+            raise RuntimeError(f"mpo_pf_rhs status {st}")
+        return L
+
+    def pf_rk3(self, U, G, dt):
+        U = _arr(U, self.nU * self.ncells).copy()
+        G = _arr(G, self.ndim * self.N * self.ncells)
+        st = lib().mpo_pf_rk3(self.ref(), _ptr(U), _ptr(G), float(dt))
+        if st != 0:
+            raise RuntimeError(f"mpo_pf_rk3 status {st}")
+        return U
+
+    def pf_step(self, U, dt, eta):
+        """The Phase-Field step of Sec. 2.2.1: phi_p = alpha_p of U (the
+        hyperbolic result), [div J_p] by Eq. (28), Q_p by Eq. (4), then
+        SSP-RK3 of Eq. (5) with the gradients frozen over the step."""
+        divj, info = self.pf_divj(U, eta)
+        G, res = self.pf_gradients(U, divj)
+        return self.pf_rk3(U, G, dt), {"divj": divj, "G": G, "residual": res, **info}
+
+    def step_pf(self, U, dt, eta):
+        """One full time step with the Phase-Field mechanism: the hyperbolic
+        SSP-RK3 step, then the Phase-Field step, both with dt."""
+        return self.pf_step(self.step(U, dt), dt, eta)
+
+    def pf_flux(self, VL, VR, G, dir=0):
+        F = np.zeros(self.nU)
+        lib().mpo_pf_flux(self.ref(), int(dir), _ptr(_arr(VL, self.nU)),
+                          _ptr(_arr(VR, self.nU)), _ptr(_arr(G, self.N)), _ptr(F))
+        return F
 
     # ---- pointwise building blocks -------------------------------------
     def pressure(self, Ucell):
@@ -254,6 +390,10 @@ def weno5w(q):
 
 def gl_interior(fbar, fL, fR):
     return lib().mpo_gl_interior(float(fbar), float(fL), float(fR))
+
+
+def pf_gprime(phi):
+    return lib().mpo_pf_gprime(float(phi))
 
 
 def num_threads():

@@ -514,6 +514,56 @@ def air_helium_shock_tube(dx=0.01, opts=None):
 # random admissible states for parity tests
 # ---------------------------------------------------------------------------
 
+def pf_bubble(shape, nphase=2, width=1.0, bc=BC_PERIODIC, u=(1.0, 0.5),
+              r=0.25, opts=None):
+    """A Phase-Field test state: gas bubble (radius r of the unit box, tanh
+    profile `width` cells wide) in water (SI); for N = 3 a shell of the third
+    liquid (thickness r/2) around it; uniform velocity and P = 1e5.  1D: a
+    slab [0.5 - r, 0.5 + r].  Cell averages by Gauss quadrature."""
+    shape = tuple(shape)
+    ndim = len(shape)
+    N = nphase
+    mats = [AIR_SI, WATER_SI, CAVITY_WATER_SI][:N]
+    g, pi, D = _eos(mats)
+    rho = np.array([1.0, 1000.0, 1030.0])[:N]
+    if ndim == 1:
+        n = shape[0]
+        dx = 1.0 / n
+        w = width * dx
+        a1 = np.clip(cell_average_1d(lambda x: _tanh_slab(x, 0.5 - r, 0.5 + r, w),
+                                     n, 0.0, 1.0), 0.0, 1.0)
+        if N == 3:
+            a13 = np.clip(cell_average_1d(
+                lambda x: _tanh_slab(x, 0.5 - 1.5 * r, 0.5 + 1.5 * r, w), n, 0.0, 1.0), 0.0, 1.0)
+        dxs = (dx,)
+        vel = np.full((1, n), float(u[0]))
+    else:
+        nx, ny = shape
+        dx = 1.0 / nx
+        w = width * dx
+        box = ((0, 1), (0, ny / nx))
+        yc = 0.5 * ny / nx
+        a1 = np.clip(cell_average_2d(lambda X, Y: _tanh_disc(X, Y, 0.5, yc, r, w),
+                                     nx, ny, box), 0.0, 1.0)
+        if N == 3:
+            a13 = np.clip(cell_average_2d(
+                lambda X, Y: _tanh_disc(X, Y, 0.5, yc, 1.5 * r, w), nx, ny, box), 0.0, 1.0)
+        dxs = (dx, dx)
+        vel = np.stack([np.full((ny, nx), float(u[0])), np.full((ny, nx), float(u[1]))])
+    if N == 3:
+        a3 = np.clip(a13 - a1, 0.0, 1.0)
+        alpha = np.stack([a1, 1.0 - a1 - a3, a3])
+        alpha[1] = np.clip(alpha[1], 0.0, 1.0)
+    else:
+        alpha = np.stack([a1, 1.0 - a1])
+    m = np.stack([rho[p] * alpha[p] for p in range(N)])
+    U = conserved(alpha, m, vel, 1e5, g, pi, D)
+    o = opts or Options(flux=FLUX_HLL, cfl=0.2, phase_field=1)
+    return Workload("pf_bubble_%s_N%d" % ("x".join(map(str, shape)), N), ndim, shape,
+                    dxs, ((bc, bc),) * ndim, g, pi, D, default_pmin(pi, 1e5),
+                    np.zeros(N), _to4d(U, ndim), t_end=0.0, opts=o)
+
+
 def random_state(shape, nphase=2, seed=0, ndim=None, bc=BC_PERIODIC,
                  si=True, absent=(), opts=None, rough=0.5, lowp=0.02):
     """Admissible but rough states: sharp material jumps, mixed cells, random
