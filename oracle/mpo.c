@@ -932,7 +932,8 @@ int mpo_pf_divj(const mpo_problem *pb, const double *U, double eta,
 }
 
 void mpo_pf_flux(const mpo_problem *pb, int dir, const double *VL,
-                 const double *VR, const double *G, double *F) {
+                 const double *VR, const double *G, const double *kf,
+                 double *F) {
   (void)dir;
   const int N = pb->nphase, nd = pb->ndim, nU = mpo_nU(pb);
   const double *mL = VL, *uL = VL + N, PL = VL[N + nd], *aL = VL + N + nd + 1;
@@ -949,8 +950,12 @@ void mpo_pf_flux(const mpo_problem *pb, int dir, const double *VL,
   for (int p = 0; p < N; ++p) {
     const double gm = G[p] < 0.0 ? G[p] : 0.0;
     const double gp = G[p] > 0.0 ? G[p] : 0.0;
-    const double dl = gm * (1.0 - aR[p]);   /* left cell gives  (G < 0) */
-    const double dr = gp * (1.0 - aL[p]);   /* right cell gives (G > 0) */
+    /* donor/receiver product, capped at the face coefficient of Eq. (4) */
+    const double bl = aL[p] * (1.0 - aR[p]), br = aR[p] * (1.0 - aL[p]);
+    const double sl = bl > kf[p] ? kf[p] / bl : 1.0;
+    const double sr = br > kf[p] ? kf[p] / br : 1.0;
+    const double dl = gm * (1.0 - aR[p]) * sl;   /* left cell gives  (G < 0) */
+    const double dr = gp * (1.0 - aL[p]) * sr;   /* right cell gives (G > 0) */
     const double A = eos_A(pb, p), B = eos_B(pb, p), D = pb->D[p];
     const double fa = dl * aL[p] + dr * aR[p];
     const double fm = dl * mL[p] + dr * mR[p];
@@ -987,7 +992,7 @@ void mpo_pf_flux(const mpo_problem *pb, int dir, const double *VL,
  * -1/2..n-1/2 with the frozen gradient of that face, and
  *   +(F_{i+1/2} - F_{i-1/2}) / dx   (Eq. (5): dU/dt = +div F^PF). */
 int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
-               double *L) {
+               const double *K, double *L) {
   int st = check_problem(pb);
   if (st != MPO_OK) return st;
   const int N = pb->nphase, nU = mpo_nU(pb), nd = pb->ndim;
@@ -1010,7 +1015,7 @@ int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
       double *VL = malloc(sizeof(double) * (size_t)(n + 2) * nU);
       double *VR = malloc(sizeof(double) * (size_t)(n + 2) * nU);
       double *F = malloc(sizeof(double) * (size_t)(n + 1) * nU);
-      double Us[5 * (4 * MPO_MAXP + 4)], Gf[MPO_MAXP];
+      double Us[5 * (4 * MPO_MAXP + 4)], Gf[MPO_MAXP], kf[MPO_MAXP];
 #pragma omp for schedule(static)
       for (long line = 0; line < nl; ++line) {
         const long j1 = line % n3[o1], j2 = line / n3[o1];
@@ -1027,9 +1032,15 @@ int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
           /* the upper face of cell f-1; face -1/2 is face n-1/2 when periodic
            * and carries no gradient at an outflow end */
           const long owner = f > 0 ? f - 1 : (periodic ? n - 1 : -1);
-          for (int p = 0; p < N; ++p)
+          const long other = f < n ? f : (periodic ? 0 : -1);
+          for (int p = 0; p < N; ++p) {
             Gf[p] = owner >= 0 ? G[(long)(dir * N + p) * nc + base + owner * s] : 0.0;
-          mpo_pf_flux(pb, dir, VL + f * nU, VR + (f + 1) * nU, Gf, F + f * nU);
+            kf[p] = (owner >= 0 && other >= 0)
+                        ? 0.5 * (K[(long)p * nc + base + owner * s] +
+                                 K[(long)p * nc + base + other * s])
+                        : 0.0;
+          }
+          mpo_pf_flux(pb, dir, VL + f * nU, VR + (f + 1) * nU, Gf, kf, F + f * nU);
         }
         for (long i = 0; i < n; ++i) {
           const long cell = base + i * s;
@@ -1044,7 +1055,8 @@ int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
   return MPO_OK;
 }
 
-int mpo_pf_rk3(const mpo_problem *pb, double *U, const double *G, double dt) {
+int mpo_pf_rk3(const mpo_problem *pb, double *U, const double *G,
+               const double *K, double dt) {
   int st = check_problem(pb);
   if (st != MPO_OK) return st;
   const long nt = (long)mpo_nU(pb) * mpo_ncells(pb);
@@ -1052,12 +1064,12 @@ int mpo_pf_rk3(const mpo_problem *pb, double *U, const double *G, double dt) {
   double *U1 = malloc(sizeof(double) * (size_t)nt);
   double *U2 = malloc(sizeof(double) * (size_t)nt);
   if (!L || !U1 || !U2) { free(L); free(U1); free(U2); return MPO_ERR_ARG; }
-  mpo_pf_rhs(pb, U, G, L);
+  mpo_pf_rhs(pb, U, G, K, L);
   for (long k = 0; k < nt; ++k) U1[k] = U[k] + dt * L[k];
-  mpo_pf_rhs(pb, U1, G, L);
+  mpo_pf_rhs(pb, U1, G, K, L);
   for (long k = 0; k < nt; ++k)
     U2[k] = 0.75 * U[k] + 0.25 * U1[k] + 0.25 * (dt * L[k]);
-  mpo_pf_rhs(pb, U2, G, L);
+  mpo_pf_rhs(pb, U2, G, K, L);
   for (long k = 0; k < nt; ++k)
     U[k] = U[k] / 3.0 + 2.0 * U2[k] / 3.0 + 2.0 * (dt * L[k]) / 3.0;
   free(L); free(U1); free(U2);

@@ -150,26 +150,32 @@ int mpo_pf_divj(const mpo_problem *pb, const double *U, double eta,
 
 /* Phase-Field numerical flux across a face normal to dir (reading of the
  * bound-preserving flux the paper cites): from the face primitives VL, VR
- * (m, u, P, alpha) and the face gradients G_p = dQ_p/dx_dir,
- *   F^alpha_p = min(G_p,0) alpha_p^L (1 - alpha_p^R)
- *             + max(G_p,0) alpha_p^R (1 - alpha_p^L)
- * (the donor side gives, the receiver needs room), F^m_p the same with m_p
- * as the donor factor, momentum and energy carried with the donor's u and
- * (|u|^2/2, A_p P + B_p, D_p) as in F^PF of Eq. (1); then
+ * (m, u, P, alpha), the face gradients G_p = dQ_p/dx_dir and the face
+ * coefficients kf_p of Eq. (4),
+ *   F^alpha_p = min(G_p,0) c(alpha_p^L (1 - alpha_p^R))
+ *             + max(G_p,0) c(alpha_p^R (1 - alpha_p^L)),  c(x) = min(x, kf_p)
+ * (the donor side gives, the receiver needs room, and the flux never exceeds
+ * the k_f dQ/dx that Eq. (4) delivers), F^m_p the same with m_p as the donor
+ * factor (scaled by the same cap), momentum and energy carried with the
+ * donor's u and (|u|^2/2, A_p P + B_p, D_p) as in F^PF of Eq. (1); then
  * S = sum_p F^alpha_p is removed in proportion to the face-average alpha_p
  * (mass in proportion to the face-average m_p, with face-average u and P), so
  * that sum_p F^alpha_p = 0 at every face. */
 void mpo_pf_flux(const mpo_problem *pb, int dir, const double *VL,
-                 const double *VR, const double *G, double *F);
+                 const double *VR, const double *G, const double *kf,
+                 double *F);
 
 /* The Phase-Field operator of Eq. (5), L^PF(U) = div F^PF, with WENO-C/CL
- * face states and frozen face gradients G: G[(d * N + p) * ncells + cell]
- * is dQ_p/dx_d at the upper face (x_{i+1/2}) of the cell. */
+ * face states, frozen face gradients G and frozen cell coefficients K:
+ * G[(d * N + p) * ncells + cell] is dQ_p/dx_d at the upper face
+ * (x_{i+1/2}) of the cell, K[p * ncells + cell] the k_p of Eq. (4) there
+ * (the face coefficient is the mean of its two cells). */
 int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
-               double *L);
-/* Third-order SSP Runge-Kutta of the Phase-Field step with G frozen, in
- * place (Sec. 4: the same time stepping as the hyperbolic step). */
-int mpo_pf_rk3(const mpo_problem *pb, double *U, const double *G, double dt);
+               const double *K, double *L);
+/* Third-order SSP Runge-Kutta of the Phase-Field step with G and K frozen,
+ * in place (Sec. 4: the same time stepping as the hyperbolic step). */
+int mpo_pf_rk3(const mpo_problem *pb, double *U, const double *G,
+               const double *K, double dt);
 
 /* threads the OpenMP loops use (1 when built without OpenMP) */
 int mpo_num_threads(void);

@@ -16,6 +16,17 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpo.so")
 MAXP = 8
+# floor of the coefficient k = phi (1 - phi) of Eq. (4) (reading): with it
+# the equation joins all cells and is solvable for every right side of zero
+# total, and its condition number stays bounded; it changes k only where
+# phi < 1e-6 or 1 - phi < 1e-6
+PF_KFLOOR = 1e-6
+# the Phase-Field step's own CFL bound (reading): |G_d| dt / dx_d <= 1/12, the
+# sufficient bound of the Gauss-Lobatto argument (end weight 1/12).  The
+# solve's gradient is clipped there; that happens only in nearly pure cells,
+# where Eq. (4) would carry volume between separate interfaces through a
+# medium of conductivity ~ PF_KFLOOR and the capped flux is negligible.
+PF_CFL = 1.0 / 12.0
 
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 RECON_WENO_C, RECON_WENO_CL = 0, 1
@@ -84,9 +95,9 @@ def lib():
         L.mpo_pf_gprime.argtypes = [C.c_double]
         L.mpo_pf_gprime.restype = C.c_double
         L.mpo_pf_divj.argtypes = [pp, dp, C.c_double, dp, dp]
-        L.mpo_pf_flux.argtypes = [pp, C.c_int, dp, dp, dp, dp]
-        L.mpo_pf_rhs.argtypes = [pp, dp, dp, dp]
-        L.mpo_pf_rk3.argtypes = [pp, dp, dp, C.c_double]
+        L.mpo_pf_flux.argtypes = [pp, C.c_int, dp, dp, dp, dp, dp]
+        L.mpo_pf_rhs.argtypes = [pp, dp, dp, dp, dp]
+        L.mpo_pf_rk3.argtypes = [pp, dp, dp, dp, C.c_double]
         L.mpo_num_threads.restype = C.c_int
         L.mpo_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -209,10 +220,11 @@ class Problem:
     def q_operator(self, phi):
         """The matrix of the discrete left side of Eq. (4):
         (A Q)_i = sum_d [k_{i+1/2}(Q_{i+1} - Q_i) - k_{i-1/2}(Q_i - Q_{i-1})]/dx_d^2
-        with k = phi (1 - phi) and the face k the mean of its two cells
-        (reading: second order, as the other discrete operators of Eq. (28))."""
+        with k = max(phi (1 - phi), PF_KFLOOR) and the face k the mean of its two cells
+        (reading: second order, as the other discrete operators of
+        Eq. (28))."""
         import scipy.sparse as sp
-        k = phi * (1.0 - phi)
+        k = np.maximum(phi * (1.0 - phi), PF_KFLOOR)
         rows, cols, vals = [], [], []
         for d, (i, j) in enumerate(self._faces()):
             c = 0.5 * (k[i] + k[j]) / self.dx[d] ** 2
@@ -227,11 +239,9 @@ class Problem:
         """Solve Eq. (4) for each phase by a sparse direct solve (the
         definition: the solution of the discrete system) and return the face
         gradients G (ndim, N, ncells): dQ_p/dx_d at the upper face of each
-        cell (0 at an outflow end and where the face k is 0), plus the
-        relative residuals.  Q is fixed
-        up to a constant on each connected set of cells joined by faces with
-        k > 0; one cell of each set is held at 0, cells with no such face
-        keep Q = 0."""
+        cell (0 at an outflow end), plus the relative residuals.  Q is fixed
+        up to a constant (the floored k joins all cells); one cell is held at
+        0.  A phase with [div J_p] = 0 everywhere has Q_p = 0."""
         import scipy.sparse.csgraph as cg
         import scipy.sparse.linalg as sla
         U = _arr(U, self.nU * self.ncells).reshape(self.nU, self.ncells)
@@ -257,51 +267,75 @@ class Problem:
                         keep[cells[0]] = False
                 ix = np.nonzero(keep)[0]
                 if ix.size:
-                    Q[ix] = sla.spsolve(A[ix][:, ix].tocsc(), r[ix])
+                    # sparse LU, then iterative refinement with the same
+                    # factors (the coefficient spans many decades)
+                    Ar = A[ix][:, ix].tocsc()
+                    lu = sla.splu(Ar)
+                    x = lu.solve(r[ix])
+                    for _ in range(4):
+                        x = x + lu.solve(r[ix] - Ar @ x)
+                    Q[ix] = x
                 nr = np.linalg.norm(r)
                 res[p] = np.linalg.norm(A @ Q - r) / nr
-            k = phi * (1.0 - phi)
             for d, (i, j) in enumerate(faces):
-                # no gradient across a face with k = 0: Q on its two sides
-                # belongs to separate sets (reading)
-                kf = 0.5 * (k[i] + k[j])
-                G[d, p, i] = np.where(kf > 0.0, (Q[j] - Q[i]) / self.dx[d], 0.0)
+                G[d, p, i] = (Q[j] - Q[i]) / self.dx[d]
         return G, res
 
-    def pf_rhs(self, U, G):
+    def pf_k(self, U):
+        """k_p = max(phi_p (1 - phi_p), PF_KFLOOR) of Eq. (4), (N, ncells)."""
+        a = _arr(U, self.nU * self.ncells).reshape(self.nU, -1)[self.N + self.ndim + 1:]
+        return np.ascontiguousarray(np.maximum(a * (1.0 - a), PF_KFLOOR))
+
+    def pf_rhs(self, U, G, K):
         U = _arr(U, self.nU * self.ncells)
         G = _arr(G, self.ndim * self.N * self.ncells)
+        K = _arr(K, self.N * self.ncells)
         L = np.empty_like(U)
-        st = lib().mpo_pf_rhs(self.ref(), _ptr(U), _ptr(G), _ptr(L))
+        st = lib().mpo_pf_rhs(self.ref(), _ptr(U), _ptr(G), _ptr(K), _ptr(L))
         if st != 0:
             raise RuntimeError(f"mpo_pf_rhs status {st}")
         return L
 
-    def pf_rk3(self, U, G, dt):
+    def pf_rk3(self, U, G, K, dt):
         U = _arr(U, self.nU * self.ncells).copy()
         G = _arr(G, self.ndim * self.N * self.ncells)
-        st = lib().mpo_pf_rk3(self.ref(), _ptr(U), _ptr(G), float(dt))
+        K = _arr(K, self.N * self.ncells)
+        st = lib().mpo_pf_rk3(self.ref(), _ptr(U), _ptr(G), _ptr(K), float(dt))
         if st != 0:
             raise RuntimeError(f"mpo_pf_rk3 status {st}")
         return U
 
+    def pf_clip(self, G, dt):
+        """Gradients clipped to the Phase-Field CFL bound PF_CFL dx_d / dt."""
+        G = np.array(G, dtype=np.float64, copy=True)
+        for d in range(self.ndim):
+            g = PF_CFL * self.dx[d] / dt
+            G[d] = np.minimum(np.maximum(G[d], -g), g)
+        return G
+
     def pf_step(self, U, dt, eta):
         """The Phase-Field step of Sec. 2.2.1: phi_p = alpha_p of U (the
-        hyperbolic result), [div J_p] by Eq. (28), Q_p by Eq. (4), then
-        SSP-RK3 of Eq. (5) with the gradients frozen over the step."""
+        hyperbolic result), [div J_p] by Eq. (28), Q_p by Eq. (4), the face
+        gradients clipped to the PF CFL bound, then SSP-RK3 of Eq. (5) with
+        the gradients frozen over the step."""
         divj, info = self.pf_divj(U, eta)
         G, res = self.pf_gradients(U, divj)
-        return self.pf_rk3(U, G, dt), {"divj": divj, "G": G, "residual": res, **info}
+        G = self.pf_clip(G, dt)
+        K = self.pf_k(U)
+        return self.pf_rk3(U, G, K, dt), {"divj": divj, "G": G, "K": K, "residual": res,
+                                          **info}
 
     def step_pf(self, U, dt, eta):
         """One full time step with the Phase-Field mechanism: the hyperbolic
         SSP-RK3 step, then the Phase-Field step, both with dt."""
         return self.pf_step(self.step(U, dt), dt, eta)
 
-    def pf_flux(self, VL, VR, G, dir=0):
+    def pf_flux(self, VL, VR, G, kf=None, dir=0):
         F = np.zeros(self.nU)
+        kf = np.full(self.N, np.inf) if kf is None else kf
         lib().mpo_pf_flux(self.ref(), int(dir), _ptr(_arr(VL, self.nU)),
-                          _ptr(_arr(VR, self.nU)), _ptr(_arr(G, self.N)), _ptr(F))
+                          _ptr(_arr(VR, self.nU)), _ptr(_arr(G, self.N)),
+                          _ptr(_arr(kf, self.N)), _ptr(F))
         return F
 
     # ---- pointwise building blocks -------------------------------------

@@ -12,7 +12,7 @@ Sec. 4, Eq. (28)) against what the model and the mathematics fix:
   gradients; the constant-coefficient operator is the five-point Laplacian;
 * the PF flux: zero without gradient, no transfer out of an empty donor or
   into a full receiver, sum_p F^alpha_p = 0, m_p = rho_p alpha_p carried
-  consistently, uniform u and P carried exactly;
+  consistently, uniform u and P carried exactly, the cap at k_f |G|;
 * the PF step: periodic totals conserved, sum alpha = 1, bounds, uniform u
   and P preserved, an absent phase stays zero and N = 3 with an absent
   phase reproduces N = 2 bitwise.
@@ -119,9 +119,9 @@ def test_q_equation_prefix_sum_1d(oracle):
         r, _ = pb.pf_divj(U, w.dx[0])
         G, res = pb.pf_gradients(U, r)
         assert (res <= 1e-12).all()
-        a = w.U.reshape(w.nU, -1)[-N:]
+        K = pb.pf_k(U)
         for p in range(N):
-            k = a[p] * (1 - a[p])
+            k = K[p]
             kf = 0.5 * (k[:-1] + k[1:])
             J = w.dx[0] * np.cumsum(r[p])[:-1]
             Jd = kf * G[0, p, :-1]
@@ -154,9 +154,9 @@ def test_q_equation_2d_reduces_to_1d(oracle):
     assert np.abs(r2.reshape(N, ny, n) - r1[:, None, :]).max() <= 1e-12 * np.abs(r1).max()
     G2, res = pb2.pf_gradients(U2.reshape(-1), r2)
     G2 = G2.reshape(2, N, ny, n)
-    a = U1[-N:]
+    K = pb1.pf_k(U1.reshape(-1))
     for p in range(N):
-        k = a[p] * (1 - a[p])
+        k = K[p]
         kf = np.append(0.5 * (k[:-1] + k[1:]), 0.0)
         J1 = kf * G1[0, p]
         J2 = kf[None, :] * G2[0, p]
@@ -212,6 +212,12 @@ def test_pf_flux_pins(oracle):
         E = Fm.sum() * 0.5 * u * u + (Fa * (A * P + B)).sum()
         assert F[N + 1] == pytest.approx(E, abs=1e-12 * sc * (A * P + B).max())
         assert (pb.pf_flux(VL, VR, np.zeros(N)) == 0).all()
+        # the cap: no volume flux beyond k_f |G| of Eq. (4)
+        kf = rng.uniform(0, 0.05, N)
+        Fc = pb.pf_flux(VL, VR, G, kf)
+        S = (np.abs(G) * kf).sum()
+        for p in range(N):
+            assert abs(Fc[N + 2 + p]) <= abs(G[p]) * kf[p] + S * 1.01 + 1e-300
     # an empty donor gives nothing, a full receiver takes nothing
     aL = np.array([1.0, 0.0, 0.0])
     aR = np.array([0.0, 1.0, 0.0])
