@@ -55,7 +55,7 @@ typedef enum {
   MP_ERR_OOM = -3,          /* device allocation failed                     */
   MP_ERR_INADMISSIBLE = -4, /* a state left the admissible set (Eq. (8))    */
   MP_ERR_NONFINITE = -5,    /* a state holds NaN or Inf                     */
-  MP_ERR_SOLVER = -6,       /* reserved: iterative solver did not converge  */
+  MP_ERR_SOLVER = -6,       /* the solve of Eq. (4) did not converge        */
   MP_ERR_UNSUPPORTED = -7   /* valid but not built (e.g. N above the build) */
 } mp_status;
 
@@ -90,11 +90,13 @@ typedef struct {
   int32_t model;           /* MP_MODEL_ALLAIRE (K_p = 0) or _KAPILA (Sec. 2.1)*/
   int32_t precision;       /* MP_PREC_FP64 or MP_PREC_MIXED                  */
   int32_t energy_limiter;  /* 1: apply Eq. (21) (default); 0: skip it       */
-  int32_t phase_field;     /* must be 0 (the Phase-Field step is not built)  */
+  int32_t phase_field;     /* 1: each step ends with the Phase-Field step of
+                              Sec. 2.2.1 (Eqs. (4), (5), (28)); 0: off       */
   double cfl;              /* CFL number of the time step (> 0)              */
-  double eta_over_dx;      /* reserved (Phase-Field interface thickness)     */
-  double cg_rtol;          /* reserved                                       */
-  int32_t cg_maxit;        /* reserved                                       */
+  double eta_over_dx;      /* eta / min_d dx_d of Eq. (28) (> 0; 1 in Sec. 4) */
+  double cg_rtol;          /* Eq. (4) solve: stop at ||res|| <= cg_rtol ||[div J]||
+                              (<= 0: 1e-12)                                  */
+  int32_t cg_maxit;        /* iteration limit of that solve (<= 0: 10000)    */
   int32_t check_bounds;    /* 1: mp_weno_step checks the result (see below)  */
   int32_t use_graph;       /* 1: replay mp_weno_step as a captured HIP graph */
 } mp_weno_opts;
@@ -111,9 +113,12 @@ int32_t mp_weno_max_phases(void);
  * hipStream_t (NULL: the null stream; not allowed with use_graph, which
  * captures on the stream); every later call is ordered on it.
  * Allocates the scratch: two RK stage buffers and one direction accumulator
- * per instance (3 n_U doubles per cell) plus small reduction buffers.
- * Errors: MP_ERR_ARG (bad sizes, gamma <= 1, dx <= 0, ...), MP_ERR_UNSUPPORTED
- * (N or ndim beyond the build, phase_field != 0), MP_ERR_OOM, MP_ERR_HIP.
+ * per instance (3 n_U doubles per cell) plus small reduction buffers; with
+ * phase_field, (6 + d) N doubles per cell more (k_p, [div J_p], Q_p, three CG
+ * vectors and the face gradients).
+ * Errors: MP_ERR_ARG (bad sizes, gamma <= 1, dx <= 0, phase_field with
+ * eta_over_dx <= 0, ...), MP_ERR_UNSUPPORTED (N or ndim beyond the build),
+ * MP_ERR_OOM, MP_ERR_HIP.
  * On error *ctx is NULL. */
 mp_status mp_weno_init(mp_weno_ctx **ctx, int32_t n_inst,
                        const mp_weno_instance *inst, const mp_weno_opts *opt,
@@ -126,6 +131,28 @@ mp_status mp_weno_init(mp_weno_ctx **ctx, int32_t n_inst,
  * context's stream.  This is the parity entry point. */
 mp_status mp_weno_rhs(mp_weno_ctx *ctx, const double *const *U_in,
                       double *const *dUdt);
+
+/* The Phase-Field fields of Sec. 2.2.1 for every instance, from the volume
+ * fractions of U_in (host array of n_inst device pointers; NULL or a NULL
+ * entry: the instance's U) taken as the order parameters phi_p:
+ *   divj[i]: [div J_p] of Eq. (28), N fields [p][cells] (second-order
+ *            Laplacian, mid-point integrals, M = eta max|u| / 2, multipliers
+ *            over the present phases);
+ *   grad[i]: the face gradients dQ_p/dx_d of the solution of Eq. (4), d N
+ *            fields [d][p][cells], at the upper face of each cell (0 at an
+ *            outflow end, across faces where phi(1 - phi) vanishes on both
+ *            sides, and for a phase with [div J_p] = 0);
+ *   dUdt[i]: the Phase-Field operator of Eq. (5), div F^PF, with those
+ *            gradients and the WENO-C/CL face states of U_in (U layout).
+ * Any of divj, grad, dUdt may be NULL (not computed); a non-NULL dUdt must
+ * hold n_inst non-NULL pointers.  The solve of Eq. (4) starts from Q = 0.
+ * Needs phase_field = 1 (else MP_ERR_UNSUPPORTED); synchronises the stream
+ * (the solve is driven from the host); MP_ERR_SOLVER if the solve did not
+ * reach cg_rtol within cg_maxit iterations.  The parity entry point of the
+ * Phase-Field step. */
+mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
+                            double *const *divj, double *const *grad,
+                            double *const *dUdt);
 
 /* CFL time step per instance: dt = cfl / max_cells sum_d (|u_d| + c)/dx_d,
  * clipped so that t + dt <= t_end (t is the instance's time, advanced by
@@ -141,7 +168,15 @@ mp_status mp_weno_dt(mp_weno_ctx *ctx, double *dt, int32_t where);
  * except with check_bounds = 1: then the call synchronises, checks the new
  * states for non-finite values (MP_ERR_NONFINITE) and for violations of the
  * bounds of Eq. (8) (MP_ERR_INADMISSIBLE); on either error every U is
- * restored to its value before the step and the time is not advanced. */
+ * restored to its value before the step and the time is not advanced.
+ * With phase_field = 1 the hyperbolic step is followed by the Phase-Field
+ * step (Sec. 2.2.1) with the same dt: [div J] and Eq. (4) on the hyperbolic
+ * result (the solve starts from the previous step's Q), then SSP-RK3 of
+ * Eq. (5) with the gradients frozen.  That step synchronises the stream (its
+ * solve is driven from the host) and is never replayed from a graph.
+ * MP_ERR_SOLVER: the solve did not converge; U then holds the hyperbolic
+ * result (restored to the state before the step with check_bounds = 1) and
+ * the time is not advanced. */
 mp_status mp_weno_step(mp_weno_ctx *ctx, const double *dt_dev);
 
 /* Diagnostics per instance, MP_DIAG_LEN doubles each (out[i*MP_DIAG_LEN+k]):
@@ -151,6 +186,8 @@ mp_status mp_weno_step(mp_weno_ctx *ctx, const double *dt_dev);
  *   k = 24         : min over cells of psi(U) (Eq. (9))
  *   k = 25         : number of non-finite entries
  *   k = 26, 27     : instance time t and number of steps taken
+ *   k = 29, 30     : Phase-Field step: CG iterations and relative residual
+ *                    of the last solve of Eq. (4) (0 when it is off)
  * where = MP_WHERE_HOST (synchronises) or MP_WHERE_DEVICE. */
 mp_status mp_weno_diag(mp_weno_ctx *ctx, double *out, int32_t where);
 

@@ -67,6 +67,9 @@ def lib():
         L.mp_weno_init.restype = C.c_int
         L.mp_weno_rhs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp)]
         L.mp_weno_rhs.restype = C.c_int
+        L.mp_weno_pf_fields.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                        C.POINTER(vp)]
+        L.mp_weno_pf_fields.restype = C.c_int
         L.mp_weno_dt.argtypes = [vp, vp, C.c_int32]
         L.mp_weno_dt.restype = C.c_int
         L.mp_weno_step.argtypes = [vp, vp]
@@ -91,7 +94,8 @@ def lib():
 
 
 EXPORTED = ["mp_weno_abi_version", "mp_weno_max_phases", "mp_weno_init",
-            "mp_weno_rhs", "mp_weno_dt", "mp_weno_step", "mp_weno_diag",
+            "mp_weno_rhs", "mp_weno_pf_fields", "mp_weno_dt", "mp_weno_step",
+            "mp_weno_diag",
             "mp_weno_set_time", "mp_weno_destroy", "mp_weno_strerror",
             "mp_weno_last_error", "mp_weno_profile", "mp_weno_timing"]
 
@@ -126,7 +130,7 @@ def make_opts(o, check_bounds=False, use_graph=False):
     x.phase_field = int(o.phase_field)
     x.cfl = float(o.cfl)
     x.eta_over_dx = float(o.eta_over_dx)
-    x.cg_rtol, x.cg_maxit = 1e-12, 1000
+    x.cg_rtol, x.cg_maxit = float(o.cg_rtol), int(o.cg_maxit)
     x.check_bounds, x.use_graph = int(check_bounds), int(use_graph)
     return x
 
@@ -191,6 +195,31 @@ class Solver:
         self._check(lib().mp_weno_rhs(self.ctx, ins, ptrs))
         self._leave()
         return outs
+
+    def pf_fields(self, U_in=None, divj=True, grad=True, dudt=True):
+        """Phase-Field fields per instance from the volume fractions of U_in
+        (default: the instances' states): dict of lists of torch tensors
+        'divj' (N, cells), 'grad' (d, N, cells), 'dudt' (U layout)."""
+        torch = self.torch
+        n = len(self.U)
+        out = {}
+        arrs = {}
+        for key, on, shape in (("divj", divj, lambda w: (w.N, w.ncells)),
+                               ("grad", grad, lambda w: (w.ndim, w.N, w.ncells)),
+                               ("dudt", dudt, None)):
+            if on:
+                out[key] = [torch.empty(shape(w), dtype=torch.float64, device=self.device)
+                            if shape else torch.empty_like(u) for w, u in zip(self.w, self.U)]
+                arrs[key] = (C.c_void_p * n)(*[C.c_void_p(t.data_ptr()) for t in out[key]])
+            else:
+                arrs[key] = None
+        ins = (C.c_void_p * n)(*[C.c_void_p((U_in[i] if U_in else self.U[i]).data_ptr())
+                                 for i in range(n)])
+        self._enter()
+        self._check(lib().mp_weno_pf_fields(self.ctx, ins, arrs["divj"], arrs["grad"],
+                                            arrs["dudt"]))
+        self._leave()
+        return out
 
     def dt(self):
         out = np.zeros(len(self.U))

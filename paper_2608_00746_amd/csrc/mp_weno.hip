@@ -42,6 +42,22 @@ constexpr int kMaxN = 5;          // phases built
 constexpr int kBX = 256;          // lanes of the x sweep (254 output cells)
 constexpr int kRedBlock = 256;    // reduction workgroup
 constexpr int kDiagSlots = 32;    // per-block partials of the diagnostics
+constexpr int kPartSlots = 40;    // stride of the per-chunk partials
+// per-instance Phase-Field scalars (offsets into Desc::pfs): mobility,
+// M / eta^2, multipliers B_q, CG iterations and relative residual at exit,
+// and per phase ||b||^2, res.z, alpha, beta, done flag, iterations
+constexpr int kPfsLen = 64;
+// floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
+// is solvable for every right side of zero total and stays conditioned; only
+// cells with phi or 1 - phi below ~1e-6 see it
+constexpr double kKFloor = 1e-6;
+// the Phase-Field step's own CFL bound: |G_d| dt / dx_d <= 1/12 (the
+// Gauss-Lobatto end weight); the solve's gradient is clipped there, which
+// only happens in nearly pure cells where the capped flux is negligible
+constexpr double kPfCfl = 1.0 / 12.0;
+constexpr int kPfsM = 0, kPfsMe2 = 1, kPfsB = 2, kPfsIts = 10, kPfsRes = 11,
+              kPfsBB = 16, kPfsRZ = 24, kPfsAlpha = 32, kPfsBeta = 40,
+              kPfsDone = 48, kPfsPits = 56;
 
 // The state pointers come from a table in device memory, so the compiler
 // cannot tell their address space and would emit flat loads and stores (which
@@ -76,6 +92,17 @@ struct Desc {
   double* steps;
   double* diag;              // MP_DIAG_LEN results
   double t_end, vol;
+  // Phase-Field step (null when it is off)
+  const double* pfin;        // state whose volume fractions are phi_p
+  double* pfs;               // per-instance scalars (kPfs* offsets)
+  double* pf_k;              // k_p = phi_p (1 - phi_p)            [N][cells]
+  double* pf_b;              // [div J_p] (right side of Eq. (4))  [N][cells]
+  double* pf_q;              // Q_p                                [N][cells]
+  double* pf_r;              // CG residual                        [N][cells]
+  double* pf_p;              // CG direction                       [N][cells]
+  double* pf_ap;             // K p                                [N][cells]
+  double* pf_g;              // dQ_p/dx_d at upper faces           [d][N][cells]
+  double eta;                // interface thickness parameter
 };
 
 // RK stage s of Shu and Osher's third-order scheme (s = 0, 1, 2), or the
@@ -181,7 +208,7 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
 // ---------------------------------------------------------------------------
 // x sweep
 // ---------------------------------------------------------------------------
-template <int N, int D, typename W>
+template <int N, int D, typename W, int PFM>
 __global__ __launch_bounds__(kBX) void k_sweep_x(const Desc* __restrict__ descs,
                                                  const int2* __restrict__ map,
                                                  int ninst, int stage, int swz) {
@@ -275,7 +302,23 @@ __global__ __launch_bounds__(kBX) void k_sweep_x(const Desc* __restrict__ descs,
     R.P = sface[2 * N + 2 * D + 1][r];
     R.rho = sface[2 * N + 2 * D + 2][r];
     R.c = sface[2 * N + 2 * D + 3][r];
-    riemann<N, D, W>(fp, R, 0, g.flux, F);
+    if constexpr (PFM) {
+      // gradient at face x_{xi+1/2}: face -1/2 is face n-1/2 when periodic
+      // and carries none at an outflow end
+      const int xo = xi < 0 ? (g.bcx0 == MP_BC_PERIODIC ? g.nx - 1 : -1) : (xi < g.nx ? xi : -1);
+      const int xq = xo < 0 ? -1 : (xo + 1 < g.nx ? xo + 1 : (g.bcx1 == MP_BC_PERIODIC ? 0 : -1));
+      double G[N], kf[N];
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        const bool in = xq >= 0;
+        G[p] = in ? gptr(d.pf_g)[(int64_t)p * nc + row + xo] : 0.0;
+        kf[p] = in ? 0.5 * (gptr(d.pf_k)[(int64_t)p * nc + row + xo] +
+                            gptr(d.pf_k)[(int64_t)p * nc + row + xq]) : 0.0;
+      }
+      pf_flux<N, D>(fp, R, G, kf, e, F);
+    } else {
+      riemann<N, D, W>(fp, R, 0, g.flux, F);
+    }
 #pragma unroll
     for (int c = 0; c < NU; ++c) sflux[c][l] = F.f[c];
     sflux[NU][l] = F.uh;
@@ -284,13 +327,18 @@ __global__ __launch_bounds__(kBX) void k_sweep_x(const Desc* __restrict__ descs,
 
   if (l >= 1 && l < kBX - 1 && xi < g.nx) {
     double L[NU];
-    double opk[N];
-    one_plus_k<N, D>(ub, e, g.model, opk);
+    if constexpr (PFM) {
 #pragma unroll
-    for (int c = 0; c < NU; ++c) L[c] = -(F.f[c] - sflux[c][l - 1]) * g.rdx;
-    const double du = (F.uh - sflux[NU][l - 1]) * g.rdx;
+      for (int c = 0; c < NU; ++c) L[c] = (F.f[c] - sflux[c][l - 1]) * g.rdx;
+    } else {
+      double opk[N];
+      one_plus_k<N, D>(ub, e, g.model, opk);
 #pragma unroll
-    for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
+      for (int c = 0; c < NU; ++c) L[c] = -(F.f[c] - sflux[c][l - 1]) * g.rdx;
+      const double du = (F.uh - sflux[NU][l - 1]) * g.rdx;
+#pragma unroll
+      for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
+    }
     const int64_t idx = row + xi;
     if constexpr (D == 1) {
       finish_cell<N, D>(a, nc, idx, ub, L);
@@ -314,7 +362,7 @@ constexpr int kTX = 16;
 constexpr int kTY = 16;
 constexpr int kOY = kTY - 2;      // output rows per tile
 
-template <int N, typename W>
+template <int N, typename W, int PFM>
 __global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map,
                                                        int ninst, int stage, int swz) {
@@ -408,7 +456,21 @@ __global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Desc* __restrict__ 
     R.P = sface[2 * N + 2 * D + 1][r][tx];
     R.rho = sface[2 * N + 2 * D + 2][r][tx];
     R.c = sface[2 * N + 2 * D + 3][r][tx];
-    riemann<N, D, W>(fp, R, 1, g.flux, F);
+    if constexpr (PFM) {
+      const int yo = yi < 0 ? (g.bcy0 == MP_BC_PERIODIC ? g.ny - 1 : -1) : (yi < g.ny ? yi : -1);
+      const int yq = yo < 0 ? -1 : (yo + 1 < g.ny ? yo + 1 : (g.bcy1 == MP_BC_PERIODIC ? 0 : -1));
+      double G[N], kf[N];
+#pragma unroll
+      for (int p = 0; p < N; ++p) {
+        const bool in = yq >= 0;
+        G[p] = in ? gptr(d.pf_g)[(int64_t)(N + p) * nc + (int64_t)yo * g.nx + xc] : 0.0;
+        kf[p] = in ? 0.5 * (gptr(d.pf_k)[(int64_t)p * nc + (int64_t)yo * g.nx + xc] +
+                            gptr(d.pf_k)[(int64_t)p * nc + (int64_t)yq * g.nx + xc]) : 0.0;
+      }
+      pf_flux<N, D>(fp, R, G, kf, e, F);
+    } else {
+      riemann<N, D, W>(fp, R, 1, g.flux, F);
+    }
 #pragma unroll
     for (int c = 0; c < NU; ++c) sflux[c][ty][tx] = F.f[c];
     sflux[NU][ty][tx] = F.uh;
@@ -418,14 +480,20 @@ __global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Desc* __restrict__ 
   if (ty >= 1 && ty < kTY - 1 && colok && yi < g.ny) {
     const int64_t idx = (int64_t)yi * g.nx + x;
     double L[NU];
-    double opk[N];
-    one_plus_k<N, D>(ub, e, g.model, opk);
+    if constexpr (PFM) {
 #pragma unroll
-    for (int c = 0; c < NU; ++c)
-      L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
-    const double du = (F.uh - sflux[NU][ty - 1][tx]) * g.rdy;
+      for (int c = 0; c < NU; ++c)
+        L[c] = a.acc[(int64_t)c * nc + idx] + (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
+    } else {
+      double opk[N];
+      one_plus_k<N, D>(ub, e, g.model, opk);
 #pragma unroll
-    for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
+      for (int c = 0; c < NU; ++c)
+        L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
+      const double du = (F.uh - sflux[NU][ty - 1][tx]) * g.rdy;
+#pragma unroll
+      for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
+    }
     finish_cell<N, D>(a, nc, idx, ub, L);
   }
 }
@@ -570,7 +638,7 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kDiagSlots + k] = sh[0];
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + k] = sh[0];
     __syncthreads();
   }
 }
@@ -587,7 +655,7 @@ __global__ void k_diag_finish(const Desc* __restrict__ descs, const int* __restr
   else if (k == 23) r = -INFINITY;
   else r = 0.0;
   for (int b = start[blockIdx.x]; b < start[blockIdx.x + 1]; ++b) {
-    const double x = part[(int64_t)b * kDiagSlots + k];
+    const double x = part[(int64_t)b * kPartSlots + k];
     if (k == 21 || k == 22 || k == 24) r = fmin(r, x);
     else if (k == 20 || k == 23 || k == 28) r = fmax(r, x);
     else r = r + x;
@@ -595,7 +663,540 @@ __global__ void k_diag_finish(const Desc* __restrict__ descs, const int* __restr
   if (k < 20) r *= d.vol;
   if (k == 26) r = *gptr(d.t);
   if (k == 27) r = *gptr(d.steps);
+  if (k == 29) r = d.pfs ? gptr(d.pfs)[kPfsIts] : 0.0;
+  if (k == 30) r = d.pfs ? gptr(d.pfs)[kPfsRes] : 0.0;
   gptr(d.diag)[k] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Phase-Field step (Sec. 2.2.1, Eqs. (4)-(5); Sec. 4, Eq. (28))
+// ---------------------------------------------------------------------------
+// With phi_p = alpha_p of the hyperbolic result:
+//   [div J_p] = M lap(phi_p) - (M/eta^2)(g'(phi_p) - phi_p sum_q g'(phi_q))
+//               + sum_q W_pq B_q,        M = eta max|u| / 2,
+// where B solves the integral system of Eq. (28) over the present phases
+// (B of the last present phase = 0: the system is singular and L^c does not
+// depend on that choice).  Eq. (4) is solved for Q_p by Jacobi-preconditioned
+// conjugate gradients on K Q = -[div J], with
+//   (K Q)_i = sum over faces of k_f (Q_i - Q_j) / dx^2,  k_f = (k_i + k_j)/2,
+// k = phi (1 - phi), faces across periodic ends only.  The solve starts from
+// the previous step's Q and stops at ||res|| <= rtol ||div J||.  The face
+// gradients are frozen and the PF flux is advanced by SSP-RK3 with the
+// WENO-C face states of the sweeps.  All reductions are two-level with a
+// fixed order.
+
+__device__ __forceinline__ double gprime(double f) {
+  return 2.0 * f * (1.0 - f) * (1.0 - 2.0 * f);
+}
+
+// fixed-order tree over the workgroup (256 lanes); op 0 sum, 1 max
+__device__ __forceinline__ double block_reduce(double v, double* sh, int op) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double x = sh[threadIdx.x], y = sh[threadIdx.x + s];
+      sh[threadIdx.x] = op ? fmax(x, y) : x + y;
+    }
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// sum (or max) of slot k of an instance's chunk partials, fixed order
+__device__ __forceinline__ double reduce_chunks(const double* __restrict__ part, int b0, int b1,
+                                                int k, double* sh, int op) {
+  double v = 0.0;
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += kRedBlock) {
+    const double x = part[(int64_t)b * kPartSlots + k];
+    v = op ? fmax(v, x) : v + x;
+  }
+  return block_reduce(v, sh, op);
+}
+
+// neighbour of cell (x, y) one step along dir (+1 / -1); -1 if no face there
+__device__ __forceinline__ int64_t nbr(const Grid& g, int D, int x, int y, int dir, int s) {
+  if (dir == 0) {
+    int xn = x + s;
+    if (xn < 0) { if (g.bcx0 != MP_BC_PERIODIC) return -1; xn += g.nx; }
+    if (xn >= g.nx) { if (g.bcx1 != MP_BC_PERIODIC) return -1; xn -= g.nx; }
+    return (int64_t)y * g.nx + xn;
+  }
+  (void)D;
+  int yn = y + s;
+  if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += g.ny; }
+  if (yn >= g.ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= g.ny; }
+  return (int64_t)yn * g.nx + x;
+}
+
+// (K v)_i and the Jacobi diagonal for phase p at cell i
+template <int D>
+__device__ __forceinline__ void k_apply(const Grid& g, const gdouble* __restrict__ k,
+                                        const gdouble* __restrict__ v, int64_t i, int x, int y,
+                                        double& Kv, double& diag) {
+  Kv = 0.0;
+  diag = 0.0;
+  const double ki = k[i], vi = v[i];
+#pragma unroll
+  for (int dir = 0; dir < D; ++dir) {
+    const double r2 = dir == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
+#pragma unroll
+    for (int s = -1; s <= 1; s += 2) {
+      const int64_t j = nbr(g, D, x, y, dir, s);
+      if (j >= 0) {
+        const double kf = 0.5 * (ki + k[j]) * r2;
+        Kv += kf * (vi - v[j]);
+        diag += kf;
+      }
+    }
+  }
+}
+
+// pass 1: k_p, max |u|, and the integrands of Eq. (28)'s multiplier system
+//   slots: [0] max|u|, [1 + p N + q] W_pq, [1 + N^2 + p] (g'_p - phi_p sum g'),
+//          [1 + N^2 + N + p] phi_p
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_prep(const Desc* __restrict__ descs,
+                                                       const int2* __restrict__ map, int ninst,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  constexpr int NS = 1 + N * N + 2 * N;
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const int64_t nc = d.g.nc;
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  const gdouble* U = gptr(d.pfin);
+  gdouble* K = gptr(d.pf_k);
+  double acc[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+    double phi[N], rho = 0.0, sg = 0.0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      phi[p] = U[(int64_t)(N + D + 1 + p) * nc + i];
+      rho += U[(int64_t)p * nc + i];
+      sg += gprime(phi[p]);
+      K[(int64_t)p * nc + i] = fmax(phi[p] * (1.0 - phi[p]), kKFloor);
+    }
+    double u2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double u = U[(int64_t)(N + k) * nc + i] / rho;
+      u2 += u * u;
+    }
+    acc[0] = fmax(acc[0], sqrt(u2));
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        acc[1 + p * N + q] += p == q ? phi[p] * (1.0 - phi[q]) : -phi[p] * phi[q];
+      acc[1 + N * N + p] += gprime(phi[p]) - phi[p] * sg;
+      acc[1 + N * N + N + p] += phi[p];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double r = block_reduce(acc[k], sh, k == 0 ? 1 : 0);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + k] = r;
+  }
+}
+
+// one workgroup per instance: M, and B from the reduced multiplier system
+template <int N>
+__global__ __launch_bounds__(kRedBlock) void k_pf_setup(const Desc* __restrict__ descs,
+                                                        const int* __restrict__ start,
+                                                        const double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  __shared__ double red[1 + N * N + 2 * N];
+  const Desc& d = descs[blockIdx.x];
+  const int b0 = start[blockIdx.x], b1 = start[blockIdx.x + 1];
+  for (int k = 0; k < 1 + N * N + 2 * N; ++k) {
+    const double r = reduce_chunks(part, b0, b1, k, sh, k == 0 ? 1 : 0);
+    if (threadIdx.x == 0) red[k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  gdouble* s = gptr(d.pfs);
+  const double M = 0.5 * d.eta * red[0];
+  const double Me2 = M / (d.eta * d.eta);
+  double B[N];
+  int pres[N], np = 0;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    B[p] = 0.0;
+    if (red[1 + N * N + N + p] > 0.0) pres[np++] = p;
+  }
+  if (np > 1) {
+    const int n = np - 1;
+    double A[N][N], b[N];
+    for (int r = 0; r < n; ++r) {
+      for (int c = 0; c < n; ++c) A[r][c] = red[1 + pres[r] * N + pres[c]] * d.vol;
+      b[r] = Me2 * (red[1 + N * N + pres[r]] * d.vol);
+    }
+    bool ok = true;
+    for (int k = 0; k < n && ok; ++k) {           // partial pivoting
+      int pv = k;
+      for (int r = k + 1; r < n; ++r)
+        if (fabs(A[r][k]) > fabs(A[pv][k])) pv = r;
+      if (A[pv][k] == 0.0) { ok = false; break; }
+      if (pv != k) {
+        for (int c = 0; c < n; ++c) { const double t = A[k][c]; A[k][c] = A[pv][c]; A[pv][c] = t; }
+        const double t = b[k]; b[k] = b[pv]; b[pv] = t;
+      }
+      for (int r = k + 1; r < n; ++r) {
+        const double f = A[r][k] / A[k][k];
+        for (int c = k; c < n; ++c) A[r][c] -= f * A[k][c];
+        b[r] -= f * b[k];
+      }
+    }
+    if (ok) {
+      for (int k = n - 1; k >= 0; --k) {
+        double v = b[k];
+        for (int c = k + 1; c < n; ++c) v -= A[k][c] * b[c];
+        b[k] = v / A[k][k];
+      }
+      for (int r = 0; r < n; ++r) B[pres[r]] = b[r];
+    }
+  }
+  s[kPfsM] = M;
+  s[kPfsMe2] = Me2;
+#pragma unroll
+  for (int p = 0; p < N; ++p) s[kPfsB + p] = B[p];
+}
+
+// [div J_p] at every cell; start of the CG solve (residual of the warm start,
+// Jacobi direction) with partials [p] ||b||^2, [N + p] res.z, [2N + p] ||res||^2
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ descs,
+                                                       const int2* __restrict__ map, int ninst,
+                                                       double* __restrict__ part, int cold) {
+  __shared__ double sh[kRedBlock];
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const Grid& g = d.g;
+  const int64_t nc = g.nc;
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  const gdouble* U = gptr(d.pfin);
+  const gdouble* K = gptr(d.pf_k);
+  const gdouble* s = gptr(d.pfs);
+  const double M = s[kPfsM], Me2 = s[kPfsMe2];
+  double B[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) B[p] = s[kPfsB + p];
+  double acc[3 * N];
+#pragma unroll
+  for (int k = 0; k < 3 * N; ++k) acc[k] = 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+    double phi[N], sg = 0.0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      phi[p] = U[(int64_t)(N + D + 1 + p) * nc + i];
+      sg += gprime(phi[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      const gdouble* f = U + (int64_t)(N + D + 1 + p) * nc;
+      double lap = 0.0;
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        const int64_t lo = nbr(g, D, x, y, dir, -1), hi = nbr(g, D, x, y, dir, 1);
+        const double fl = lo >= 0 ? f[lo] : phi[p];    // outflow: zero gradient
+        const double fh = hi >= 0 ? f[hi] : phi[p];
+        const double r2 = dir == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
+        lap += (fh - 2.0 * phi[p] + fl) * r2;
+      }
+      double Lc = 0.0;
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        Lc += (p == q ? phi[p] * (1.0 - phi[q]) : -phi[p] * phi[q]) * B[q];
+      const double b = M * lap - Me2 * (gprime(phi[p]) - phi[p] * sg) + Lc;
+      const int64_t ip = (int64_t)p * nc + i;
+      gptr(d.pf_b)[ip] = b;
+      // K Q = -b from the previous Q (or 0)
+      double Kq = 0.0, dg = 0.0;
+      if (cold) {
+        double dummy;
+        gptr(d.pf_q)[ip] = 0.0;
+        k_apply<D>(g, K + (int64_t)p * nc, K + (int64_t)p * nc, i, x, y, dummy, dg);
+      } else {
+        k_apply<D>(g, K + (int64_t)p * nc, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, dg);
+      }
+      const double res = -b - Kq;
+      const double z = dg > 0.0 ? res / dg : 0.0;
+      gptr(d.pf_r)[ip] = res;
+      gptr(d.pf_p)[ip] = z;
+      acc[p] += b * b;
+      acc[N + p] += res * z;
+      acc[2 * N + p] += res * res;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3 * N; ++k) {
+    const double r = block_reduce(acc[k], sh, 0);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + k] = r;
+  }
+}
+
+// one workgroup per instance: ||b||, first res.z, convergence of the start
+template <int N>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_start(const Desc* __restrict__ descs,
+                                                           const int* __restrict__ start,
+                                                           const double* __restrict__ part,
+                                                           double rtol) {
+  __shared__ double sh[kRedBlock];
+  __shared__ double red[3 * N];
+  const Desc& d = descs[blockIdx.x];
+  for (int k = 0; k < 3 * N; ++k) {
+    const double r = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], k, sh, 0);
+    if (threadIdx.x == 0) red[k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  gdouble* s = gptr(d.pfs);
+  double res = 0.0;
+  for (int p = 0; p < N; ++p) {
+    const double bb = red[p], rr = red[2 * N + p];
+    s[kPfsBB + p] = bb;
+    s[kPfsRZ + p] = red[N + p];
+    const bool done = bb == 0.0 || sqrt(rr) <= rtol * sqrt(bb);
+    s[kPfsDone + p] = done ? 1.0 : 0.0;
+    s[kPfsPits + p] = 0.0;
+    if (bb > 0.0) res = fmax(res, sqrt(rr / bb));
+  }
+  s[kPfsIts] = 0.0;
+  s[kPfsRes] = res;
+}
+
+// CG step 1: Ap = K p, partials [p] p.Ap
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_ap(const Desc* __restrict__ descs,
+                                                        const int2* __restrict__ map, int ninst,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const Grid& g = d.g;
+  const int64_t nc = g.nc;
+  const gdouble* s = gptr(d.pfs);
+  bool live[N];
+  bool any = false;
+#pragma unroll
+  for (int p = 0; p < N; ++p) { live[p] = s[kPfsDone + p] == 0.0; any = any || live[p]; }
+  if (!any) return;                       // uniform over the workgroup
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  double acc[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) acc[p] = 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      if (!live[p]) continue;
+      double Kp, dg;
+      const gdouble* pp = gptr(d.pf_p) + (int64_t)p * nc;
+      k_apply<D>(g, gptr(d.pf_k) + (int64_t)p * nc, pp, i, x, y, Kp, dg);
+      gptr(d.pf_ap)[(int64_t)p * nc + i] = Kp;
+      acc[p] += pp[i] * Kp;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    if (!live[p]) continue;
+    const double r = block_reduce(acc[p], sh, 0);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + p] = r;
+  }
+}
+
+// CG step 2 (one workgroup per instance): alpha = res.z / p.Ap
+template <int N>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_alpha(const Desc* __restrict__ descs,
+                                                           const int* __restrict__ start,
+                                                           const double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  const Desc& d = descs[blockIdx.x];
+  gdouble* s = gptr(d.pfs);
+  for (int p = 0; p < N; ++p) {
+    if (s[kPfsDone + p] != 0.0) continue;
+    const double pap = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
+    if (threadIdx.x == 0) {
+      if (pap > 0.0) {
+        s[kPfsAlpha + p] = s[kPfsRZ + p] / pap;
+      } else {                             // breakdown: nothing left to solve
+        s[kPfsAlpha + p] = 0.0;
+        s[kPfsDone + p] = 1.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// CG step 3: Q += alpha p, res -= alpha Ap, z = res / diag;
+// partials [p] res.z, [N + p] ||res||^2
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_update(const Desc* __restrict__ descs,
+                                                            const int2* __restrict__ map,
+                                                            int ninst, double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const Grid& g = d.g;
+  const int64_t nc = g.nc;
+  const gdouble* s = gptr(d.pfs);
+  bool live[N];
+  double al[N];
+  bool any = false;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    live[p] = s[kPfsDone + p] == 0.0;
+    al[p] = s[kPfsAlpha + p];
+    any = any || live[p];
+  }
+  if (!any) return;
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  double acc[2 * N];
+#pragma unroll
+  for (int k = 0; k < 2 * N; ++k) acc[k] = 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      if (!live[p]) continue;
+      const int64_t ip = (int64_t)p * nc + i;
+      gptr(d.pf_q)[ip] += al[p] * gptr(d.pf_p)[ip];
+      const double res = gptr(d.pf_r)[ip] - al[p] * gptr(d.pf_ap)[ip];
+      gptr(d.pf_r)[ip] = res;
+      double dummy, dg;
+      const gdouble* K = gptr(d.pf_k) + (int64_t)p * nc;
+      k_apply<D>(g, K, K, i, x, y, dummy, dg);
+      const double z = dg > 0.0 ? res / dg : 0.0;
+      acc[p] += res * z;
+      acc[N + p] += res * res;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    if (!live[p]) continue;
+    double r = block_reduce(acc[p], sh, 0);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + p] = r;
+    r = block_reduce(acc[N + p], sh, 0);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + N + p] = r;
+  }
+}
+
+// CG step 4 (one workgroup per instance): convergence test and beta
+template <int N>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict__ descs,
+                                                          const int* __restrict__ start,
+                                                          const double* __restrict__ part,
+                                                          double rtol) {
+  __shared__ double sh[kRedBlock];
+  const Desc& d = descs[blockIdx.x];
+  gdouble* s = gptr(d.pfs);
+  double its = s[kPfsIts], rmax = 0.0;
+  bool stepped = false;
+  for (int p = 0; p < N; ++p) {
+    if (s[kPfsDone + p] != 0.0) continue;
+    const double rz = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
+    const double rr = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], N + p, sh, 0);
+    stepped = true;
+    if (threadIdx.x == 0) {
+      const double bb = s[kPfsBB + p];
+      s[kPfsBeta + p] = s[kPfsRZ + p] > 0.0 ? rz / s[kPfsRZ + p] : 0.0;
+      s[kPfsRZ + p] = rz;
+      s[kPfsPits + p] += 1.0;
+      its = fmax(its, s[kPfsPits + p]);
+      rmax = fmax(rmax, sqrt(rr / bb));
+      if (sqrt(rr) <= rtol * sqrt(bb)) s[kPfsDone + p] = 1.0;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && stepped) {
+    s[kPfsIts] = its;
+    s[kPfsRes] = rmax;
+  }
+}
+
+// CG step 5: p = z + beta p
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_dir(const Desc* __restrict__ descs,
+                                                         const int2* __restrict__ map, int ninst) {
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const Grid& g = d.g;
+  const int64_t nc = g.nc;
+  const gdouble* s = gptr(d.pfs);
+  bool live[N];
+  double be[N];
+  bool any = false;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    live[p] = s[kPfsDone + p] == 0.0;
+    be[p] = s[kPfsBeta + p];
+    any = any || live[p];
+  }
+  if (!any) return;
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      if (!live[p]) continue;
+      const int64_t ip = (int64_t)p * nc + i;
+      double dummy, dg;
+      const gdouble* K = gptr(d.pf_k) + (int64_t)p * nc;
+      k_apply<D>(g, K, K, i, x, y, dummy, dg);
+      const double z = dg > 0.0 ? gptr(d.pf_r)[ip] / dg : 0.0;
+      gptr(d.pf_p)[ip] = z + be[p] * gptr(d.pf_p)[ip];
+    }
+  }
+}
+
+// frozen face gradients dQ_p/dx_d at the upper face of every cell: none at an
+// outflow end or for a phase with [div J] = 0 everywhere; clip != 0: limited
+// to the Phase-Field CFL bound of the step's dt
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_grad(const Desc* __restrict__ descs,
+                                                       const int2* __restrict__ map, int ninst,
+                                                       int clip) {
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const Grid& g = d.g;
+  const int64_t nc = g.nc;
+  const gdouble* s = gptr(d.pfs);
+  const int64_t c0 = (int64_t)it.y * kRedChunk;
+  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  const double dt = clip ? *gptr(d.dt) : 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      const gdouble* Q = gptr(d.pf_q) + (int64_t)p * nc;
+      const bool on = s[kPfsBB + p] > 0.0;
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        const int64_t j = nbr(g, D, x, y, dir, 1);
+        double G = 0.0;
+        if (on && j >= 0) {
+          const double rd = dir == 0 ? g.rdx : g.rdy;
+          G = (Q[j] - Q[i]) * rd;
+          if (clip) {
+            const double gm = kPfCfl / (dt * rd);
+            G = fmin(fmax(G, -gm), gm);
+          }
+        }
+        gptr(d.pf_g)[(int64_t)(dir * N + p) * nc + i] = G;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -609,6 +1210,8 @@ struct Inst {
   double* U2 = nullptr;
   double* acc = nullptr;
   double* backup = nullptr;
+  double* pf = nullptr;            // Phase-Field work arrays (one allocation)
+  double* pfs = nullptr;           // Phase-Field scalars (kPfsLen)
 };
 
 // Instances of one (N, d): device descriptor table and tile offsets.
@@ -633,19 +1236,47 @@ struct Bracket {
 
 using StageFn = void (*)(const Group&, int stage, int swz, hipStream_t);
 using RedFn = void (*)(const Group&, double* part, hipStream_t);
+// Phase-Field kernels: per-cell passes over reduction chunks and per-instance
+// finishers (rtol is used by the finishers that test convergence)
+using PfFn = void (*)(const Group&, double* part, int flag, double rtol, hipStream_t);
 
-template <int N, int D, typename W>
+template <int N, int D, typename W, int PFM>
 void launch_x(const Group& G, int stage, int swz, hipStream_t s) {
   const int n = (int)G.ids.size();
-  hipLaunchKernelGGL((k_sweep_x<N, D, W>), dim3(G.xs[n]), dim3(kBX), 0, s, G.desc,
+  hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM>), dim3(G.xs[n]), dim3(kBX), 0, s, G.desc,
                      G.xmap, n, stage, swz);
 }
 
-template <int N, typename W>
+template <int N, typename W, int PFM>
 void launch_y(const Group& G, int stage, int swz, hipStream_t s) {
   const int n = (int)G.ids.size();
-  hipLaunchKernelGGL((k_sweep_y<N, W>), dim3(G.ys[n]), dim3(kTX * kTY), 0, s, G.desc,
+  hipLaunchKernelGGL((k_sweep_y<N, W, PFM>), dim3(G.ys[n]), dim3(kTX * kTY), 0, s, G.desc,
                      G.ymap, n, stage, swz);
+}
+
+// kind: 0 prep, 1 divJ + CG start, 2 K p, 3 update, 4 direction, 5 gradients
+template <int N, int D, int KIND>
+void launch_pf_cells(const Group& G, double* part, int flag, double, hipStream_t s) {
+  const int n = (int)G.ids.size();
+  double* pt = part + G.part_off * kPartSlots;
+  const dim3 grid(G.rs[n]), blk(kRedBlock);
+  if constexpr (KIND == 0) hipLaunchKernelGGL((k_pf_prep<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
+  if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_divj<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt, flag);
+  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_ap<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
+  if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_update<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
+  if constexpr (KIND == 4) hipLaunchKernelGGL((k_pf_cg_dir<N, D>), grid, blk, 0, s, G.desc, G.rmap, n);
+  if constexpr (KIND == 5) hipLaunchKernelGGL((k_pf_grad<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, flag);
+}
+
+// kind: 0 setup (M, B), 1 CG start, 2 alpha, 3 beta
+template <int N, int KIND>
+void launch_pf_inst(const Group& G, double* part, int, double rtol, hipStream_t s) {
+  const double* pt = part + G.part_off * kPartSlots;
+  const dim3 grid((unsigned)G.ids.size()), blk(kRedBlock);
+  if constexpr (KIND == 0) hipLaunchKernelGGL((k_pf_setup<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
+  if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_cg_start<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
+  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_alpha<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
+  if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_beta<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
 }
 
 template <int N, int D>
@@ -659,24 +1290,48 @@ template <int N, int D>
 void launch_diag(const Group& G, double* part, hipStream_t s) {
   const int n = (int)G.ids.size();
   hipLaunchKernelGGL((k_diag<N, D>), dim3(G.rs[n]), dim3(kRedBlock), 0, s, G.desc, G.rmap,
-                     n, part + G.part_off * kDiagSlots);
+                     n, part + G.part_off * kPartSlots);
 }
 
 struct Table {
-  StageFn sx[kMaxN + 1][3][2] = {};
-  StageFn sy[kMaxN + 1][2] = {};
+  StageFn sx[2][kMaxN + 1][3][2] = {};     // [PF flux][N][d][precision]
+  StageFn sy[2][kMaxN + 1][2] = {};
   RedFn dt[kMaxN + 1][3] = {};
   RedFn diag[kMaxN + 1][3] = {};
+  PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
+  PfFn pfi[4][kMaxN + 1] = {};             // per-instance PF finishers
 };
+
+template <int N, int D>
+void fill_pf(Table& t) {
+  t.pfc[0][N][D] = launch_pf_cells<N, D, 0>;
+  t.pfc[1][N][D] = launch_pf_cells<N, D, 1>;
+  t.pfc[2][N][D] = launch_pf_cells<N, D, 2>;
+  t.pfc[3][N][D] = launch_pf_cells<N, D, 3>;
+  t.pfc[4][N][D] = launch_pf_cells<N, D, 4>;
+  t.pfc[5][N][D] = launch_pf_cells<N, D, 5>;
+}
 
 template <int N>
 void fill(Table& t) {
-  t.sx[N][1][0] = launch_x<N, 1, double>;
-  t.sx[N][1][1] = launch_x<N, 1, float>;
-  t.sx[N][2][0] = launch_x<N, 2, double>;
-  t.sx[N][2][1] = launch_x<N, 2, float>;
-  t.sy[N][0] = launch_y<N, double>;
-  t.sy[N][1] = launch_y<N, float>;
+  t.sx[0][N][1][0] = launch_x<N, 1, double, 0>;
+  t.sx[0][N][1][1] = launch_x<N, 1, float, 0>;
+  t.sx[0][N][2][0] = launch_x<N, 2, double, 0>;
+  t.sx[0][N][2][1] = launch_x<N, 2, float, 0>;
+  t.sy[0][N][0] = launch_y<N, double, 0>;
+  t.sy[0][N][1] = launch_y<N, float, 0>;
+  t.sx[1][N][1][0] = launch_x<N, 1, double, 1>;
+  t.sx[1][N][1][1] = launch_x<N, 1, float, 1>;
+  t.sx[1][N][2][0] = launch_x<N, 2, double, 1>;
+  t.sx[1][N][2][1] = launch_x<N, 2, float, 1>;
+  t.sy[1][N][0] = launch_y<N, double, 1>;
+  t.sy[1][N][1] = launch_y<N, float, 1>;
+  fill_pf<N, 1>(t);
+  fill_pf<N, 2>(t);
+  t.pfi[0][N] = launch_pf_inst<N, 0>;
+  t.pfi[1][N] = launch_pf_inst<N, 1>;
+  t.pfi[2][N] = launch_pf_inst<N, 2>;
+  t.pfi[3][N] = launch_pf_inst<N, 3>;
   t.dt[N][1] = launch_dt<N, 1>;
   t.dt[N][2] = launch_dt<N, 2>;
   t.diag[N][1] = launch_diag<N, 1>;
@@ -706,6 +1361,7 @@ struct mp_weno_ctx {
   double* steps = nullptr;    // n_inst
   double* part = nullptr;     // reduction partials (kDiagSlots per chunk)
   double* diag = nullptr;     // n_inst * MP_DIAG_LEN
+  double* pfs = nullptr;      // n_inst * kPfsLen Phase-Field scalars
   int swz = -1;               // XCD-aware tile order: 1 on, 0 off, -1 on for
                               // groups of several instances (measured: it
                               // keeps each small instance on one L2 and costs
@@ -744,20 +1400,21 @@ static mp_status fail(mp_weno_ctx* c, mp_status s, const std::string& msg) {
                                          hipGetErrorString(e_));              \
   } while (0)
 
-// one RK stage (s = 0, 1, 2) or L(U) (s = 3) of every group
-static mp_status enqueue_stage(mp_weno_ctx* c, int s) {
+// one RK stage (s = 0, 1, 2) or L(U) (s = 3) of every group; pf selects the
+// Phase-Field flux instead of the Riemann solver
+static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
   const Table& T = table();
   const int prec = c->opt.precision;
   Bracket br;
-  const Bracket* b = s < 3 ? c->next_bracket(br) : nullptr;
+  const Bracket* b = (s < 3 && !pf) ? c->next_bracket(br) : nullptr;
   const int w = b ? b->which : 0;
   if (w == 1 || w == 3) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
   auto swz = [c](const Group& G) { return c->swz < 0 ? (G.ids.size() > 1 ? 1 : 0) : c->swz; };
-  for (const Group& G : c->groups) T.sx[G.N][G.D][prec](G, s, swz(G), c->stream);
+  for (const Group& G : c->groups) T.sx[pf][G.N][G.D][prec](G, s, swz(G), c->stream);
   if (w == 1) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   if (w == 2) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
   for (const Group& G : c->groups)
-    if (G.D == 2) T.sy[G.N][prec](G, s, swz(G), c->stream);
+    if (G.D == 2) T.sy[pf][G.N][prec](G, s, swz(G), c->stream);
   if (w == 2 || w == 3) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -774,10 +1431,65 @@ static mp_status enqueue_dt(mp_weno_ctx* c) {
   return MP_OK;
 }
 
+// [div J], the Q solve and the frozen gradients of every instance, from the
+// volume fractions of each descriptor's pfin.  The CG loop is driven from the
+// host: batches of iterations, then a look at the per-phase done flags
+// (synchronises the stream).  cold: start from Q = 0 instead of the last Q.
+static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
+  const Table& T = table();
+  const double rtol = c->opt.cg_rtol > 0.0 ? c->opt.cg_rtol : 1e-12;
+  const int maxit = c->opt.cg_maxit > 0 ? c->opt.cg_maxit : 10000;
+  for (const Group& G : c->groups) {
+    T.pfc[0][G.N][G.D](G, c->part, 0, rtol, c->stream);
+    T.pfi[0][G.N](G, c->part, 0, rtol, c->stream);
+    T.pfc[1][G.N][G.D](G, c->part, cold, rtol, c->stream);
+    T.pfi[1][G.N](G, c->part, 0, rtol, c->stream);
+  }
+  HIPCHK(c, hipGetLastError());
+  const size_t n = c->inst.size();
+  std::vector<double> flags(n * kPfsLen);
+  constexpr int kBatch = 16;
+  bool all_done = false;
+  for (int it = 0;;) {
+    HIPCHK(c, hipMemcpyAsync(flags.data(), c->pfs, sizeof(double) * flags.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    all_done = true;
+    for (size_t i = 0; i < n && all_done; ++i)
+      for (int p = 0; p < c->inst[i].N; ++p)
+        if (flags[i * kPfsLen + kPfsDone + p] == 0.0) { all_done = false; break; }
+    if (all_done || it >= maxit) break;
+    const int nb = std::min(kBatch, maxit - it);
+    it += nb;
+    for (int k = 0; k < nb; ++k)
+      for (const Group& G : c->groups) {
+        T.pfc[2][G.N][G.D](G, c->part, 0, rtol, c->stream);
+        T.pfi[2][G.N](G, c->part, 0, rtol, c->stream);
+        T.pfc[3][G.N][G.D](G, c->part, 0, rtol, c->stream);
+        T.pfi[3][G.N](G, c->part, 0, rtol, c->stream);
+        T.pfc[4][G.N][G.D](G, c->part, 0, rtol, c->stream);
+      }
+    HIPCHK(c, hipGetLastError());
+  }
+  for (const Group& G : c->groups) T.pfc[5][G.N][G.D](G, c->part, clip, rtol, c->stream);
+  HIPCHK(c, hipGetLastError());
+  if (!all_done) return fail(c, MP_ERR_SOLVER, "Phase-Field CG did not reach cg_rtol within cg_maxit");
+  return MP_OK;
+}
+
 static mp_status enqueue_rk(mp_weno_ctx* c) {
   for (int s = 0; s < 3; ++s) {
     mp_status st = enqueue_stage(c, s);
     if (st != MP_OK) return st;
+  }
+  if (c->opt.phase_field) {
+    // the Phase-Field step on the hyperbolic result, same dt
+    mp_status st = run_pf_solve(c, 0, 1);
+    if (st != MP_OK) return st;
+    for (int s = 0; s < 3; ++s) {
+      st = enqueue_stage(c, s, 1);
+      if (st != MP_OK) return st;
+    }
   }
   const int n = (int)c->inst.size();
   hipLaunchKernelGGL(k_advance_time, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->t,
@@ -791,7 +1503,7 @@ static mp_status enqueue_diag(mp_weno_ctx* c) {
   for (const Group& G : c->groups) {
     T.diag[G.N][G.D](G, c->part, c->stream);
     hipLaunchKernelGGL(k_diag_finish, dim3(G.ids.size()), dim3(64), 0, c->stream, G.desc,
-                       G.rstart, c->part + G.part_off * kDiagSlots);
+                       G.rstart, c->part + G.part_off * kPartSlots);
   }
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -830,13 +1542,14 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
   }
   for (auto& I : c->inst) {
     (void)hipFree(I.U1); (void)hipFree(I.U2); (void)hipFree(I.acc); (void)hipFree(I.backup);
+    (void)hipFree(I.pf);
   }
   for (auto& G : c->groups) {
     (void)hipFree(G.desc); (void)hipFree(G.xmap); (void)hipFree(G.ymap);
     (void)hipFree(G.rmap); (void)hipFree(G.rstart);
   }
   (void)hipFree(c->dt); (void)hipFree(c->t); (void)hipFree(c->steps); (void)hipFree(c->part);
-  (void)hipFree(c->diag);
+  (void)hipFree(c->diag); (void)hipFree(c->pfs);
   delete c;
   return MP_OK;
 }
@@ -844,7 +1557,8 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
 static mp_status validate(int32_t n_inst, const mp_weno_instance* inst,
                           const mp_weno_opts* opt, void* hip_stream) {
   if (n_inst < 1 || !inst || !opt) return MP_ERR_ARG;
-  if (opt->phase_field != 0) return MP_ERR_UNSUPPORTED;
+  if (opt->phase_field != 0 && opt->phase_field != 1) return MP_ERR_ARG;
+  if (opt->phase_field && !(opt->eta_over_dx > 0.0)) return MP_ERR_ARG;
   if (opt->precision != MP_PREC_FP64 && opt->precision != MP_PREC_MIXED) return MP_ERR_ARG;
   if (opt->recon < 0 || opt->recon > 1 || opt->flux < 0 || opt->flux > 1 ||
       opt->model < 0 || opt->model > 1 || !(opt->cfl > 0.0))
@@ -889,7 +1603,8 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
   if (hipMalloc(&c->dt, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&c->t, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&c->steps, sizeof(double) * n) != hipSuccess ||
-      hipMalloc(&c->diag, sizeof(double) * n * MP_DIAG_LEN) != hipSuccess) {
+      hipMalloc(&c->diag, sizeof(double) * n * MP_DIAG_LEN) != hipSuccess ||
+      (opt->phase_field && hipMalloc(&c->pfs, sizeof(double) * n * kPfsLen) != hipSuccess)) {
     mp_weno_destroy(c);
     return MP_ERR_OOM;
   }
@@ -905,8 +1620,13 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
                     hipMalloc(&I.U2, bytes) == hipSuccess &&
                     (I.D == 1 || hipMalloc(&I.acc, bytes) == hipSuccess) &&
                     (!opt->check_bounds || hipMalloc(&I.backup, bytes) == hipSuccess);
+    // Phase-Field work arrays: k, b, Q, res, p, Kp ([N][cells] each) and the
+    // face gradients ([d][N][cells])
+    const bool okpf = !opt->phase_field ||
+        hipMalloc(&I.pf, sizeof(double) * (size_t)(6 + I.D) * I.N * (size_t)I.nc) == hipSuccess;
+    if (opt->phase_field) I.pfs = c->pfs + (size_t)i * kPfsLen;
     c->inst.push_back(I);
-    if (!ok) {
+    if (!ok || !okpf) {
       mp_weno_destroy(c);
       return MP_ERR_OOM;
     }
@@ -966,6 +1686,21 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         d.t_end = s.t_end;
         d.vol = 1.0;
         for (int k = 0; k < I.D; ++k) d.vol *= s.dx[k];
+        if (opt->phase_field) {
+          const size_t f = (size_t)I.N * (size_t)I.nc;
+          d.pfin = s.U;
+          d.pfs = I.pfs;
+          d.pf_k = I.pf;
+          d.pf_b = I.pf + f;
+          d.pf_q = I.pf + 2 * f;
+          d.pf_r = I.pf + 3 * f;
+          d.pf_p = I.pf + 4 * f;
+          d.pf_ap = I.pf + 5 * f;
+          d.pf_g = I.pf + 6 * f;
+          double h = s.dx[0];
+          for (int k = 1; k < I.D; ++k) h = std::min(h, s.dx[k]);
+          d.eta = opt->eta_over_dx * h;
+        }
         G.hdesc.push_back(d);
         const int64_t nstrip = (g.nx + kBX - 3) / (kBX - 2);
         const int64_t nty = I.D > 1 ? (int64_t)((g.nx + kTX - 1) / kTX) * ((g.ny + kOY - 1) / kOY) : 0;
@@ -1011,7 +1746,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         return MP_ERR_HIP;
       }
     }
-  if (hipMalloc(&c->part, sizeof(double) * std::max<size_t>(part_total, 1) * kDiagSlots) != hipSuccess) {
+  if (hipMalloc(&c->part, sizeof(double) * std::max<size_t>(part_total, 1) * kPartSlots) != hipSuccess) {
     mp_weno_destroy(c);
     return MP_ERR_OOM;
   }
@@ -1021,6 +1756,16 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       hipMemcpy(c->dt, zeros.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) {
     mp_weno_destroy(c);
     return MP_ERR_HIP;
+  }
+  if (opt->phase_field) {
+    // Q starts at 0 (the first solve warm-starts from it); scalars cleared
+    bool okz = hipMemset(c->pfs, 0, sizeof(double) * n * kPfsLen) == hipSuccess;
+    for (const Inst& I : c->inst)
+      okz = okz && hipMemset(I.pf, 0, sizeof(double) * (size_t)(6 + I.D) * I.N * (size_t)I.nc) == hipSuccess;
+    if (!okz || hipDeviceSynchronize() != hipSuccess) {
+      mp_weno_destroy(c);
+      return MP_ERR_HIP;
+    }
   }
   *out = c;
   return MP_OK;
@@ -1050,6 +1795,51 @@ mp_status mp_weno_rhs(mp_weno_ctx* c, const double* const* U_in, double* const* 
                         hipMemcpyHostToDevice));
   }
   return enqueue_stage(c, 3);
+}
+
+mp_status mp_weno_pf_fields(mp_weno_ctx* c, const double* const* U_in, double* const* divj,
+                            double* const* grad, double* const* dUdt) {
+  if (!c) return MP_ERR_ARG;
+  if (!c->opt.phase_field) return fail(c, MP_ERR_UNSUPPORTED, "phase_field is off");
+  if (dUdt)
+    for (size_t i = 0; i < c->inst.size(); ++i)
+      if (!dUdt[i]) return fail(c, MP_ERR_ARG, "null output pointer");
+  // the descriptor tables carry the input/output pointers of this call
+  auto set_inputs = [c, U_in, dUdt](bool call) -> mp_status {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (Group& G : c->groups) {
+      for (size_t k = 0; k < G.ids.size(); ++k) {
+        const int id = G.ids[k];
+        const double* u = (call && U_in && U_in[id]) ? U_in[id] : c->inst[id].in.U;
+        G.hdesc[k].pfin = u;
+        if (call) {
+          G.hdesc[k].rin = u;
+          G.hdesc[k].rout = dUdt ? dUdt[id] : nullptr;
+        }
+      }
+      HIPCHK(c, hipMemcpy(G.desc, G.hdesc.data(), sizeof(Desc) * G.ids.size(),
+                          hipMemcpyHostToDevice));
+    }
+    return MP_OK;
+  };
+  mp_status st = set_inputs(true);
+  if (st != MP_OK) return st;
+  st = run_pf_solve(c, 1, 0);
+  if (st == MP_OK) {
+    for (size_t i = 0; i < c->inst.size(); ++i) {
+      const Inst& I = c->inst[i];
+      const size_t f = (size_t)I.N * (size_t)I.nc;
+      if (divj && divj[i])
+        HIPCHK(c, hipMemcpyAsync(divj[i], I.pf + f, sizeof(double) * f,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      if (grad && grad[i])
+        HIPCHK(c, hipMemcpyAsync(grad[i], I.pf + 6 * f, sizeof(double) * I.D * f,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (dUdt) st = enqueue_stage(c, 3, 1);
+  }
+  const mp_status st2 = set_inputs(false);
+  return st != MP_OK ? st : st2;
 }
 
 mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
@@ -1094,7 +1884,7 @@ mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {
   if (ext)
     HIPCHK(c, hipMemcpyAsync(c->dt, dt_dev, sizeof(double) * n, hipMemcpyDeviceToDevice,
                              c->stream));
-  if (c->opt.use_graph && !c->profile) {
+  if (c->opt.use_graph && !c->profile && !c->opt.phase_field) {
     hipGraphExec_t& ge = c->graph[ext ? 1 : 0];
     if (!ge) {
       hipGraph_t gph;
@@ -1109,7 +1899,15 @@ mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {
     HIPCHK(c, hipGraphLaunch(ge, c->stream));
   } else {
     mp_status s = enqueue_step(c, ext);
-    if (s != MP_OK) return s;
+    if (s != MP_OK) {
+      if (c->opt.check_bounds) {
+        for (auto& I : c->inst)
+          HIPCHK(c, hipMemcpyAsync(I.in.U, I.backup, sizeof(double) * I.nU * I.nc,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+      }
+      return s;
+    }
   }
   if (c->opt.check_bounds) {
     mp_status s = enqueue_diag(c);

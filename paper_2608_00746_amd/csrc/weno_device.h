@@ -636,4 +636,69 @@ __device__ __forceinline__ void riemann(const Face<N, D>& L,
   F.uh = chi * Ss;
 }
 
+// -------------------------------------------------------------------------
+// Phase-Field flux (Eq. (5); F^PF of Eq. (1))
+// -------------------------------------------------------------------------
+// Bound-preserving donor/receiver form across one face, from the face states
+// L (the upper face of the lower cell) and R, and the gradients G_p = dQ_p/dx
+// at the face:  the volume flux of phase p is
+//   min(G_p,0) alpha_p^L (1 - alpha_p^R) + max(G_p,0) alpha_p^R (1 - alpha_p^L)
+// (the giving side needs the phase, the taking side needs room); the mass
+// flux uses m_p as the donor factor, momentum and energy are carried with the
+// donor's u and (|u|^2/2, A_p P + B_p, D_p).  The donor/receiver product is
+// capped at the face coefficient kf_p of Eq. (4), so the flux never exceeds
+// the k_f |dQ/dx| that equation delivers.  The phase sum S of the volume
+// fluxes is then removed in proportion to the face-average alpha_p (mass in
+// proportion to the face-average m_p, with the face-average u and P), which
+// makes sum_p F^alpha_p vanish at every face.
+template <int N, int D>
+__device__ __forceinline__ void pf_flux(const Face<N, D>& L, const Face<N, D>& R,
+                                        const double* G, const double* kf, const Eos& e,
+                                        Flux<N, D>& F) {
+  constexpr int NE = N + D;
+#pragma unroll
+  for (int c = 0; c < 2 * N + D + 1; ++c) F.f[c] = 0.0;
+  double keL = 0.0, keR = 0.0, keb = 0.0, ub[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    keL += L.u[k] * L.u[k];
+    keR += R.u[k] * R.u[k];
+    ub[k] = 0.5 * (L.u[k] + R.u[k]);
+    keb += ub[k] * ub[k];
+  }
+  keL *= 0.5;
+  keR *= 0.5;
+  keb *= 0.5;
+  const double Pb = 0.5 * (L.P + R.P);
+  double S = 0.0;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    const double bl = L.a[p] * (1.0 - R.a[p]), br = R.a[p] * (1.0 - L.a[p]);
+    const double sl = bl > kf[p] ? kf[p] / bl : 1.0;
+    const double sr = br > kf[p] ? kf[p] / br : 1.0;
+    const double dl = fmin(G[p], 0.0) * (1.0 - R.a[p]) * sl;   // lower side gives
+    const double dr = fmax(G[p], 0.0) * (1.0 - L.a[p]) * sr;   // upper side gives
+    const double fa = dl * L.a[p] + dr * R.a[p];
+    const double fm = dl * L.m[p] + dr * R.m[p];
+    F.f[NE + 1 + p] = fa;
+    F.f[p] = fm;
+#pragma unroll
+    for (int k = 0; k < D; ++k) F.f[N + k] += dl * L.m[p] * L.u[k] + dr * R.m[p] * R.u[k];
+    F.f[NE] += dl * (L.m[p] * keL + L.a[p] * (e.A[p] * L.P + e.B[p]) + L.m[p] * e.Dp[p]) +
+               dr * (R.m[p] * keR + R.a[p] * (e.A[p] * R.P + e.B[p]) + R.m[p] * e.Dp[p]);
+    S += fa;
+  }
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    const double ca = 0.5 * (L.a[p] + R.a[p]) * S;
+    const double cm = 0.5 * (L.m[p] + R.m[p]) * S;
+    F.f[NE + 1 + p] -= ca;
+    F.f[p] -= cm;
+#pragma unroll
+    for (int k = 0; k < D; ++k) F.f[N + k] -= cm * ub[k];
+    F.f[NE] -= cm * (keb + e.Dp[p]) + ca * (e.A[p] * Pb + e.B[p]);
+  }
+  F.uh = 0.0;
+}
+
 }  // namespace mpw

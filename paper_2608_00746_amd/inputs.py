@@ -38,6 +38,8 @@ class Options:
     phase_field: int = 0
     cfl: float = 0.5
     eta_over_dx: float = 1.0
+    cg_rtol: float = 1e-12
+    cg_maxit: int = 10000
 
 
 @dataclass

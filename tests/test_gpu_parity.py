@@ -265,9 +265,17 @@ def test_invalid_arguments():
         _solver(w)
     assert ei.value.status == ERR_ARG
     w = I.random_state((16,), nphase=2, seed=1)
-    o = I.Options(phase_field=1)
+    for o in (I.Options(phase_field=1, eta_over_dx=0.0), I.Options(phase_field=2)):
+        with pytest.raises(MpWenoError) as ei:
+            _solver(w, opts=o)
+        assert ei.value.status == ERR_ARG
+    w = I.random_state((16,), nphase=2, seed=1)
+    w.ndim = 3
+    w.n = (16, 1, 1)
+    w.dx = (w.dx[0], 1.0, 1.0)
+    w.bc = w.bc * 3
     with pytest.raises(MpWenoError) as ei:
-        _solver(w, opts=o)
+        _solver(w)
     assert ei.value.status == ERR_UNSUPPORTED
 
 

@@ -1,0 +1,210 @@
+"""The Phase-Field step on the GPU (Sec. 2.2.1, Eqs. (4), (5), (28)) against
+the oracle, through mp_weno_pf_fields and mp_weno_step.
+
+Tolerances (written here, derived from the arithmetic):
+* [div J_p]: no solve involved; the GPU sums the integrals of Eq. (28) in
+  another order, so 1e-12 of max |[div J_p]| per phase.
+* face fluxes J = k_f dQ/dx of Eq. (4): the GPU stops its conjugate-gradient
+  solve at ||res|| <= 1e-12 ||[div J]||; the oracle solves directly.  A
+  residual r changes J by at most ~ ||r||_1 dx (1D: exactly a prefix sum of
+  it), so J agrees to TOL_J = 1e-9 of max |J| (measured ~1e-12 .. 1e-10).
+  G itself is compared only where k_f is not negligible (elsewhere it is
+  round-off divided by k_f and only J = k_f G enters the flux).
+* L^PF and states after whole steps: dt-scaled like the hyperbolic parity
+  (dt |dL| / component scale) <= TOL_J.
+Exact invariants on the GPU: conservation, sum alpha = 1, bounds, uniform u
+and P, an absent phase stays zero and N = 3 with an absent phase reproduces
+N = 2 bitwise.
+"""
+import numpy as np
+import pytest
+
+from paper_2608_00746_amd import inputs as I
+from conftest import oracle_problem
+from test_gpu_parity import _scales
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+TOL_DIVJ = 1e-12
+TOL_J = 1e-9
+
+
+def _solver(ws, **kw):
+    from paper_2608_00746_amd.binding import Solver
+    return Solver(ws if isinstance(ws, list) else [ws], **kw)
+
+
+CASES = [
+    lambda: I.pf_bubble((160,), 2, width=1.0, bc=I.BC_PERIODIC),
+    lambda: I.pf_bubble((137,), 3, width=1.5, bc=I.BC_OUTFLOW),
+    lambda: I.pf_bubble((48, 40), 2, width=1.0, bc=I.BC_PERIODIC),
+    lambda: I.pf_bubble((36, 30), 3, width=1.5, bc=I.BC_OUTFLOW),
+    lambda: I.pf_bubble((300, 20), 2, width=2.0, bc=I.BC_OUTFLOW, u=(50.0, -20.0)),
+]
+
+
+def _faces_k(w, pb, U):
+    """k_f = (k_i + k_j)/2 at the upper face of each cell, per direction and
+    phase (0 where there is no face), with the k of Eq. (4)."""
+    N, d = w.N, w.ndim
+    k = pb.pf_k(U).reshape((N,) + tuple(w.n[::-1]))
+    out = np.zeros((d, N, w.ncells))
+    for dd in range(d):
+        ax = 1 + (d - 1 - dd)
+        kj = np.roll(k, -1, axis=ax)
+        kf = 0.5 * (k + kj)
+        if w.bc[dd][1] != I.BC_PERIODIC:
+            sl = [slice(None)] * (d + 1)
+            sl[ax] = -1
+            kf[tuple(sl)] = 0.0
+        out[dd] = kf.reshape(N, -1)
+    return out
+
+
+@pytest.mark.parametrize("make", CASES)
+def test_pf_fields_vs_oracle(oracle, make):
+    w = make()
+    pb = oracle_problem(oracle, w)
+    U = w.U.reshape(-1)
+    eta = w.dx[0] * w.opts.eta_over_dx
+    r_o, info = pb.pf_divj(U, eta)
+    G_o, res = pb.pf_gradients(U, r_o)
+    L_o = pb.pf_rhs(U, G_o, pb.pf_k(U))
+    s = _solver(w)
+    f = s.pf_fields()
+    r_g = f["divj"][0].cpu().numpy()
+    G_g = f["grad"][0].cpu().numpy()
+    L_g = f["dudt"][0].cpu().numpy().reshape(-1)
+    d = s.diag()[0]
+    s.close()
+    print(w.name, "CG iterations", d[29], "residual", d[30], "oracle residual", res)
+    assert d[30] <= 1e-12 and d[29] > 0
+    # [div J]
+    for p in range(w.N):
+        sc = np.abs(r_o[p]).max()
+        assert np.abs(r_g[p] - r_o[p]).max() <= TOL_DIVJ * sc, p
+    # face fluxes J = k_f G
+    kf = _faces_k(w, pb, U)
+    J_o, J_g = kf * G_o, kf * G_g
+    for p in range(w.N):
+        sc = np.abs(J_o[:, p]).max()
+        err = np.abs(J_g[:, p] - J_o[:, p]).max() / sc
+        print("  phase", p, "J rel err", err)
+        assert err <= TOL_J, (p, err)
+    # L^PF, dt-scaled
+    dt = pb.dt(U)
+    sc = _scales(w)
+    inc = dt * np.abs((L_g - L_o).reshape(w.nU, -1)).max(axis=1) / sc
+    print("  L^PF dt-scaled err", np.array2string(inc, precision=2))
+    assert np.isfinite(L_g).all() and (inc <= TOL_J).all(), inc
+
+
+@pytest.mark.parametrize("make,K", [(CASES[0], 5), (CASES[3], 3), (CASES[4], 3)])
+def test_pf_steps_vs_oracle(oracle, make, K):
+    w = make()
+    w.t_end = 0.0
+    pb = oracle_problem(oracle, w, t_end=0.0)
+    eta = w.dx[0] * w.opts.eta_over_dx
+    s = _solver(w)
+    U = w.U.reshape(-1).copy()
+    for _ in range(K):
+        dt = pb.dt(U)
+        U, _ = pb.step_pf(U, dt, eta)
+        s.step(dt)
+    Ug = s.host(0).reshape(w.nU, -1)
+    Uo = U.reshape(w.nU, -1)
+    err = np.abs(Ug - Uo).max(axis=1) / _scales(w, U)
+    print(w.name, "state rel err after", K, "PF steps:", np.array2string(err, precision=2))
+    assert (err <= TOL_J).all(), err
+    d = s.diag()[0]
+    assert d[27] == K and d[25] == 0
+    s.close()
+
+
+def test_pf_step_invariants():
+    w = I.pf_bubble((64, 48), 3, width=1.5, bc=I.BC_PERIODIC)
+    s = _solver(w)
+    d0 = s.diag()[0]
+    K = 10
+    for _ in range(K):
+        s.step()
+    d = s.diag()[0]
+    U = s.host(0).reshape(w.nU, -1)
+    N = 3
+    vol = np.prod(w.dx) * w.ncells
+    sc = _scales(w)
+    for c in range(w.nU):
+        assert abs(d[c] - d0[c]) <= 1e-13 * sc[c] * vol * np.sqrt(K), c
+    assert d[20] <= 16 * N * EPS * np.sqrt(K)
+    assert d[21] >= 0 and d[22] >= 0 and d[23] <= 1 + 1e-13
+    rho = U[:N].sum(0)
+    assert np.abs(U[N] / rho - 1.0).max() <= 1e-12
+    assert np.abs(U[N + 1] / rho - 0.5).max() <= 1e-12
+    g, pi = w.gamma, w.pinf
+    A, B = 1 / (g - 1), g * pi / (g - 1)
+    a = U[-N:]
+    P = (U[N + 2] - 0.5 * (U[N] ** 2 + U[N + 1] ** 2) / rho - (B[:, None] * a).sum(0)) \
+        / (A[:, None] * a).sum(0)
+    assert np.abs(P - 1e5).max() <= 64 * EPS * (1e5 + (g * pi).max()) * np.sqrt(K)
+    assert d[29] > 0
+    s.close()
+
+
+def test_pf_absent_phase_reduction_bitwise():
+    w3 = I.pf_bubble((40, 36), 3, width=1.5)
+    U3 = w3.U.reshape(w3.nU, -1)
+    N = 3
+    a = U3[-N:].copy()
+    a[1] += a[2]
+    a[2] = 0.0
+    m = np.array([1.0, 1000.0, 1030.0])[:, None] * a
+    rho = U3[:N].sum(0)
+    u = np.stack([U3[N] / rho, U3[N + 1] / rho])
+    w3.U = I.conserved(a, m, u, 1e5, w3.gamma, w3.pinf, w3.D).reshape(w3.U.shape)
+    keep = [0, 1, 3, 4, 5, 6, 7]
+    w2 = w3.copy()
+    w2.gamma, w2.pinf, w2.D, w2.pmin, w2.cT = (x[:2] for x in
+                                               (w3.gamma, w3.pinf, w3.D, w3.pmin, w3.cT))
+    w2.U = w3.U[keep].copy()
+    s3, s2 = _solver(w3), _solver(w2)
+    for _ in range(3):
+        s3.step()
+        s2.step()
+    A, B = s3.host(0).reshape(9, -1), s2.host(0).reshape(7, -1)
+    assert (A[2] == 0).all() and (A[-1] == 0).all()
+    assert np.array_equal(A[keep], B)
+    s3.close()
+    s2.close()
+
+
+def test_pf_batched_bitwise_vs_solo():
+    ws = [I.pf_bubble((48, 40), 2), I.pf_bubble((96,), 3, bc=I.BC_OUTFLOW),
+          I.pf_bubble((30, 33), 3, bc=I.BC_OUTFLOW), I.pf_bubble((70,), 2)]
+    b = _solver(ws)
+    solos = [_solver(w) for w in ws]
+    for _ in range(3):
+        b.step()
+        for s in solos:
+            s.step()
+    for i, s in enumerate(solos):
+        assert np.array_equal(b.host(i), s.host(0)), i
+        s.close()
+    b.close()
+
+
+def test_pf_solver_failure_restores_state():
+    """A solve that cannot reach the tolerance in one iteration is reported
+    (MP_ERR_SOLVER) and, with check_bounds, the state before the step is
+    restored (failure forced from the host through cg_maxit)."""
+    from paper_2608_00746_amd.binding import MpWenoError, ERR_SOLVER
+    w = I.pf_bubble((48, 40), 2)
+    w.opts.cg_maxit = 1
+    s = _solver(w, check_bounds=True)
+    before = s.host(0).copy()
+    with pytest.raises(MpWenoError) as ei:
+        s.step()
+    assert ei.value.status == ERR_SOLVER
+    assert np.array_equal(s.host(0), before)
+    assert s.diag()[0][27] == 0
+    s.close()
