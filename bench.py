@@ -66,15 +66,20 @@ def cpu_baseline(ws, seconds):
     U = w.U.reshape(-1).copy()
     t0 = time.perf_counter()
     steps = 0
+    eta = o.eta_over_dx * min(w.dx)
     while True:
-        U = pb.step(U, pb.dt(U, 0.0))
+        if o.phase_field:
+            U, _ = pb.step_pf(U, pb.dt(U, 0.0), eta)
+        else:
+            U = pb.step(U, pb.dt(U, 0.0))
         steps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
     return {"value": steps * w.ncells / el, "unit": "cell-updates/s",
             "cores": mpo.num_threads(), "kind": "oracle",
-            "sample": f"{steps} full RK3 steps of {w.name} ({w.ncells} cells), "
+            "sample": f"{steps} full RK3 steps{' with the Phase-Field step' if o.phase_field else ''} "
+                      f"of {w.name} ({w.ncells} cells), "
                       f"{el:.1f} s, OpenMP over grid lines"}
 
 
@@ -89,6 +94,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--phase-field", action="store_true",
+                    help="end every step with the Phase-Field step (reported separately)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -101,6 +108,9 @@ def main():
 
     ws = workload(args.workload, args.precision)
     from paper_2608_00746_amd import inputs as I
+    if args.phase_field:
+        for w in ws:
+            w.opts.phase_field = 1
     precision = "mixed" if ws[0].opts.precision == I.PREC_MIXED else "fp64"
     stream = torch.cuda.Stream()
     s = Solver(ws, stream=stream, use_graph=not args.no_graph)
@@ -129,6 +139,7 @@ def main():
 
     # sanity: the state stayed finite and admissible
     d = s.diag()
+    cg_its = float(d[:, 29].max())
     if (d[:, 25] > 0).any():
         raise SystemExit("non-finite state after the timed steps")
 
@@ -160,7 +171,8 @@ def main():
             "precision": precision,
             "recon": ["WENO-C", "WENO-CL"][w0.opts.recon],
             "flux": ["HLLC", "HLL"][w0.opts.flux],
-            "cfl": w0.opts.cfl, "graph": not args.no_graph,
+            "cfl": w0.opts.cfl, "graph": not args.no_graph and not args.phase_field,
+            "phase_field": bool(args.phase_field),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -173,6 +185,8 @@ def main():
     }
     if len(ws) > 1:
         out["instances_per_s"] = len(ws) * args.steps / (ms / 1e3)
+    if args.phase_field:
+        out["pf_cg_iterations_last_step"] = cg_its
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_seconds)
     s.close()
