@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="copy a buffer of this many MiB device-to-device once before the "
+                         "timed region (a reference kernel of known traffic for counters)")
     ap.add_argument("--phase-field", action="store_true",
                     help="end every step with the Phase-Field step (reported separately)")
     args = ap.parse_args()
@@ -119,6 +122,13 @@ def main():
     for _ in range(args.warmup):
         s.step()
     torch.cuda.synchronize()
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # timed region: K whole steps bracketed by synchronisation; the stage
     # kernel of every RK stage is bracketed by HIP events on its stream

@@ -208,8 +208,19 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
 // ---------------------------------------------------------------------------
 // x sweep
 // ---------------------------------------------------------------------------
+// Waves per SIMD the sweeps are compiled for: one or two phases fit 3 (or 4)
+// waves in the register file with at most a few spilled values, which hides
+// FP64 latency better than 2 waves (measured +7..10 % on N = 2); three and
+// four phases would spill heavily at 3 and keep 2; five need the AGPRs too.
+template <int N, int D>
+constexpr int sweep_waves() {
+  return N == 1 ? (D == 1 ? 4 : 3) : (N == 2 ? 3 : (N <= 4 ? 2 : 1));
+}
+
 template <int N, int D, typename W, int PFM>
-__global__ __launch_bounds__(kBX) void k_sweep_x(const Desc* __restrict__ descs,
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kBX),
+                          amdgpu_waves_per_eu(sweep_waves<N, D>(), 8)))
+void k_sweep_x(const Desc* __restrict__ descs,
                                                  const int2* __restrict__ map,
                                                  int ninst, int stage, int swz) {
   const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));
@@ -363,7 +374,9 @@ constexpr int kTY = 16;
 constexpr int kOY = kTY - 2;      // output rows per tile
 
 template <int N, typename W, int PFM>
-__global__ __launch_bounds__(kTX * kTY) void k_sweep_y(const Desc* __restrict__ descs,
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kTX * kTY),
+                          amdgpu_waves_per_eu(sweep_waves<N, 2>(), 8)))
+void k_sweep_y(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map,
                                                        int ninst, int stage, int swz) {
   const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));

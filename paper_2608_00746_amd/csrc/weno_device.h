@@ -153,6 +153,18 @@ __device__ __forceinline__ double psi(const double* m, const double* a,
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Reciprocal of a positive normal double in [2^-1000, 2^1000] without the
+// special-case scaling of the IEEE division sequence: the hardware estimate
+// refined by two Newton steps (within an ulp or two of 1/x).
+__device__ __forceinline__ double rcp_normal(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_normal(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // -------------------------------------------------------------------------
 // WENO5 with the relative-smoothness weights (Sec. 3.1, 3.3)
 // -------------------------------------------------------------------------
@@ -213,21 +225,29 @@ __device__ __forceinline__ void wenow_weights(const W bin[3], W wl[3], W wr[3]) 
     wr[0] = W(0.3); wr[1] = W(0.6); wr[2] = W(0.1);
     return;
   }
-  // a (sub)normal-range maximum would overflow 1/bm: rescale the set by an
-  // exact power of two first, which leaves every ratio unchanged
+  // Scale the set so that its largest member lies in [1/2, 1): an exact
+  // power of two (FP64), which leaves every ratio unchanged and needs no
+  // division; the hardware reciprocal of the maximum (FP32, after an exact
+  // power-of-two lift of sets below 2^-100).
   constexpr bool DBL = sizeof(W) == 8;
-  const W small = DBL ? W(0x1p-900) : W(0x1p-100);
-  if (bm < small) {
-    const W up = DBL ? W(0x1p700) : W(0x1p80);
-    b[0] *= up; b[1] *= up; b[2] *= up; bm *= up;
+  W s0, s1, s2;
+  if constexpr (DBL) {
+    int e;
+    (void)frexp(bm, &e);
+    s0 = ldexp(b[0], -e); s1 = ldexp(b[1], -e); s2 = ldexp(b[2], -e);
+  } else {
+    if (bm < W(0x1p-100)) {
+      const W up = W(0x1p80);
+      b[0] *= up; b[1] *= up; b[2] *= up; bm *= up;
+    }
+    const W r = rcp(bm);
+    s0 = b[0] * r; s1 = b[1] * r; s2 = b[2] * r;
   }
-  const W r = rcp(bm);
   // Scaled indicators below tau join the zero set: this keeps every product
   // below (and the reciprocal of their sum) inside the normal range; the
   // face value moves by at most the spread of those candidates, which is
   // O(tau) relative to the stencil's variation.
   const W tau = DBL ? W(1e-70) : W(1e-8);
-  W s0 = b[0] * r, s1 = b[1] * r, s2 = b[2] * r;
   s0 = s0 < tau ? W(0) : s0;
   s1 = s1 < tau ? W(0) : s1;
   s2 = s2 < tau ? W(0) : s2;
@@ -237,7 +257,8 @@ __device__ __forceinline__ void wenow_weights(const W bin[3], W wl[3], W wr[3]) 
   const W r0 = W(0.3) * p0, r1 = W(0.6) * p1, r2 = W(0.1) * p2;
   const W dl = l0 + l1 + l2, dr = r0 + r1 + r2;
   if (dl > W(0)) {
-    const W il = rcp(dl), ir = rcp(dr);
+    // dl, dr >= 1e-281 (every nonzero scaled indicator is >= tau)
+    const W il = rcp_normal(dl), ir = rcp_normal(dr);
     wl[0] = l0 * il; wl[1] = l1 * il; wl[2] = l2 * il;
     wr[0] = r0 * ir; wr[1] = r1 * ir; wr[2] = r2 * ir;
   } else {
