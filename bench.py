@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shapes (no mp_weno_autotune at set-up)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="copy a buffer of this many MiB device-to-device once before the "
                          "timed region (a reference kernel of known traffic for counters)")
@@ -118,6 +120,7 @@ def main():
     stream = torch.cuda.Stream()
     s = Solver(ws, stream=stream, use_graph=not args.no_graph)
     cells = sum(w.ncells for w in ws)
+    tiles = None if args.no_autotune else s.autotune()
 
     for _ in range(args.warmup):
         s.step()
@@ -183,6 +186,9 @@ def main():
             "flux": ["HLLC", "HLL"][w0.opts.flux],
             "cfl": w0.opts.cfl, "graph": not args.no_graph and not args.phase_field,
             "phase_field": bool(args.phase_field),
+            "tiles": "default" if tiles is None else
+                     sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
+                             for t in tiles.tolist()}),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

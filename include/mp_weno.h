@@ -154,6 +154,18 @@ mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
                             double *const *divj, double *const *grad,
                             double *const *dUdt);
 
+/* Autotuner: for every group of instances with the same (N, d), time the
+ * tile shapes of the two sweeps (x strips of 256 or 128 lanes; y tiles of
+ * 16 x 16 or 32 x 8 lanes) and the XCD-aware tile order (off / on) on the
+ * current states, reps launches each (0: 5), and keep the fastest for the
+ * hyperbolic sweeps of later calls.  The timing evaluates L(U) into the
+ * context's stage buffer: the states, the time and the step count are not
+ * touched.  Synchronises the stream; drops a captured step graph (the next
+ * mp_weno_step captures again).  choice (may be NULL): host array of
+ * 4 n_inst int32 that receives per instance the x strip width, the y tile
+ * width and height (0 in 1D) and the tile order (0 plain, 1 XCD-aware). */
+mp_status mp_weno_autotune(mp_weno_ctx *ctx, int32_t reps, int32_t *choice);
+
 /* CFL time step per instance: dt = cfl / max_cells sum_d (|u_d| + c)/dx_d,
  * clipped so that t + dt <= t_end (t is the instance's time, advanced by
  * mp_weno_step).  where = MP_WHERE_DEVICE: dt is a device array of n_inst

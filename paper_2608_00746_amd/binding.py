@@ -70,6 +70,8 @@ def lib():
         L.mp_weno_pf_fields.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                         C.POINTER(vp)]
         L.mp_weno_pf_fields.restype = C.c_int
+        L.mp_weno_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+        L.mp_weno_autotune.restype = C.c_int
         L.mp_weno_dt.argtypes = [vp, vp, C.c_int32]
         L.mp_weno_dt.restype = C.c_int
         L.mp_weno_step.argtypes = [vp, vp]
@@ -94,8 +96,8 @@ def lib():
 
 
 EXPORTED = ["mp_weno_abi_version", "mp_weno_max_phases", "mp_weno_init",
-            "mp_weno_rhs", "mp_weno_pf_fields", "mp_weno_dt", "mp_weno_step",
-            "mp_weno_diag",
+            "mp_weno_rhs", "mp_weno_pf_fields", "mp_weno_autotune", "mp_weno_dt",
+            "mp_weno_step", "mp_weno_diag",
             "mp_weno_set_time", "mp_weno_destroy", "mp_weno_strerror",
             "mp_weno_last_error", "mp_weno_profile", "mp_weno_timing"]
 
@@ -220,6 +222,15 @@ class Solver:
                                             arrs["dudt"]))
         self._leave()
         return out
+
+    def autotune(self, reps=5):
+        """Pick the fastest sweep tile shapes and tile order per group; returns
+        per instance (x strip, y tile width, y tile height, XCD order)."""
+        out = (C.c_int32 * (4 * len(self.U)))()
+        self._enter()
+        self._check(lib().mp_weno_autotune(self.ctx, int(reps), out))
+        self._leave()
+        return np.array(list(out), dtype=np.int64).reshape(len(self.U), 4)
 
     def dt(self):
         out = np.zeros(len(self.U))

@@ -39,7 +39,14 @@
 namespace mpw {
 
 constexpr int kMaxN = 5;          // phases built
-constexpr int kBX = 256;          // lanes of the x sweep (254 output cells)
+// Tile shapes (chosen per group by mp_weno_autotune; index 0 is the default):
+// x sweep strips of kXS[v] lanes (kXS[v] - 2 output cells), y sweep tiles of
+// kYX[v] x kYY[v] lanes (kYY[v] - 2 output rows).  The Phase-Field sweeps use
+// the defaults.
+constexpr int kXVar = 2, kYVar = 2;
+constexpr int kXS[kXVar] = {256, 128};
+constexpr int kYX[kYVar] = {16, 32};
+constexpr int kYY[kYVar] = {16, 8};
 constexpr int kRedBlock = 256;    // reduction workgroup
 constexpr int kDiagSlots = 32;    // per-block partials of the diagnostics
 constexpr int kPartSlots = 40;    // stride of the per-chunk partials
@@ -217,8 +224,8 @@ constexpr int sweep_waves() {
   return N == 1 ? (D == 1 ? 4 : 3) : (N == 2 ? 3 : (N <= 4 ? 2 : 1));
 }
 
-template <int N, int D, typename W, int PFM>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, kBX),
+template <int N, int D, typename W, int PFM, int BX>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, BX),
                           amdgpu_waves_per_eu(sweep_waves<N, D>(), 8)))
 void k_sweep_x(const Desc* __restrict__ descs,
                                                  const int2* __restrict__ map,
@@ -228,7 +235,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
   const Grid& g = d.g;
   const Eos& e = d.e;
   const StageArgs a = stage_args(d, stage);
-  const int ns = (g.nx + kBX - 3) / (kBX - 2);
+  const int ns = (g.nx + BX - 3) / (BX - 2);
   const int local = it.y;
   const int y = local / ns;
   constexpr int NV = 2 * N + D + 1;
@@ -237,14 +244,14 @@ void k_sweep_x(const Desc* __restrict__ descs,
   constexpr int NFL = NU + 1;
   // the flux rows reuse the primitive rows: the stencil is in registers and
   // a barrier (after the face exchange) separates the two uses
-  constexpr int NPRIM = NV * (kBX + 4), NFLX = NFL * kBX;
+  constexpr int NPRIM = NV * (BX + 4), NFLX = NFL * BX;
   __shared__ double sraw[NPRIM > NFLX ? NPRIM : NFLX];
-  __shared__ double sface[NF][kBX];
-  double (*sprim)[kBX + 4] = reinterpret_cast<double (*)[kBX + 4]>(sraw);
-  double (*sflux)[kBX] = reinterpret_cast<double (*)[kBX]>(sraw);
+  __shared__ double sface[NF][BX];
+  double (*sprim)[BX + 4] = reinterpret_cast<double (*)[BX + 4]>(sraw);
+  double (*sflux)[BX] = reinterpret_cast<double (*)[BX]>(sraw);
 
   const int l = threadIdx.x;
-  const int x0 = (local - y * ns) * (kBX - 2);
+  const int x0 = (local - y * ns) * (BX - 2);
   const int xi = x0 - 1 + l;
   const int64_t row = (int64_t)y * g.nx;
   const int64_t nc = g.nc;
@@ -275,7 +282,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
     sprim[2 * N + D][l + 2] = v.P;
   }
   if (l < 2) put_prim(x0 - 3 + l, l);
-  if (l >= kBX - 2) put_prim(x0 - 1 + l + 2, l + 4);
+  if (l >= BX - 2) put_prim(x0 - 1 + l + 2, l + 4);
   __syncthreads();
 
   Prim<N, D> s[5];
@@ -302,7 +309,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
   __syncthreads();
 
   Flux<N, D> F;
-  if (l < kBX - 1) {
+  if (l < BX - 1) {
     Face<N, D> R;
     const int r = l + 1;
 #pragma unroll
@@ -336,7 +343,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
   }
   __syncthreads();
 
-  if (l >= 1 && l < kBX - 1 && xi < g.nx) {
+  if (l >= 1 && l < BX - 1 && xi < g.nx) {
     double L[NU];
     if constexpr (PFM) {
 #pragma unroll
@@ -369,11 +376,8 @@ void k_sweep_x(const Desc* __restrict__ descs,
 // segment is kTX contiguous doubles per component, one 128-byte line), every
 // lane reconstructs its cell along y from its column, and face states and
 // fluxes are traded with the neighbour row through LDS, as in the x sweep.
-constexpr int kTX = 16;
-constexpr int kTY = 16;
-constexpr int kOY = kTY - 2;      // output rows per tile
 
-template <int N, typename W, int PFM>
+template <int N, typename W, int PFM, int kTX, int kTY>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kTX * kTY),
                           amdgpu_waves_per_eu(sweep_waves<N, 2>(), 8)))
 void k_sweep_y(const Desc* __restrict__ descs,
@@ -387,6 +391,7 @@ void k_sweep_y(const Desc* __restrict__ descs,
   const int ntx = (g.nx + kTX - 1) / kTX;
   const int local = it.y;
   const int tyb = local / ntx, txb = local - tyb * ntx;
+  constexpr int kOY = kTY - 2;      // output rows per tile
   constexpr int D = 2;
   constexpr int NV = 2 * N + D + 1;
   constexpr int NU = NV;
@@ -1232,11 +1237,13 @@ struct Group {
   int N = 0, D = 0;
   std::vector<int> ids;            // context instance indices
   std::vector<Desc> hdesc;         // host copy of the descriptors
-  std::vector<int> xs, ys, rs;     // tile / reduction-chunk offsets (n + 1)
+  std::vector<int> xs[kXVar], ys[kYVar], rs;  // tile / chunk offsets (n + 1)
   Desc* desc = nullptr;
-  int2* xmap = nullptr;            // work item -> (instance, local tile)
-  int2* ymap = nullptr;
+  int2* xmap[kXVar] = {};          // work item -> (instance, local tile)
+  int2* ymap[kYVar] = {};
   int2* rmap = nullptr;
+  int xv = 0, yv = 0;              // tile shapes in use (autotuned)
+  int swz = -1;                    // XCD order: -1 default rule, 0 off, 1 on
   int* rstart = nullptr;           // reduction-chunk offsets on the device
   size_t part_off = 0;             // this group's reduction partials
 };
@@ -1253,18 +1260,18 @@ using RedFn = void (*)(const Group&, double* part, hipStream_t);
 // finishers (rtol is used by the finishers that test convergence)
 using PfFn = void (*)(const Group&, double* part, int flag, double rtol, hipStream_t);
 
-template <int N, int D, typename W, int PFM>
+template <int N, int D, typename W, int PFM, int V>
 void launch_x(const Group& G, int stage, int swz, hipStream_t s) {
   const int n = (int)G.ids.size();
-  hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM>), dim3(G.xs[n]), dim3(kBX), 0, s, G.desc,
-                     G.xmap, n, stage, swz);
+  hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM, kXS[V]>), dim3(G.xs[V][n]), dim3(kXS[V]), 0, s,
+                     G.desc, G.xmap[V], n, stage, swz);
 }
 
-template <int N, typename W, int PFM>
+template <int N, typename W, int PFM, int V>
 void launch_y(const Group& G, int stage, int swz, hipStream_t s) {
   const int n = (int)G.ids.size();
-  hipLaunchKernelGGL((k_sweep_y<N, W, PFM>), dim3(G.ys[n]), dim3(kTX * kTY), 0, s, G.desc,
-                     G.ymap, n, stage, swz);
+  hipLaunchKernelGGL((k_sweep_y<N, W, PFM, kYX[V], kYY[V]>), dim3(G.ys[V][n]),
+                     dim3(kYX[V] * kYY[V]), 0, s, G.desc, G.ymap[V], n, stage, swz);
 }
 
 // kind: 0 prep, 1 divJ + CG start, 2 K p, 3 update, 4 direction, 5 gradients
@@ -1307,8 +1314,8 @@ void launch_diag(const Group& G, double* part, hipStream_t s) {
 }
 
 struct Table {
-  StageFn sx[2][kMaxN + 1][3][2] = {};     // [PF flux][N][d][precision]
-  StageFn sy[2][kMaxN + 1][2] = {};
+  StageFn sx[2][kMaxN + 1][3][2][kXVar] = {};   // [PF flux][N][d][precision][shape]
+  StageFn sy[2][kMaxN + 1][2][kYVar] = {};
   RedFn dt[kMaxN + 1][3] = {};
   RedFn diag[kMaxN + 1][3] = {};
   PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
@@ -1325,20 +1332,27 @@ void fill_pf(Table& t) {
   t.pfc[5][N][D] = launch_pf_cells<N, D, 5>;
 }
 
+template <int N, int V>
+void fill_shapes(Table& t) {
+  t.sx[0][N][1][0][V] = launch_x<N, 1, double, 0, V>;
+  t.sx[0][N][1][1][V] = launch_x<N, 1, float, 0, V>;
+  t.sx[0][N][2][0][V] = launch_x<N, 2, double, 0, V>;
+  t.sx[0][N][2][1][V] = launch_x<N, 2, float, 0, V>;
+  t.sy[0][N][0][V] = launch_y<N, double, 0, V>;
+  t.sy[0][N][1][V] = launch_y<N, float, 0, V>;
+}
+
 template <int N>
 void fill(Table& t) {
-  t.sx[0][N][1][0] = launch_x<N, 1, double, 0>;
-  t.sx[0][N][1][1] = launch_x<N, 1, float, 0>;
-  t.sx[0][N][2][0] = launch_x<N, 2, double, 0>;
-  t.sx[0][N][2][1] = launch_x<N, 2, float, 0>;
-  t.sy[0][N][0] = launch_y<N, double, 0>;
-  t.sy[0][N][1] = launch_y<N, float, 0>;
-  t.sx[1][N][1][0] = launch_x<N, 1, double, 1>;
-  t.sx[1][N][1][1] = launch_x<N, 1, float, 1>;
-  t.sx[1][N][2][0] = launch_x<N, 2, double, 1>;
-  t.sx[1][N][2][1] = launch_x<N, 2, float, 1>;
-  t.sy[1][N][0] = launch_y<N, double, 1>;
-  t.sy[1][N][1] = launch_y<N, float, 1>;
+  fill_shapes<N, 0>(t);
+  fill_shapes<N, 1>(t);
+  // the Phase-Field sweeps: default shapes only
+  t.sx[1][N][1][0][0] = launch_x<N, 1, double, 1, 0>;
+  t.sx[1][N][1][1][0] = launch_x<N, 1, float, 1, 0>;
+  t.sx[1][N][2][0][0] = launch_x<N, 2, double, 1, 0>;
+  t.sx[1][N][2][1][0] = launch_x<N, 2, float, 1, 0>;
+  t.sy[1][N][0][0] = launch_y<N, double, 1, 0>;
+  t.sy[1][N][1][0] = launch_y<N, float, 1, 0>;
   fill_pf<N, 1>(t);
   fill_pf<N, 2>(t);
   t.pfi[0][N] = launch_pf_inst<N, 0>;
@@ -1422,12 +1436,17 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
   const Bracket* b = (s < 3 && !pf) ? c->next_bracket(br) : nullptr;
   const int w = b ? b->which : 0;
   if (w == 1 || w == 3) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
-  auto swz = [c](const Group& G) { return c->swz < 0 ? (G.ids.size() > 1 ? 1 : 0) : c->swz; };
-  for (const Group& G : c->groups) T.sx[pf][G.N][G.D][prec](G, s, swz(G), c->stream);
+  auto swz = [c](const Group& G) {
+    if (c->swz >= 0) return c->swz;
+    if (G.swz >= 0) return G.swz;
+    return G.ids.size() > 1 ? 1 : 0;
+  };
+  for (const Group& G : c->groups)
+    T.sx[pf][G.N][G.D][prec][pf ? 0 : G.xv](G, s, swz(G), c->stream);
   if (w == 1) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   if (w == 2) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
   for (const Group& G : c->groups)
-    if (G.D == 2) T.sy[pf][G.N][prec](G, s, swz(G), c->stream);
+    if (G.D == 2) T.sy[pf][G.N][prec][pf ? 0 : G.yv](G, s, swz(G), c->stream);
   if (w == 2 || w == 3) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -1558,8 +1577,9 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
     (void)hipFree(I.pf);
   }
   for (auto& G : c->groups) {
-    (void)hipFree(G.desc); (void)hipFree(G.xmap); (void)hipFree(G.ymap);
-    (void)hipFree(G.rmap); (void)hipFree(G.rstart);
+    (void)hipFree(G.desc); (void)hipFree(G.rmap); (void)hipFree(G.rstart);
+    for (auto* m : G.xmap) (void)hipFree(m);
+    for (auto* m : G.ymap) (void)hipFree(m);
   }
   (void)hipFree(c->dt); (void)hipFree(c->t); (void)hipFree(c->steps); (void)hipFree(c->part);
   (void)hipFree(c->diag); (void)hipFree(c->pfs);
@@ -1612,6 +1632,12 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
   c->stream = (hipStream_t)hip_stream;
   const char* sw = std::getenv("MPWENO_XCD_SWIZZLE");
   if (sw) c->swz = std::atoi(sw) ? 1 : 0;
+  // initial tile shapes (indices into kXS / kYX, kYY; later changed only by
+  // mp_weno_autotune)
+  const char* xsh = std::getenv("MPWENO_XSHAPE");
+  const char* ysh = std::getenv("MPWENO_YSHAPE");
+  const int xv0 = xsh ? std::min(std::max(std::atoi(xsh), 0), kXVar - 1) : 0;
+  const int yv0 = ysh ? std::min(std::max(std::atoi(ysh), 0), kYVar - 1) : 0;
   const size_t n = (size_t)n_inst;
   if (hipMalloc(&c->dt, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&c->t, sizeof(double) * n) != hipSuccess ||
@@ -1658,7 +1684,9 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       std::stable_sort(G.ids.begin(), G.ids.end(), [&](int a, int b) {
         return c->inst[a].nc > c->inst[b].nc;
       });
-      G.xs.push_back(0); G.ys.push_back(0); G.rs.push_back(0);
+      for (auto& v : G.xs) v.push_back(0);
+      for (auto& v : G.ys) v.push_back(0);
+      G.rs.push_back(0);
       for (int id : G.ids) {
         const Inst& I = c->inst[id];
         const mp_weno_instance& s = I.in;
@@ -1715,18 +1743,25 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           d.eta = opt->eta_over_dx * h;
         }
         G.hdesc.push_back(d);
-        const int64_t nstrip = (g.nx + kBX - 3) / (kBX - 2);
-        const int64_t nty = I.D > 1 ? (int64_t)((g.nx + kTX - 1) / kTX) * ((g.ny + kOY - 1) / kOY) : 0;
-        const int64_t nx = G.xs.back() + g.ny * nstrip;
-        const int64_t ny = G.ys.back() + nty;
-        const int64_t nr = G.rs.back() + (I.nc + kRedChunk - 1) / kRedChunk;
-        if (std::max(nx, std::max(ny, nr)) > (int64_t)INT32_MAX) {
+        int64_t top = G.rs.back() + (I.nc + kRedChunk - 1) / kRedChunk;
+        G.rs.push_back((int)std::min<int64_t>(top, INT32_MAX));
+        for (int v = 0; v < kXVar; ++v) {
+          const int64_t nstrip = (g.nx + kXS[v] - 3) / (kXS[v] - 2);
+          const int64_t nx = G.xs[v].back() + g.ny * nstrip;
+          top = std::max(top, nx);
+          G.xs[v].push_back((int)std::min<int64_t>(nx, INT32_MAX));
+        }
+        for (int v = 0; v < kYVar; ++v) {
+          const int oy = kYY[v] - 2;
+          const int64_t nty = I.D > 1 ? (int64_t)((g.nx + kYX[v] - 1) / kYX[v]) * ((g.ny + oy - 1) / oy) : 0;
+          const int64_t ny = G.ys[v].back() + nty;
+          top = std::max(top, ny);
+          G.ys[v].push_back((int)std::min<int64_t>(ny, INT32_MAX));
+        }
+        if (top >= (int64_t)INT32_MAX) {
           mp_weno_destroy(c);
           return MP_ERR_UNSUPPORTED;     // more tiles than one launch can index
         }
-        G.xs.push_back((int)nx);
-        G.ys.push_back((int)ny);
-        G.rs.push_back((int)nr);
       }
       G.part_off = part_total;
       part_total += (size_t)G.rs.back();
@@ -1737,24 +1772,39 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           for (int j = st[k]; j < st[k + 1]; ++j) v[(size_t)j] = make_int2((int)k, j - st[k]);
         return v;
       };
-      const std::vector<int2> xm = tile_map(G.xs), ym = tile_map(G.ys), rm = tile_map(G.rs);
+      const std::vector<int2> rm = tile_map(G.rs);
+      std::vector<int2> xm[kXVar], ym[kYVar];
       bool ok = hipMalloc(&G.desc, sizeof(Desc) * m) == hipSuccess &&
-                hipMalloc(&G.xmap, sizeof(int2) * std::max<size_t>(xm.size(), 1)) == hipSuccess &&
-                hipMalloc(&G.ymap, sizeof(int2) * std::max<size_t>(ym.size(), 1)) == hipSuccess &&
                 hipMalloc(&G.rmap, sizeof(int2) * std::max<size_t>(rm.size(), 1)) == hipSuccess &&
                 hipMalloc(&G.rstart, sizeof(int) * (m + 1)) == hipSuccess;
+      for (int v = 0; v < kXVar; ++v) {
+        xm[v] = tile_map(G.xs[v]);
+        ok = ok && hipMalloc(&G.xmap[v], sizeof(int2) * std::max<size_t>(xm[v].size(), 1)) == hipSuccess;
+      }
+      for (int v = 0; v < kYVar; ++v) {
+        ym[v] = tile_map(G.ys[v]);
+        ok = ok && hipMalloc(&G.ymap[v], sizeof(int2) * std::max<size_t>(ym[v].size(), 1)) == hipSuccess;
+      }
+      G.xv = xv0;
+      G.yv = yv0;
       c->groups.push_back(G);
       if (!ok) {
         mp_weno_destroy(c);
         return MP_ERR_OOM;
       }
       Group& H = c->groups.back();
-      if (hipMemcpy(H.desc, H.hdesc.data(), sizeof(Desc) * m, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(H.xmap, xm.data(), sizeof(int2) * xm.size(), hipMemcpyHostToDevice) != hipSuccess ||
-          (!ym.empty() &&
-           hipMemcpy(H.ymap, ym.data(), sizeof(int2) * ym.size(), hipMemcpyHostToDevice) != hipSuccess) ||
-          hipMemcpy(H.rmap, rm.data(), sizeof(int2) * rm.size(), hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(H.rstart, H.rs.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice) != hipSuccess) {
+      bool okc = hipMemcpy(H.desc, H.hdesc.data(), sizeof(Desc) * m, hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(H.rmap, rm.data(), sizeof(int2) * rm.size(), hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(H.rstart, H.rs.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice) == hipSuccess;
+      for (int v = 0; v < kXVar; ++v)
+        okc = okc && (xm[v].empty() ||
+                      hipMemcpy(H.xmap[v], xm[v].data(), sizeof(int2) * xm[v].size(),
+                                hipMemcpyHostToDevice) == hipSuccess);
+      for (int v = 0; v < kYVar; ++v)
+        okc = okc && (ym[v].empty() ||
+                      hipMemcpy(H.ymap[v], ym[v].data(), sizeof(int2) * ym[v].size(),
+                                hipMemcpyHostToDevice) == hipSuccess);
+      if (!okc) {
         mp_weno_destroy(c);
         return MP_ERR_HIP;
       }
@@ -1853,6 +1903,71 @@ mp_status mp_weno_pf_fields(mp_weno_ctx* c, const double* const* U_in, double* c
   }
   const mp_status st2 = set_inputs(false);
   return st != MP_OK ? st : st2;
+}
+
+mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
+  if (!c || reps < 0) return fail(c, MP_ERR_ARG, "bad argument");
+  if (reps == 0) reps = 5;
+  const Table& T = table();
+  const int prec = c->opt.precision;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // time L(U) of the current states into the stage buffer U1 (the states
+  // and the step state are untouched)
+  for (Group& G : c->groups) {
+    for (size_t k = 0; k < G.ids.size(); ++k) {
+      G.hdesc[k].rin = c->inst[G.ids[k]].in.U;
+      G.hdesc[k].rout = c->inst[G.ids[k]].U1;
+    }
+    HIPCHK(c, hipMemcpy(G.desc, G.hdesc.data(), sizeof(Desc) * G.ids.size(),
+                        hipMemcpyHostToDevice));
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(c, MP_ERR_HIP, "hipEventCreate failed");
+  }
+  mp_status st = MP_OK;
+  for (Group& G : c->groups) {
+    float best = INFINITY;
+    int bx = 0, by = 0, bs = 0;
+    for (int xv = 0; xv < kXVar && st == MP_OK; ++xv)
+      for (int yv = 0; yv < (G.D == 2 ? kYVar : 1) && st == MP_OK; ++yv)
+        for (int sw = 0; sw < 2 && st == MP_OK; ++sw) {
+          auto run = [&]() {
+            T.sx[0][G.N][G.D][prec][xv](G, 3, sw, c->stream);
+            if (G.D == 2) T.sy[0][G.N][prec][yv](G, 3, sw, c->stream);
+          };
+          run();   // warm-up
+          float ms = 0.0f;
+          if (hipEventRecord(e0, c->stream) != hipSuccess) { st = MP_ERR_HIP; break; }
+          for (int r = 0; r < reps; ++r) run();
+          if (hipEventRecord(e1, c->stream) != hipSuccess ||
+              hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess) {
+            st = MP_ERR_HIP;
+            break;
+          }
+          if (ms < best) { best = ms; bx = xv; by = yv; bs = sw; }
+        }
+    G.xv = bx;
+    G.yv = by;
+    G.swz = bs;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != MP_OK) return fail(c, st, "autotune launch failed");
+  // a captured step holds the old launch shapes
+  for (auto& g : c->graph)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  if (choice)
+    for (const Group& G : c->groups)
+      for (int id : G.ids) {
+        choice[4 * id + 0] = kXS[G.xv];
+        choice[4 * id + 1] = G.D == 2 ? kYX[G.yv] : 0;
+        choice[4 * id + 2] = G.D == 2 ? kYY[G.yv] : 0;
+        choice[4 * id + 3] = G.swz;
+      }
+  return MP_OK;
 }
 
 mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
