@@ -114,8 +114,8 @@ int32_t mp_weno_max_phases(void);
  * captures on the stream); every later call is ordered on it.
  * Allocates the scratch: two RK stage buffers and one direction accumulator
  * per instance (3 n_U doubles per cell) plus small reduction buffers; with
- * phase_field, (6 + d) N doubles per cell more (k_p, [div J_p], Q_p, three CG
- * vectors and the face gradients).
+ * phase_field, (8 + d) N doubles per cell more (k_p, [div J_p], Q_p, four CG
+ * vectors, the Jacobi diagonal and the face gradients).
  * Errors: MP_ERR_ARG (bad sizes, gamma <= 1, dx <= 0, phase_field with
  * eta_over_dx <= 0, ...), MP_ERR_UNSUPPORTED (N or ndim beyond the build),
  * MP_ERR_OOM, MP_ERR_HIP.

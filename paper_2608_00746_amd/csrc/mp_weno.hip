@@ -49,11 +49,13 @@ constexpr int kYX[kYVar] = {16, 32};
 constexpr int kYY[kYVar] = {16, 8};
 constexpr int kRedBlock = 256;    // reduction workgroup
 constexpr int kDiagSlots = 32;    // per-block partials of the diagnostics
-constexpr int kPartSlots = 40;    // stride of the per-chunk partials
+constexpr int kPartSlots = 40;    // partial slots per reduction chunk (stored slot-major:
+                                  // slot k of chunk b at k * Desc::ps + b)
 // per-instance Phase-Field scalars (offsets into Desc::pfs): mobility,
 // M / eta^2, multipliers B_q, CG iterations and relative residual at exit,
 // and per phase ||b||^2, res.z, alpha, beta, done flag, iterations
 constexpr int kPfsLen = 64;
+constexpr int kPfFields = 8;      // Phase-Field work arrays of N fields each
 // floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
 // is solvable for every right side of zero total and stays conditioned; only
 // cells with phi or 1 - phi below ~1e-6 see it
@@ -99,6 +101,8 @@ struct Desc {
   double* steps;
   double* diag;              // MP_DIAG_LEN results
   double t_end, vol;
+  int64_t ps;                // slot stride of the reduction partials
+  int64_t chunk;             // cells per reduction workgroup
   // Phase-Field step (null when it is off)
   const double* pfin;        // state whose volume fractions are phi_p
   double* pfs;               // per-instance scalars (kPfs* offsets)
@@ -107,7 +111,9 @@ struct Desc {
   double* pf_q;              // Q_p                                [N][cells]
   double* pf_r;              // CG residual                        [N][cells]
   double* pf_p;              // CG direction                       [N][cells]
-  double* pf_ap;             // K p                                [N][cells]
+  double* pf_ap;             // CG s = K p                         [N][cells]
+  double* pf_w;              // CG w = K u                         [N][cells]
+  double* pf_dg;             // Jacobi diagonal of K               [N][cells]
   double* pf_g;              // dQ_p/dx_d at upper faces           [d][N][cells]
   double eta;                // interface thickness parameter
 };
@@ -539,7 +545,11 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return r;
 }
 
-constexpr int kRedChunk = kRedBlock * 4;    // cells per reduction workgroup
+// Cells per reduction workgroup: a multiple of kRedBlock chosen per instance
+// (Desc::chunk) so that an instance has at most kMaxChunks chunks: small
+// grids still spread over many workgroups, and the per-instance finishers
+// reduce at most kMaxChunks partials per slot.
+constexpr int kMaxChunks = 2048;
 
 // per-workgroup max over its chunk of cells of sum_d (|u_d| + c)/dx_d
 template <int N, int D>
@@ -551,8 +561,8 @@ __global__ __launch_bounds__(kRedBlock) void k_dt(const Desc* __restrict__ descs
   const Desc& d = descs[it.x];
   const Grid& g = d.g;
   const Eos& e = d.e;
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < g.nc ? c0 + kRedChunk : g.nc;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < g.nc ? c0 + d.chunk : g.nc;
   double smax = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     Cons<N, D> c;
@@ -610,8 +620,8 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
   const Desc& d = descs[it.x];
   const Grid& g = d.g;
   const Eos& e = d.e;
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < g.nc ? c0 + kRedChunk : g.nc;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < g.nc ? c0 + d.chunk : g.nc;
   const gdouble* U = gptr(d.U);
   double acc[kDiagSlots];
 #pragma unroll
@@ -656,7 +666,7 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + k] = sh[0];
+    if (threadIdx.x == 0) part[(int64_t)k * d.ps + blockIdx.x] = sh[0];
     __syncthreads();
   }
 }
@@ -673,7 +683,7 @@ __global__ void k_diag_finish(const Desc* __restrict__ descs, const int* __restr
   else if (k == 23) r = -INFINITY;
   else r = 0.0;
   for (int b = start[blockIdx.x]; b < start[blockIdx.x + 1]; ++b) {
-    const double x = part[(int64_t)b * kPartSlots + k];
+    const double x = part[(int64_t)k * d.ps + b];
     if (k == 21 || k == 22 || k == 24) r = fmin(r, x);
     else if (k == 20 || k == 23 || k == 28) r = fmax(r, x);
     else r = r + x;
@@ -724,11 +734,11 @@ __device__ __forceinline__ double block_reduce(double v, double* sh, int op) {
 }
 
 // sum (or max) of slot k of an instance's chunk partials, fixed order
-__device__ __forceinline__ double reduce_chunks(const double* __restrict__ part, int b0, int b1,
-                                                int k, double* sh, int op) {
+__device__ __forceinline__ double reduce_chunks(const double* __restrict__ part, int64_t ps,
+                                                int b0, int b1, int k, double* sh, int op) {
   double v = 0.0;
   for (int b = b0 + (int)threadIdx.x; b < b1; b += kRedBlock) {
-    const double x = part[(int64_t)b * kPartSlots + k];
+    const double x = part[(int64_t)k * ps + b];
     v = op ? fmax(v, x) : v + x;
   }
   return block_reduce(v, sh, op);
@@ -784,8 +794,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_prep(const Desc* __restrict__ 
   const int2 it = locate(map, ninst, blockIdx.x);
   const Desc& d = descs[it.x];
   const int64_t nc = d.g.nc;
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
   const gdouble* U = gptr(d.pfin);
   gdouble* K = gptr(d.pf_k);
   double acc[NS];
@@ -819,7 +829,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_prep(const Desc* __restrict__ 
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double r = block_reduce(acc[k], sh, k == 0 ? 1 : 0);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + k] = r;
+    if (threadIdx.x == 0) part[(int64_t)k * d.ps + blockIdx.x] = r;
   }
 }
 
@@ -833,7 +843,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_setup(const Desc* __restrict__
   const Desc& d = descs[blockIdx.x];
   const int b0 = start[blockIdx.x], b1 = start[blockIdx.x + 1];
   for (int k = 0; k < 1 + N * N + 2 * N; ++k) {
-    const double r = reduce_chunks(part, b0, b1, k, sh, k == 0 ? 1 : 0);
+    const double r = reduce_chunks(part, d.ps, b0, b1, k, sh, k == 0 ? 1 : 0);
     if (threadIdx.x == 0) red[k] = r;
   }
   __syncthreads();
@@ -886,8 +896,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_setup(const Desc* __restrict__
   for (int p = 0; p < N; ++p) s[kPfsB + p] = B[p];
 }
 
-// [div J_p] at every cell; start of the CG solve (residual of the warm start,
-// Jacobi direction) with partials [p] ||b||^2, [N + p] res.z, [2N + p] ||res||^2
+// [div J_p] at every cell; start of the CG solve: the residual of the warm
+// start r = -b - K Q and the Jacobi diagonal; partial [p] ||b||^2
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map, int ninst,
@@ -897,8 +907,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
   const Desc& d = descs[it.x];
   const Grid& g = d.g;
   const int64_t nc = g.nc;
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
   const gdouble* U = gptr(d.pfin);
   const gdouble* K = gptr(d.pf_k);
   const gdouble* s = gptr(d.pfs);
@@ -906,9 +916,9 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
   double B[N];
 #pragma unroll
   for (int p = 0; p < N; ++p) B[p] = s[kPfsB + p];
-  double acc[3 * N];
+  double acc[N];
 #pragma unroll
-  for (int k = 0; k < 3 * N; ++k) acc[k] = 0.0;
+  for (int k = 0; k < N; ++k) acc[k] = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
     double phi[N], sg = 0.0;
@@ -938,64 +948,61 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
       gptr(d.pf_b)[ip] = b;
       // K Q = -b from the previous Q (or 0)
       double Kq = 0.0, dg = 0.0;
+      const gdouble* Kp = K + (int64_t)p * nc;
       if (cold) {
         double dummy;
         gptr(d.pf_q)[ip] = 0.0;
-        k_apply<D>(g, K + (int64_t)p * nc, K + (int64_t)p * nc, i, x, y, dummy, dg);
+        k_apply<D>(g, Kp, Kp, i, x, y, dummy, dg);
       } else {
-        k_apply<D>(g, K + (int64_t)p * nc, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, dg);
+        k_apply<D>(g, Kp, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, dg);
       }
-      const double res = -b - Kq;
-      const double z = dg > 0.0 ? res / dg : 0.0;
-      gptr(d.pf_r)[ip] = res;
-      gptr(d.pf_p)[ip] = z;
+      gptr(d.pf_r)[ip] = -b - Kq;
+      gptr(d.pf_dg)[ip] = dg;
       acc[p] += b * b;
-      acc[N + p] += res * z;
-      acc[2 * N + p] += res * res;
     }
   }
 #pragma unroll
-  for (int k = 0; k < 3 * N; ++k) {
+  for (int k = 0; k < N; ++k) {
     const double r = block_reduce(acc[k], sh, 0);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + k] = r;
+    if (threadIdx.x == 0) part[(int64_t)k * d.ps + blockIdx.x] = r;
   }
 }
 
-// one workgroup per instance: ||b||, first res.z, convergence of the start
+// one workgroup per instance: ||b||^2 of each phase; a phase with b = 0 has
+// nothing to solve (its Q is cleared by the next pass)
 template <int N>
 __global__ __launch_bounds__(kRedBlock) void k_pf_cg_start(const Desc* __restrict__ descs,
                                                            const int* __restrict__ start,
-                                                           const double* __restrict__ part,
-                                                           double rtol) {
+                                                           const double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
-  __shared__ double red[3 * N];
   const Desc& d = descs[blockIdx.x];
-  for (int k = 0; k < 3 * N; ++k) {
-    const double r = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], k, sh, 0);
-    if (threadIdx.x == 0) red[k] = r;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
   gdouble* s = gptr(d.pfs);
-  double res = 0.0;
   for (int p = 0; p < N; ++p) {
-    const double bb = red[p], rr = red[2 * N + p];
-    s[kPfsBB + p] = bb;
-    s[kPfsRZ + p] = red[N + p];
-    const bool done = bb == 0.0 || sqrt(rr) <= rtol * sqrt(bb);
-    s[kPfsDone + p] = done ? 1.0 : 0.0;
-    s[kPfsPits + p] = 0.0;
-    if (bb > 0.0) res = fmax(res, sqrt(rr / bb));
+    const double bb = reduce_chunks(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
+    if (threadIdx.x == 0) {
+      s[kPfsBB + p] = bb;
+      s[kPfsDone + p] = bb == 0.0 ? 1.0 : 0.0;
+      s[kPfsPits + p] = 0.0;
+    }
   }
-  s[kPfsIts] = 0.0;
-  s[kPfsRes] = res;
+  if (threadIdx.x == 0) {
+    s[kPfsIts] = 0.0;
+    s[kPfsRes] = 0.0;
+  }
 }
 
-// CG step 1: Ap = K p, partials [p] p.Ap
+// Conjugate gradients with one reduction per iteration (Chronopoulos and
+// Gear), Jacobi preconditioner u = r / diag(K):
+//   spmv:    w = K u, partials [p] r.u, [N + p] w.u, [2N + p] r.r
+//   scalars: beta = g / g_prev, alpha = g / (delta - beta g / alpha_prev)
+//            (beta = 0, alpha = g / delta on the first iteration); done once
+//            ||r|| <= rtol ||b||
+//   axpy:    p = u + beta p, s = w + beta s, Q += alpha p, r -= alpha s
+// Phases that are done skip their work (the flag is uniform per instance).
 template <int N, int D>
-__global__ __launch_bounds__(kRedBlock) void k_pf_cg_ap(const Desc* __restrict__ descs,
-                                                        const int2* __restrict__ map, int ninst,
-                                                        double* __restrict__ part) {
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_spmv(const Desc* __restrict__ descs,
+                                                          const int2* __restrict__ map, int ninst,
+                                                          double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
   const int2 it = locate(map, ninst, blockIdx.x);
   const Desc& d = descs[it.x];
@@ -1007,132 +1014,89 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_ap(const Desc* __restrict__
 #pragma unroll
   for (int p = 0; p < N; ++p) { live[p] = s[kPfsDone + p] == 0.0; any = any || live[p]; }
   if (!any) return;                       // uniform over the workgroup
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
-  double acc[N];
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
+  double acc[3 * N];
 #pragma unroll
-  for (int p = 0; p < N; ++p) acc[p] = 0.0;
+  for (int k = 0; k < 3 * N; ++k) acc[k] = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       if (!live[p]) continue;
-      double Kp, dg;
-      const gdouble* pp = gptr(d.pf_p) + (int64_t)p * nc;
-      k_apply<D>(g, gptr(d.pf_k) + (int64_t)p * nc, pp, i, x, y, Kp, dg);
-      gptr(d.pf_ap)[(int64_t)p * nc + i] = Kp;
-      acc[p] += pp[i] * Kp;
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < N; ++p) {
-    if (!live[p]) continue;
-    const double r = block_reduce(acc[p], sh, 0);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + p] = r;
-  }
-}
-
-// CG step 2 (one workgroup per instance): alpha = res.z / p.Ap
-template <int N>
-__global__ __launch_bounds__(kRedBlock) void k_pf_cg_alpha(const Desc* __restrict__ descs,
-                                                           const int* __restrict__ start,
-                                                           const double* __restrict__ part) {
-  __shared__ double sh[kRedBlock];
-  const Desc& d = descs[blockIdx.x];
-  gdouble* s = gptr(d.pfs);
-  for (int p = 0; p < N; ++p) {
-    if (s[kPfsDone + p] != 0.0) continue;
-    const double pap = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
-    if (threadIdx.x == 0) {
-      if (pap > 0.0) {
-        s[kPfsAlpha + p] = s[kPfsRZ + p] / pap;
-      } else {                             // breakdown: nothing left to solve
-        s[kPfsAlpha + p] = 0.0;
-        s[kPfsDone + p] = 1.0;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// CG step 3: Q += alpha p, res -= alpha Ap, z = res / diag;
-// partials [p] res.z, [N + p] ||res||^2
-template <int N, int D>
-__global__ __launch_bounds__(kRedBlock) void k_pf_cg_update(const Desc* __restrict__ descs,
-                                                            const int2* __restrict__ map,
-                                                            int ninst, double* __restrict__ part) {
-  __shared__ double sh[kRedBlock];
-  const int2 it = locate(map, ninst, blockIdx.x);
-  const Desc& d = descs[it.x];
-  const Grid& g = d.g;
-  const int64_t nc = g.nc;
-  const gdouble* s = gptr(d.pfs);
-  bool live[N];
-  double al[N];
-  bool any = false;
-#pragma unroll
-  for (int p = 0; p < N; ++p) {
-    live[p] = s[kPfsDone + p] == 0.0;
-    al[p] = s[kPfsAlpha + p];
-    any = any || live[p];
-  }
-  if (!any) return;
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
-  double acc[2 * N];
-#pragma unroll
-  for (int k = 0; k < 2 * N; ++k) acc[k] = 0.0;
-  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
-    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
-#pragma unroll
-    for (int p = 0; p < N; ++p) {
-      if (!live[p]) continue;
-      const int64_t ip = (int64_t)p * nc + i;
-      gptr(d.pf_q)[ip] += al[p] * gptr(d.pf_p)[ip];
-      const double res = gptr(d.pf_r)[ip] - al[p] * gptr(d.pf_ap)[ip];
-      gptr(d.pf_r)[ip] = res;
-      double dummy, dg;
       const gdouble* K = gptr(d.pf_k) + (int64_t)p * nc;
-      k_apply<D>(g, K, K, i, x, y, dummy, dg);
-      const double z = dg > 0.0 ? res / dg : 0.0;
-      acc[p] += res * z;
-      acc[N + p] += res * res;
+      const gdouble* R = gptr(d.pf_r) + (int64_t)p * nc;
+      const gdouble* DG = gptr(d.pf_dg) + (int64_t)p * nc;
+      auto u_at = [&](int64_t j) { return DG[j] > 0.0 ? R[j] / DG[j] : 0.0; };
+      const double ui = u_at(i);
+      double w = 0.0;
+      const double ki = K[i];
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir) {
+        const double r2 = dir == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
+#pragma unroll
+        for (int sg = -1; sg <= 1; sg += 2) {
+          const int64_t j = nbr(g, D, x, y, dir, sg);
+          if (j >= 0) w += 0.5 * (ki + K[j]) * r2 * (ui - u_at(j));
+        }
+      }
+      gptr(d.pf_w)[(int64_t)p * nc + i] = w;
+      const double ri = R[i];
+      acc[p] += ri * ui;
+      acc[N + p] += w * ui;
+      acc[2 * N + p] += ri * ri;
     }
   }
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     if (!live[p]) continue;
-    double r = block_reduce(acc[p], sh, 0);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + p] = r;
-    r = block_reduce(acc[N + p], sh, 0);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * kPartSlots + N + p] = r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double r = block_reduce(acc[k * N + p], sh, 0);
+      if (threadIdx.x == 0) part[(int64_t)(k * N + p) * d.ps + blockIdx.x] = r;
+    }
   }
 }
 
-// CG step 4 (one workgroup per instance): convergence test and beta
 template <int N>
-__global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict__ descs,
-                                                          const int* __restrict__ start,
-                                                          const double* __restrict__ part,
-                                                          double rtol) {
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_scalars(const Desc* __restrict__ descs,
+                                                             const int* __restrict__ start,
+                                                             const double* __restrict__ part,
+                                                             double rtol) {
   __shared__ double sh[kRedBlock];
   const Desc& d = descs[blockIdx.x];
   gdouble* s = gptr(d.pfs);
   double its = s[kPfsIts], rmax = 0.0;
   bool stepped = false;
   for (int p = 0; p < N; ++p) {
-    if (s[kPfsDone + p] != 0.0) continue;
-    const double rz = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
-    const double rr = reduce_chunks(part, start[blockIdx.x], start[blockIdx.x + 1], N + p, sh, 0);
+    if (s[kPfsDone + p] != 0.0) continue;    // uniform over the workgroup
+    const int b0 = start[blockIdx.x], b1 = start[blockIdx.x + 1];
+    const double gam = reduce_chunks(part, d.ps, b0, b1, p, sh, 0);
+    const double del = reduce_chunks(part, d.ps, b0, b1, N + p, sh, 0);
+    const double rr = reduce_chunks(part, d.ps, b0, b1, 2 * N + p, sh, 0);
     stepped = true;
     if (threadIdx.x == 0) {
       const double bb = s[kPfsBB + p];
-      s[kPfsBeta + p] = s[kPfsRZ + p] > 0.0 ? rz / s[kPfsRZ + p] : 0.0;
-      s[kPfsRZ + p] = rz;
-      s[kPfsPits + p] += 1.0;
-      its = fmax(its, s[kPfsPits + p]);
+      const double k = s[kPfsPits + p];
       rmax = fmax(rmax, sqrt(rr / bb));
-      if (sqrt(rr) <= rtol * sqrt(bb)) s[kPfsDone + p] = 1.0;
+      if (sqrt(rr) <= rtol * sqrt(bb)) {
+        s[kPfsDone + p] = 1.0;
+      } else {
+        double beta = 0.0, eta = del;
+        if (k > 0.0) {
+          beta = gam / s[kPfsRZ + p];
+          eta = del - beta * gam / s[kPfsAlpha + p];
+        }
+        if (!(eta > 0.0) || !(gam > 0.0)) {
+          s[kPfsDone + p] = 1.0;               // breakdown: nothing left to solve
+        } else {
+          s[kPfsBeta + p] = beta;
+          s[kPfsAlpha + p] = gam / eta;
+          s[kPfsRZ + p] = gam;
+          s[kPfsPits + p] = k + 1.0;
+          its = fmax(its, k + 1.0);
+        }
+      }
     }
     __syncthreads();
   }
@@ -1142,38 +1106,42 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict
   }
 }
 
-// CG step 5: p = z + beta p
 template <int N, int D>
-__global__ __launch_bounds__(kRedBlock) void k_pf_cg_dir(const Desc* __restrict__ descs,
-                                                         const int2* __restrict__ map, int ninst) {
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict__ descs,
+                                                          const int2* __restrict__ map, int ninst) {
   const int2 it = locate(map, ninst, blockIdx.x);
   const Desc& d = descs[it.x];
-  const Grid& g = d.g;
-  const int64_t nc = g.nc;
+  const int64_t nc = d.g.nc;
   const gdouble* s = gptr(d.pfs);
-  bool live[N];
-  double be[N];
+  bool live[N], first[N];
+  double al[N], be[N];
   bool any = false;
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     live[p] = s[kPfsDone + p] == 0.0;
+    first[p] = s[kPfsPits + p] == 1.0;
+    al[p] = s[kPfsAlpha + p];
     be[p] = s[kPfsBeta + p];
     any = any || live[p];
   }
   if (!any) return;
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
-    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       if (!live[p]) continue;
       const int64_t ip = (int64_t)p * nc + i;
-      double dummy, dg;
-      const gdouble* K = gptr(d.pf_k) + (int64_t)p * nc;
-      k_apply<D>(g, K, K, i, x, y, dummy, dg);
-      const double z = dg > 0.0 ? gptr(d.pf_r)[ip] / dg : 0.0;
-      gptr(d.pf_p)[ip] = z + be[p] * gptr(d.pf_p)[ip];
+      const double dg = gptr(d.pf_dg)[ip];
+      const double r = gptr(d.pf_r)[ip];
+      const double u = dg > 0.0 ? r / dg : 0.0;
+      const double w = gptr(d.pf_w)[ip];
+      const double pp = first[p] ? u : u + be[p] * gptr(d.pf_p)[ip];
+      const double ss = first[p] ? w : w + be[p] * gptr(d.pf_ap)[ip];
+      gptr(d.pf_p)[ip] = pp;
+      gptr(d.pf_ap)[ip] = ss;
+      gptr(d.pf_q)[ip] += al[p] * pp;
+      gptr(d.pf_r)[ip] = r - al[p] * ss;
     }
   }
 }
@@ -1190,8 +1158,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_grad(const Desc* __restrict__ 
   const Grid& g = d.g;
   const int64_t nc = g.nc;
   const gdouble* s = gptr(d.pfs);
-  const int64_t c0 = (int64_t)it.y * kRedChunk;
-  const int64_t c1 = c0 + kRedChunk < nc ? c0 + kRedChunk : nc;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
   const double dt = clip ? *gptr(d.dt) : 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
@@ -1274,29 +1242,28 @@ void launch_y(const Group& G, int stage, int swz, hipStream_t s) {
                      dim3(kYX[V] * kYY[V]), 0, s, G.desc, G.ymap[V], n, stage, swz);
 }
 
-// kind: 0 prep, 1 divJ + CG start, 2 K p, 3 update, 4 direction, 5 gradients
+// kind: 0 prep, 1 divJ + CG start, 2 K u with the dot products, 3 axpy,
+// 5 gradients
 template <int N, int D, int KIND>
 void launch_pf_cells(const Group& G, double* part, int flag, double, hipStream_t s) {
   const int n = (int)G.ids.size();
-  double* pt = part + G.part_off * kPartSlots;
+  double* pt = part + G.part_off;
   const dim3 grid(G.rs[n]), blk(kRedBlock);
   if constexpr (KIND == 0) hipLaunchKernelGGL((k_pf_prep<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
   if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_divj<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt, flag);
-  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_ap<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
-  if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_update<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
-  if constexpr (KIND == 4) hipLaunchKernelGGL((k_pf_cg_dir<N, D>), grid, blk, 0, s, G.desc, G.rmap, n);
+  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_spmv<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
+  if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_axpy<N, D>), grid, blk, 0, s, G.desc, G.rmap, n);
   if constexpr (KIND == 5) hipLaunchKernelGGL((k_pf_grad<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, flag);
 }
 
-// kind: 0 setup (M, B), 1 CG start, 2 alpha, 3 beta
+// kind: 0 setup (M, B), 1 CG start, 2 CG scalars
 template <int N, int KIND>
 void launch_pf_inst(const Group& G, double* part, int, double rtol, hipStream_t s) {
-  const double* pt = part + G.part_off * kPartSlots;
+  const double* pt = part + G.part_off;
   const dim3 grid((unsigned)G.ids.size()), blk(kRedBlock);
   if constexpr (KIND == 0) hipLaunchKernelGGL((k_pf_setup<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
-  if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_cg_start<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
-  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_alpha<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
-  if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_beta<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
+  if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_cg_start<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
+  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_scalars<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
 }
 
 template <int N, int D>
@@ -1310,7 +1277,7 @@ template <int N, int D>
 void launch_diag(const Group& G, double* part, hipStream_t s) {
   const int n = (int)G.ids.size();
   hipLaunchKernelGGL((k_diag<N, D>), dim3(G.rs[n]), dim3(kRedBlock), 0, s, G.desc, G.rmap,
-                     n, part + G.part_off * kPartSlots);
+                     n, part + G.part_off);
 }
 
 struct Table {
@@ -1328,7 +1295,6 @@ void fill_pf(Table& t) {
   t.pfc[1][N][D] = launch_pf_cells<N, D, 1>;
   t.pfc[2][N][D] = launch_pf_cells<N, D, 2>;
   t.pfc[3][N][D] = launch_pf_cells<N, D, 3>;
-  t.pfc[4][N][D] = launch_pf_cells<N, D, 4>;
   t.pfc[5][N][D] = launch_pf_cells<N, D, 5>;
 }
 
@@ -1358,7 +1324,6 @@ void fill(Table& t) {
   t.pfi[0][N] = launch_pf_inst<N, 0>;
   t.pfi[1][N] = launch_pf_inst<N, 1>;
   t.pfi[2][N] = launch_pf_inst<N, 2>;
-  t.pfi[3][N] = launch_pf_inst<N, 3>;
   t.dt[N][1] = launch_dt<N, 1>;
   t.dt[N][2] = launch_dt<N, 2>;
   t.diag[N][1] = launch_diag<N, 1>;
@@ -1394,6 +1359,11 @@ struct mp_weno_ctx {
                               // keeps each small instance on one L2 and costs
                               // a few percent on a single grid)
   hipGraphExec_t graph[2] = {nullptr, nullptr};   // [external dt?]
+  // Phase-Field solve: one captured batch of CG iterations (replayed on
+  // stream), the private stream it is captured on, pinned done flags
+  hipGraphExec_t pf_graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  double* pf_flags = nullptr;
   std::string err;
   int profile = 0;            // Bracket::which
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -1472,36 +1442,64 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
   const double rtol = c->opt.cg_rtol > 0.0 ? c->opt.cg_rtol : 1e-12;
   const int maxit = c->opt.cg_maxit > 0 ? c->opt.cg_maxit : 10000;
   for (const Group& G : c->groups) {
-    T.pfc[0][G.N][G.D](G, c->part, 0, rtol, c->stream);
-    T.pfi[0][G.N](G, c->part, 0, rtol, c->stream);
-    T.pfc[1][G.N][G.D](G, c->part, cold, rtol, c->stream);
-    T.pfi[1][G.N](G, c->part, 0, rtol, c->stream);
+    T.pfc[0][G.N][G.D](G, c->part, 0, rtol, c->stream);     // k, max|u|, integrands
+    T.pfi[0][G.N](G, c->part, 0, rtol, c->stream);          // M, B
+    T.pfc[1][G.N][G.D](G, c->part, cold, rtol, c->stream);  // [div J], r, diag
+    T.pfi[1][G.N](G, c->part, 0, rtol, c->stream);          // ||b||
+    T.pfc[2][G.N][G.D](G, c->part, 0, rtol, c->stream);     // w = K u, dots
+    T.pfi[2][G.N](G, c->part, 0, rtol, c->stream);          // first alpha
   }
   HIPCHK(c, hipGetLastError());
   const size_t n = c->inst.size();
-  std::vector<double> flags(n * kPfsLen);
-  constexpr int kBatch = 16;
+  if (!c->pf_flags)
+    HIPCHK(c, hipHostMalloc((void**)&c->pf_flags, sizeof(double) * n * kPfsLen, 0));
+  // kBatch iterations (p, s, Q, r update; w = K u with the dot products;
+  // alpha, beta, done) for every group; phases that are done skip their work
+  constexpr int kBatch = 32;
+  auto batch = [&](int nb, hipStream_t st) {
+    for (int k = 0; k < nb; ++k)
+      for (const Group& G : c->groups) {
+        T.pfc[3][G.N][G.D](G, c->part, 0, rtol, st);
+        T.pfc[2][G.N][G.D](G, c->part, 0, rtol, st);
+        T.pfi[2][G.N](G, c->part, 0, rtol, st);
+      }
+  };
+  if (!c->pf_graph) {
+    // captured once on a private stream (a context on the null stream can
+    // still replay it) and launched on the context's stream
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t gph;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    batch(kBatch, c->cap_stream);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gph);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+      return fail(c, MP_ERR_HIP, "capture of the Phase-Field solve failed");
+    const hipError_t e3 = hipGraphInstantiate(&c->pf_graph, gph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gph);
+    if (e3 != hipSuccess) {
+      c->pf_graph = nullptr;
+      return fail(c, MP_ERR_HIP, hipGetErrorString(e3));
+    }
+  }
   bool all_done = false;
   for (int it = 0;;) {
-    HIPCHK(c, hipMemcpyAsync(flags.data(), c->pfs, sizeof(double) * flags.size(),
+    HIPCHK(c, hipMemcpyAsync(c->pf_flags, c->pfs, sizeof(double) * n * kPfsLen,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     all_done = true;
     for (size_t i = 0; i < n && all_done; ++i)
       for (int p = 0; p < c->inst[i].N; ++p)
-        if (flags[i * kPfsLen + kPfsDone + p] == 0.0) { all_done = false; break; }
+        if (c->pf_flags[i * kPfsLen + kPfsDone + p] == 0.0) { all_done = false; break; }
     if (all_done || it >= maxit) break;
     const int nb = std::min(kBatch, maxit - it);
     it += nb;
-    for (int k = 0; k < nb; ++k)
-      for (const Group& G : c->groups) {
-        T.pfc[2][G.N][G.D](G, c->part, 0, rtol, c->stream);
-        T.pfi[2][G.N](G, c->part, 0, rtol, c->stream);
-        T.pfc[3][G.N][G.D](G, c->part, 0, rtol, c->stream);
-        T.pfi[3][G.N](G, c->part, 0, rtol, c->stream);
-        T.pfc[4][G.N][G.D](G, c->part, 0, rtol, c->stream);
-      }
-    HIPCHK(c, hipGetLastError());
+    if (nb == kBatch) {
+      HIPCHK(c, hipGraphLaunch(c->pf_graph, c->stream));
+    } else {
+      batch(nb, c->stream);
+      HIPCHK(c, hipGetLastError());
+    }
   }
   for (const Group& G : c->groups) T.pfc[5][G.N][G.D](G, c->part, clip, rtol, c->stream);
   HIPCHK(c, hipGetLastError());
@@ -1535,7 +1533,7 @@ static mp_status enqueue_diag(mp_weno_ctx* c) {
   for (const Group& G : c->groups) {
     T.diag[G.N][G.D](G, c->part, c->stream);
     hipLaunchKernelGGL(k_diag_finish, dim3(G.ids.size()), dim3(64), 0, c->stream, G.desc,
-                       G.rstart, c->part + G.part_off * kPartSlots);
+                       G.rstart, c->part + G.part_off);
   }
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -1568,6 +1566,9 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
   if (!c) return MP_OK;
   for (auto& g : c->graph)
     if (g) (void)hipGraphExecDestroy(g);
+  if (c->pf_graph) (void)hipGraphExecDestroy(c->pf_graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->pf_flags) (void)hipHostFree(c->pf_flags);
   for (auto& e : c->events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -1659,10 +1660,10 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
                     hipMalloc(&I.U2, bytes) == hipSuccess &&
                     (I.D == 1 || hipMalloc(&I.acc, bytes) == hipSuccess) &&
                     (!opt->check_bounds || hipMalloc(&I.backup, bytes) == hipSuccess);
-    // Phase-Field work arrays: k, b, Q, res, p, Kp ([N][cells] each) and the
-    // face gradients ([d][N][cells])
+    // Phase-Field work arrays: k, b, Q, r, p, s, w, diag ([N][cells] each)
+    // and the face gradients ([d][N][cells])
     const bool okpf = !opt->phase_field ||
-        hipMalloc(&I.pf, sizeof(double) * (size_t)(6 + I.D) * I.N * (size_t)I.nc) == hipSuccess;
+        hipMalloc(&I.pf, sizeof(double) * (size_t)(kPfFields + I.D) * I.N * (size_t)I.nc) == hipSuccess;
     if (opt->phase_field) I.pfs = c->pfs + (size_t)i * kPfsLen;
     c->inst.push_back(I);
     if (!ok || !okpf) {
@@ -1737,13 +1738,18 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           d.pf_r = I.pf + 3 * f;
           d.pf_p = I.pf + 4 * f;
           d.pf_ap = I.pf + 5 * f;
-          d.pf_g = I.pf + 6 * f;
+          d.pf_w = I.pf + 6 * f;
+          d.pf_dg = I.pf + 7 * f;
+          d.pf_g = I.pf + 8 * f;
           double h = s.dx[0];
           for (int k = 1; k < I.D; ++k) h = std::min(h, s.dx[k]);
           d.eta = opt->eta_over_dx * h;
         }
+        d.chunk = (int64_t)kRedBlock *
+                  std::max<int64_t>(1, (I.nc + (int64_t)kRedBlock * kMaxChunks - 1) /
+                                           ((int64_t)kRedBlock * kMaxChunks));
         G.hdesc.push_back(d);
-        int64_t top = G.rs.back() + (I.nc + kRedChunk - 1) / kRedChunk;
+        int64_t top = G.rs.back() + (I.nc + d.chunk - 1) / d.chunk;
         G.rs.push_back((int)std::min<int64_t>(top, INT32_MAX));
         for (int v = 0; v < kXVar; ++v) {
           const int64_t nstrip = (g.nx + kXS[v] - 3) / (kXS[v] - 2);
@@ -1813,6 +1819,15 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
     mp_weno_destroy(c);
     return MP_ERR_OOM;
   }
+  // the partials' slot stride is known once every group is built
+  for (Group& G : c->groups) {
+    for (Desc& d : G.hdesc) d.ps = (int64_t)part_total;
+    if (hipMemcpy(G.desc, G.hdesc.data(), sizeof(Desc) * G.hdesc.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      mp_weno_destroy(c);
+      return MP_ERR_HIP;
+    }
+  }
   std::vector<double> zeros(n, 0.0);
   if (hipMemcpy(c->t, zeros.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->steps, zeros.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1824,7 +1839,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
     // Q starts at 0 (the first solve warm-starts from it); scalars cleared
     bool okz = hipMemset(c->pfs, 0, sizeof(double) * n * kPfsLen) == hipSuccess;
     for (const Inst& I : c->inst)
-      okz = okz && hipMemset(I.pf, 0, sizeof(double) * (size_t)(6 + I.D) * I.N * (size_t)I.nc) == hipSuccess;
+      okz = okz && hipMemset(I.pf, 0, sizeof(double) * (size_t)(kPfFields + I.D) * I.N * (size_t)I.nc) == hipSuccess;
     if (!okz || hipDeviceSynchronize() != hipSuccess) {
       mp_weno_destroy(c);
       return MP_ERR_HIP;
@@ -1896,7 +1911,7 @@ mp_status mp_weno_pf_fields(mp_weno_ctx* c, const double* const* U_in, double* c
         HIPCHK(c, hipMemcpyAsync(divj[i], I.pf + f, sizeof(double) * f,
                                  hipMemcpyDeviceToDevice, c->stream));
       if (grad && grad[i])
-        HIPCHK(c, hipMemcpyAsync(grad[i], I.pf + 6 * f, sizeof(double) * I.D * f,
+        HIPCHK(c, hipMemcpyAsync(grad[i], I.pf + 8 * f, sizeof(double) * I.D * f,
                                  hipMemcpyDeviceToDevice, c->stream));
     }
     if (dUdt) st = enqueue_stage(c, 3, 1);
