@@ -191,6 +191,14 @@ mp_status mp_weno_dt(mp_weno_ctx *ctx, double *dt, int32_t where);
  * the time is not advanced. */
 mp_status mp_weno_step(mp_weno_ctx *ctx, const double *dt_dev);
 
+/* nsteps calls of mp_weno_step(ctx, NULL) (the device CFL step).  With
+ * use_graph (and neither profiling, check_bounds nor the Phase-Field step,
+ * which need the host between steps) runs of 16 steps are captured once as
+ * one graph and replayed, so consecutive steps follow each other without a
+ * graph launch between them.  Asynchronous; results identical to nsteps
+ * single steps. */
+mp_status mp_weno_advance(mp_weno_ctx *ctx, int32_t nsteps);
+
 /* Diagnostics per instance, MP_DIAG_LEN doubles each (out[i*MP_DIAG_LEN+k]):
  *   k = 0 .. n_U-1 : sum over cells of U_c times the cell volume
  *   k = 20         : max over cells |sum_p alpha_p - 1|

@@ -72,6 +72,8 @@ def lib():
         L.mp_weno_pf_fields.restype = C.c_int
         L.mp_weno_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
         L.mp_weno_autotune.restype = C.c_int
+        L.mp_weno_advance.argtypes = [vp, C.c_int32]
+        L.mp_weno_advance.restype = C.c_int
         L.mp_weno_dt.argtypes = [vp, vp, C.c_int32]
         L.mp_weno_dt.restype = C.c_int
         L.mp_weno_step.argtypes = [vp, vp]
@@ -97,7 +99,7 @@ def lib():
 
 EXPORTED = ["mp_weno_abi_version", "mp_weno_max_phases", "mp_weno_init",
             "mp_weno_rhs", "mp_weno_pf_fields", "mp_weno_autotune", "mp_weno_dt",
-            "mp_weno_step", "mp_weno_diag",
+            "mp_weno_step", "mp_weno_advance", "mp_weno_diag",
             "mp_weno_set_time", "mp_weno_destroy", "mp_weno_strerror",
             "mp_weno_last_error", "mp_weno_profile", "mp_weno_timing"]
 
@@ -250,6 +252,13 @@ class Solver:
         self._dt_keep = d
         self._enter()
         self._check(lib().mp_weno_step(self.ctx, C.c_void_p(d.data_ptr())))
+        self._leave()
+
+    def advance(self, nsteps):
+        """nsteps SSP-RK3 steps with the device CFL step (runs of 16 steps
+        replay one captured graph when use_graph is on)."""
+        self._enter()
+        self._check(lib().mp_weno_advance(self.ctx, int(nsteps)))
         self._leave()
 
     def diag(self):

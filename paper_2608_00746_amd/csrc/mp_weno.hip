@@ -581,10 +581,12 @@ __global__ __launch_bounds__(kRedBlock) void k_dt(const Desc* __restrict__ descs
   if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
-// one workgroup per instance: dt = cfl / max, clipped to t_end - t
+// one workgroup per instance: dt = cfl / max, clipped to t_end - t; with
+// advance also the instance's time and step count move on (nothing in the
+// RK stages reads them)
 __global__ __launch_bounds__(kRedBlock) void k_dt_finish(
     const Desc* __restrict__ descs, const int* __restrict__ start,
-    const double* __restrict__ part, double cfl) {
+    const double* __restrict__ part, double cfl, int advance) {
   __shared__ double sh[kRedBlock / 64];
   const Desc& d = descs[blockIdx.x];
   double m = 0.0;
@@ -596,6 +598,10 @@ __global__ __launch_bounds__(kRedBlock) void k_dt_finish(
     double dt = cfl / r;
     if (d.t_end > 0.0 && t + dt > d.t_end) dt = d.t_end - t;
     *gptr(d.dt) = dt;
+    if (advance) {
+      *gptr(d.t) = t + dt;
+      *gptr(d.steps) = *gptr(d.steps) + 1.0;
+    }
   }
 }
 
@@ -1224,6 +1230,7 @@ struct Bracket {
 
 using StageFn = void (*)(const Group&, int stage, int swz, hipStream_t);
 using RedFn = void (*)(const Group&, double* part, hipStream_t);
+using DtFn = void (*)(const Group&, double* part, double cfl, int advance, hipStream_t);
 // Phase-Field kernels: per-cell passes over reduction chunks and per-instance
 // finishers (rtol is used by the finishers that test convergence)
 using PfFn = void (*)(const Group&, double* part, int flag, double rtol, hipStream_t);
@@ -1267,10 +1274,12 @@ void launch_pf_inst(const Group& G, double* part, int, double rtol, hipStream_t 
 }
 
 template <int N, int D>
-void launch_dt(const Group& G, double* part, hipStream_t s) {
+void launch_dt(const Group& G, double* part, double cfl, int advance, hipStream_t s) {
   const int n = (int)G.ids.size();
   hipLaunchKernelGGL((k_dt<N, D>), dim3(G.rs[n]), dim3(kRedBlock), 0, s, G.desc, G.rmap,
                      n, part + G.part_off);
+  hipLaunchKernelGGL(k_dt_finish, dim3(n), dim3(kRedBlock), 0, s, G.desc, G.rstart,
+                     part + G.part_off, cfl, advance);
 }
 
 template <int N, int D>
@@ -1283,7 +1292,7 @@ void launch_diag(const Group& G, double* part, hipStream_t s) {
 struct Table {
   StageFn sx[2][kMaxN + 1][3][2][kXVar] = {};   // [PF flux][N][d][precision][shape]
   StageFn sy[2][kMaxN + 1][2][kYVar] = {};
-  RedFn dt[kMaxN + 1][3] = {};
+  DtFn dt[kMaxN + 1][3] = {};
   RedFn diag[kMaxN + 1][3] = {};
   PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
   PfFn pfi[4][kMaxN + 1] = {};             // per-instance PF finishers
@@ -1359,6 +1368,9 @@ struct mp_weno_ctx {
                               // keeps each small instance on one L2 and costs
                               // a few percent on a single grid)
   hipGraphExec_t graph[2] = {nullptr, nullptr};   // [external dt?]
+  // kChain consecutive steps (device CFL step) captured as one graph
+  static constexpr int kChain = 16;
+  hipGraphExec_t chain = nullptr;
   // Phase-Field solve: one captured batch of CG iterations (replayed on
   // stream), the private stream it is captured on, pinned done flags
   hipGraphExec_t pf_graph = nullptr;
@@ -1422,13 +1434,10 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
   return MP_OK;
 }
 
-static mp_status enqueue_dt(mp_weno_ctx* c) {
+// CFL step of every instance; advance: also move time and step count on
+static mp_status enqueue_dt(mp_weno_ctx* c, int advance) {
   const Table& T = table();
-  for (const Group& G : c->groups) {
-    T.dt[G.N][G.D](G, c->part, c->stream);
-    hipLaunchKernelGGL(k_dt_finish, dim3(G.ids.size()), dim3(kRedBlock), 0, c->stream,
-                       G.desc, G.rstart, c->part + G.part_off, c->opt.cfl);
-  }
+  for (const Group& G : c->groups) T.dt[G.N][G.D](G, c->part, c->opt.cfl, advance, c->stream);
   HIPCHK(c, hipGetLastError());
   return MP_OK;
 }
@@ -1507,7 +1516,9 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
   return MP_OK;
 }
 
-static mp_status enqueue_rk(mp_weno_ctx* c) {
+// the RK stages (and the Phase-Field step); advance: move time and step
+// count on at the end (when the CFL kernel did not)
+static mp_status enqueue_rk(mp_weno_ctx* c, bool advance) {
   for (int s = 0; s < 3; ++s) {
     mp_status st = enqueue_stage(c, s);
     if (st != MP_OK) return st;
@@ -1521,9 +1532,11 @@ static mp_status enqueue_rk(mp_weno_ctx* c) {
       if (st != MP_OK) return st;
     }
   }
-  const int n = (int)c->inst.size();
-  hipLaunchKernelGGL(k_advance_time, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->t,
-                     c->steps, c->dt, n);
+  if (advance) {
+    const int n = (int)c->inst.size();
+    hipLaunchKernelGGL(k_advance_time, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->t,
+                       c->steps, c->dt, n);
+  }
   HIPCHK(c, hipGetLastError());
   return MP_OK;
 }
@@ -1566,6 +1579,7 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
   if (!c) return MP_OK;
   for (auto& g : c->graph)
     if (g) (void)hipGraphExecDestroy(g);
+  if (c->chain) (void)hipGraphExecDestroy(c->chain);
   if (c->pf_graph) (void)hipGraphExecDestroy(c->pf_graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->pf_flags) (void)hipHostFree(c->pf_flags);
@@ -1845,6 +1859,10 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       return MP_ERR_HIP;
     }
   }
+  if (hipDeviceSynchronize() != hipSuccess) {   // set-up copies and clears done
+    mp_weno_destroy(c);
+    return MP_ERR_HIP;
+  }
   *out = c;
   return MP_OK;
 }
@@ -1974,6 +1992,7 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
   // a captured step holds the old launch shapes
   for (auto& g : c->graph)
     if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  if (c->chain) { (void)hipGraphExecDestroy(c->chain); c->chain = nullptr; }
   if (choice)
     for (const Group& G : c->groups)
       for (int id : G.ids) {
@@ -1987,7 +2006,7 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
 
 mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
   if (!c || !dt) return fail(c, MP_ERR_ARG, "null argument");
-  mp_status s = enqueue_dt(c);
+  mp_status s = enqueue_dt(c, 0);
   if (s != MP_OK) return s;
   const size_t bytes = sizeof(double) * c->inst.size();
   if (where == MP_WHERE_HOST) {
@@ -1999,12 +2018,49 @@ mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
   return MP_OK;
 }
 
+// One step.  With the device CFL step and no Phase-Field step the CFL kernel
+// moves the time on (nothing later in the step reads it); otherwise it moves
+// at the end, so a failed Phase-Field solve leaves it untouched.
 static mp_status enqueue_step(mp_weno_ctx* c, bool external_dt) {
+  const bool early = !external_dt && !c->opt.phase_field;
   if (!external_dt) {
-    mp_status s = enqueue_dt(c);
+    mp_status s = enqueue_dt(c, early ? 1 : 0);
     if (s != MP_OK) return s;
   }
-  return enqueue_rk(c);
+  return enqueue_rk(c, !early);
+}
+
+mp_status mp_weno_advance(mp_weno_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, MP_ERR_ARG, "bad argument");
+  // steps that need the host between them go one by one
+  if (!c->opt.use_graph || c->profile || c->opt.phase_field || c->opt.check_bounds) {
+    for (int32_t k = 0; k < nsteps; ++k) {
+      const mp_status s = mp_weno_step(c, nullptr);
+      if (s != MP_OK) return s;
+    }
+    return MP_OK;
+  }
+  int32_t left = nsteps;
+  if (left >= mp_weno_ctx::kChain) {
+    if (!c->chain) {
+      hipGraph_t gph;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      mp_status s = MP_OK;
+      for (int k = 0; k < mp_weno_ctx::kChain && s == MP_OK; ++k) s = enqueue_step(c, false);
+      hipError_t e2 = hipStreamEndCapture(c->stream, &gph);
+      if (s != MP_OK) return s;
+      if (e2 != hipSuccess) return fail(c, MP_ERR_HIP, hipGetErrorString(e2));
+      HIPCHK(c, hipGraphInstantiate(&c->chain, gph, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(gph);
+    }
+    for (; left >= mp_weno_ctx::kChain; left -= mp_weno_ctx::kChain)
+      HIPCHK(c, hipGraphLaunch(c->chain, c->stream));
+  }
+  for (; left > 0; --left) {
+    const mp_status s = mp_weno_step(c, nullptr);
+    if (s != MP_OK) return s;
+  }
+  return MP_OK;
 }
 
 mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {

@@ -240,6 +240,29 @@ def test_determinism_and_graph_replay():
         s.close()
 
 
+def test_advance_equals_single_steps():
+    """mp_weno_advance (runs of 16 steps replayed as one graph) gives the same
+    states, time and step count as single steps."""
+    import torch
+    w = I.random_state((40, 260), nphase=2, seed=52, lowp=0.0, opts=I.Options(flux=1, cfl=0.2))
+    st = torch.cuda.Stream()
+    a = _solver(w, stream=st, use_graph=True)
+    b = _solver(w, stream=st)
+    a.advance(37)
+    for _ in range(37):
+        b.step()
+    torch.cuda.synchronize()
+    assert np.array_equal(a.host(0), b.host(0))
+    da, db = a.diag()[0], b.diag()[0]
+    assert da[27] == 37 and np.array_equal(da, db)
+    a.advance(20)          # the captured run is replayed again
+    for _ in range(20):
+        b.step()
+    assert np.array_equal(a.host(0), b.host(0))
+    a.close()
+    b.close()
+
+
 def test_check_bounds_restores_state():
     """An inadmissible input (negative volume fraction) is reported and the
     state is restored (failure handling forced from the host)."""
