@@ -155,8 +155,8 @@ mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
                             double *const *dUdt);
 
 /* Autotuner: for every group of instances with the same (N, d), time the
- * tile shapes of the two sweeps (x strips of 256 or 128 lanes; y tiles of
- * 16 x 16 or 32 x 8 lanes) and the XCD-aware tile order (off / on) on the
+ * tile shapes of the two sweeps (x strips of 256, 128 or 64 lanes; y tiles
+ * of 16 x 16, 32 x 8 or 16 x 24 lanes) and the XCD-aware tile order (off / on) on the
  * current states, reps launches each (0: 5), and keep the fastest for the
  * hyperbolic sweeps of later calls.  The timing evaluates L(U) into the
  * context's stage buffer: the states, the time and the step count are not

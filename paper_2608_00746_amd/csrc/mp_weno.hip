@@ -43,10 +43,10 @@ constexpr int kMaxN = 5;          // phases built
 // x sweep strips of kXS[v] lanes (kXS[v] - 2 output cells), y sweep tiles of
 // kYX[v] x kYY[v] lanes (kYY[v] - 2 output rows).  The Phase-Field sweeps use
 // the defaults.
-constexpr int kXVar = 2, kYVar = 2;
-constexpr int kXS[kXVar] = {256, 128};
-constexpr int kYX[kYVar] = {16, 32};
-constexpr int kYY[kYVar] = {16, 8};
+constexpr int kXVar = 3, kYVar = 3;
+constexpr int kXS[kXVar] = {256, 128, 64};
+constexpr int kYX[kYVar] = {16, 32, 16};
+constexpr int kYY[kYVar] = {16, 8, 24};
 constexpr int kRedBlock = 256;    // reduction workgroup
 constexpr int kDiagSlots = 32;    // per-block partials of the diagnostics
 constexpr int kPartSlots = 40;    // partial slots per reduction chunk (stored slot-major:
@@ -1321,6 +1321,7 @@ template <int N>
 void fill(Table& t) {
   fill_shapes<N, 0>(t);
   fill_shapes<N, 1>(t);
+  fill_shapes<N, 2>(t);
   // the Phase-Field sweeps: default shapes only
   t.sx[1][N][1][0][0] = launch_x<N, 1, double, 1, 0>;
   t.sx[1][N][1][1][0] = launch_x<N, 1, float, 1, 0>;

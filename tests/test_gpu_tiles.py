@@ -43,7 +43,7 @@ def _run(ws, K, env):
     return out
 
 
-@pytest.mark.parametrize("xs,ys", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("xs,ys", [(1, 0), (0, 1), (1, 1), (2, 2)])
 @pytest.mark.parametrize("precision", [I.PREC_FP64, I.PREC_MIXED])
 def test_tile_shapes_bitwise(xs, ys, precision):
     ws = _cases()
@@ -64,9 +64,9 @@ def test_autotune_keeps_state_and_results():
     assert ch.shape == (len(ws), 4)
     for i, w in enumerate(ws):
         assert np.array_equal(a.host(i), before[i])
-        assert ch[i, 0] in (256, 128)
+        assert ch[i, 0] in (256, 128, 64)
         if w.ndim == 2:
-            assert (ch[i, 1], ch[i, 2]) in ((16, 16), (32, 8))
+            assert (ch[i, 1], ch[i, 2]) in ((16, 16), (32, 8), (16, 24))
         else:
             assert ch[i, 1] == 0 and ch[i, 2] == 0
         assert ch[i, 3] in (0, 1)
