@@ -55,7 +55,7 @@ constexpr int kPartSlots = 40;    // partial slots per reduction chunk (stored s
 // M / eta^2, multipliers B_q, CG iterations and relative residual at exit,
 // and per phase ||b||^2, res.z, alpha, beta, done flag, iterations
 constexpr int kPfsLen = 64;
-constexpr int kPfFields = 8;      // Phase-Field work arrays of N fields each
+constexpr int kPfFields = 9;      // Phase-Field work arrays of N fields each
 // floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
 // is solvable for every right side of zero total and stays conditioned; only
 // cells with phi or 1 - phi below ~1e-6 see it
@@ -86,6 +86,21 @@ struct StageArgs {
   int mode;           // 0: write L, 1: RK stage
 };
 
+// One level of the multigrid preconditioner of Eq. (4) for one instance
+// (every array holds the N phases one after the other, [N][nc]).  Level 0 is
+// the grid itself; level l + 1 aggregates 2 x 2 cells of level l (a single
+// cell or row at an odd end) down to one cell.
+struct MgLevel {
+  int nx, ny;
+  int64_t nc;
+  double* wx;        // weight of the face to the +x neighbour (0: no face)
+  double* wy;        // weight of the face to the +y neighbour
+  double* dg;        // diagonal: sum of the cell's face weights
+  double* e;         // correction
+  double* t;         // Jacobi ping-pong
+  double* f;         // right-hand side (level 0: the CG residual)
+};
+
 // One instance as the kernels see it (device memory, read with scalar loads).
 struct Desc {
   Grid g;
@@ -113,7 +128,10 @@ struct Desc {
   double* pf_p;              // CG direction                       [N][cells]
   double* pf_ap;             // CG s = K p                         [N][cells]
   double* pf_w;              // CG w = K u                         [N][cells]
-  double* pf_dg;             // Jacobi diagonal of K               [N][cells]
+  double* pf_dg;             // diagonal of K                      [N][cells]
+  double* pf_u;              // preconditioned residual u = M^-1 r [N][cells]
+  const struct MgLevel* mg;  // multigrid levels of the preconditioner
+  int nlev;
   double* pf_g;              // dQ_p/dx_d at upper faces           [d][N][cells]
   double eta;                // interface thickness parameter
 };
@@ -1032,8 +1050,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_spmv(const Desc* __restrict
       if (!live[p]) continue;
       const gdouble* K = gptr(d.pf_k) + (int64_t)p * nc;
       const gdouble* R = gptr(d.pf_r) + (int64_t)p * nc;
-      const gdouble* DG = gptr(d.pf_dg) + (int64_t)p * nc;
-      auto u_at = [&](int64_t j) { return DG[j] > 0.0 ? R[j] / DG[j] : 0.0; };
+      const gdouble* UU = gptr(d.pf_u) + (int64_t)p * nc;
+      auto u_at = [&](int64_t j) { return UU[j]; };
       const double ui = u_at(i);
       double w = 0.0;
       const double ki = K[i];
@@ -1138,9 +1156,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict
     for (int p = 0; p < N; ++p) {
       if (!live[p]) continue;
       const int64_t ip = (int64_t)p * nc + i;
-      const double dg = gptr(d.pf_dg)[ip];
       const double r = gptr(d.pf_r)[ip];
-      const double u = dg > 0.0 ? r / dg : 0.0;
+      const double u = gptr(d.pf_u)[ip];
       const double w = gptr(d.pf_w)[ip];
       const double pp = first[p] ? u : u + be[p] * gptr(d.pf_p)[ip];
       const double ss = first[p] ? w : w + be[p] * gptr(d.pf_ap)[ip];
@@ -1151,6 +1168,214 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Multigrid preconditioner of the Q solve: a symmetric V-cycle (damped Jacobi
+// before and after the coarse correction, restriction = sum over the 2 x 2
+// aggregate, prolongation = copy to it, the coarse operator the Galerkin
+// product: a coarse face weight is the sum of the fine face weights between
+// the two aggregates).  Symmetric positive semidefinite as CG needs.
+// ---------------------------------------------------------------------------
+constexpr int kMgMaxLev = 16;
+constexpr int kMgCoarseSweeps = 8;    // sweeps on the coarsest level (even)
+constexpr double kMgOmega = 2.0 / 3.0;
+constexpr double kMgCorr = 1.0;       // scale of the coarse-grid correction
+
+// neighbour of cell (x, y) of a level one step along dir; -1 if no face
+__device__ __forceinline__ int64_t lnbr(const Grid& g, int nx, int ny, int x, int y, int dir, int s) {
+  if (dir == 0) {
+    if (nx == 1) return -1;                 // one aggregate: no face
+    int xn = x + s;
+    if (xn < 0) { if (g.bcx0 != MP_BC_PERIODIC) return -1; xn += nx; }
+    if (xn >= nx) { if (g.bcx1 != MP_BC_PERIODIC) return -1; xn -= nx; }
+    return (int64_t)y * nx + xn;
+  }
+  if (ny == 1) return -1;
+  int yn = y + s;
+  if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += ny; }
+  if (yn >= ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= ny; }
+  return (int64_t)yn * nx + x;
+}
+
+// (K v)_i of a level from its face weights
+template <int D>
+__device__ __forceinline__ double lapply(const Grid& g, const MgLevel& L, int p, const gdouble* v,
+                                         int64_t i, int x, int y) {
+  const gdouble* wx = gptr(L.wx) + (int64_t)p * L.nc;
+  const gdouble* wy = gptr(L.wy) + (int64_t)p * L.nc;
+  const double vi = v[i];
+  double r = 0.0;
+  int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
+  if (j >= 0) r += wx[i] * (vi - v[j]);
+  j = lnbr(g, L.nx, L.ny, x, y, 0, -1);
+  if (j >= 0) r += wx[j] * (vi - v[j]);
+  if constexpr (D > 1) {
+    j = lnbr(g, L.nx, L.ny, x, y, 1, 1);
+    if (j >= 0) r += wy[i] * (vi - v[j]);
+    j = lnbr(g, L.nx, L.ny, x, y, 1, -1);
+    if (j >= 0) r += wy[j] * (vi - v[j]);
+  }
+  return r;
+}
+
+// per-level work items: (instance, chunk of 256 cells of that level)
+#define MG_PROLOGUE                                                         \
+  const int2 it = locate(map, ninst, blockIdx.x);                           \
+  const Desc& d = descs[it.x];                                              \
+  const Grid& g = d.g;                                                      \
+  const gdouble* s = gptr(d.pfs);                                           \
+  bool live[N];                                                             \
+  bool any = false;                                                         \
+  _Pragma("unroll") for (int p = 0; p < N; ++p) {                           \
+    live[p] = s[kPfsDone + p] == 0.0;                                       \
+    any = any || live[p];                                                   \
+  }                                                                         \
+  if (!any) return;                                                         \
+  const int64_t i = (int64_t)it.y * kRedBlock + threadIdx.x;
+
+// level-0 face weights from k (frozen over the solve)
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_mg_weights0(const Desc* __restrict__ descs,
+                                                           const int2* __restrict__ map, int ninst) {
+  MG_PROLOGUE
+  const MgLevel L = d.mg[0];
+  if (i >= L.nc) return;
+  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    const gdouble* K = gptr(d.pf_k) + (int64_t)p * L.nc;
+    int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
+    gptr(L.wx)[(int64_t)p * L.nc + i] = j >= 0 ? 0.5 * (K[i] + K[j]) * g.rdx * g.rdx : 0.0;
+    if constexpr (D > 1) {
+      j = lnbr(g, L.nx, L.ny, x, y, 1, 1);
+      gptr(L.wy)[(int64_t)p * L.nc + i] = j >= 0 ? 0.5 * (K[i] + K[j]) * g.rdy * g.rdy : 0.0;
+    }
+  }
+}
+
+// Galerkin face weights of level l + 1 (items over level l + 1)
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_mg_coarsen(const Desc* __restrict__ descs,
+                                                          const int2* __restrict__ map, int ninst,
+                                                          int l) {
+  MG_PROLOGUE
+  const MgLevel F = d.mg[l], C = d.mg[l + 1];
+  if (i >= C.nc) return;
+  const int Y = (int)(i / C.nx), X = (int)(i - (int64_t)Y * C.nx);
+  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    const gdouble* wx = gptr(F.wx) + (int64_t)p * F.nc;
+    const gdouble* wy = gptr(F.wy) + (int64_t)p * F.nc;
+    double cx = 0.0, cy = 0.0;
+    if (C.nx > 1)
+      for (int y = 2 * Y; y <= yt; ++y) cx += wx[(int64_t)y * F.nx + xr];
+    if constexpr (D > 1) {
+      if (C.ny > 1)
+        for (int x = 2 * X; x <= xr; ++x) cy += wy[(int64_t)yt * F.nx + x];
+    }
+    gptr(C.wx)[(int64_t)p * C.nc + i] = cx;
+    if constexpr (D > 1) gptr(C.wy)[(int64_t)p * C.nc + i] = cy;
+  }
+}
+
+// diagonal of a level from its weights
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_mg_diag(const Desc* __restrict__ descs,
+                                                       const int2* __restrict__ map, int ninst,
+                                                       int l) {
+  MG_PROLOGUE
+  const MgLevel L = d.mg[l];
+  if (i >= L.nc) return;
+  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    const gdouble* wx = gptr(L.wx) + (int64_t)p * L.nc;
+    const gdouble* wy = gptr(L.wy) + (int64_t)p * L.nc;
+    double dgv = 0.0;
+    int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
+    if (j >= 0) dgv += wx[i];
+    j = lnbr(g, L.nx, L.ny, x, y, 0, -1);
+    if (j >= 0) dgv += wx[j];
+    if constexpr (D > 1) {
+      j = lnbr(g, L.nx, L.ny, x, y, 1, 1);
+      if (j >= 0) dgv += wy[i];
+      j = lnbr(g, L.nx, L.ny, x, y, 1, -1);
+      if (j >= 0) dgv += wy[j];
+    }
+    gptr(L.dg)[(int64_t)p * L.nc + i] = dgv;
+  }
+}
+
+// one damped Jacobi sweep on level l: mode 0: t = omega f / dg (from e = 0);
+// mode 1: t = e + omega (f - K e) / dg; mode 2: e = t + omega (f - K t) / dg
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_mg_smooth(const Desc* __restrict__ descs,
+                                                         const int2* __restrict__ map, int ninst,
+                                                         int l, int mode) {
+  MG_PROLOGUE
+  const MgLevel L = d.mg[l];
+  if (i >= L.nc) return;
+  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    if (!live[p]) continue;
+    const int64_t ip = (int64_t)p * L.nc + i;
+    const double dgv = gptr(L.dg)[ip];
+    const double fv = gptr(L.f)[ip];
+    if (mode == 0) {
+      gptr(L.t)[ip] = dgv > 0.0 ? kMgOmega * fv / dgv : 0.0;
+      continue;
+    }
+    const gdouble* src = gptr(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
+    gdouble* dst = gptr(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc;
+    const double kv = lapply<D>(g, L, p, src, i, x, y);
+    dst[i] = dgv > 0.0 ? src[i] + kMgOmega * (fv - kv) / dgv : src[i];
+  }
+}
+
+// f(l + 1) = sum over the aggregate of (f - K e) on level l (items over l + 1)
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_mg_restrict(const Desc* __restrict__ descs,
+                                                           const int2* __restrict__ map, int ninst,
+                                                           int l) {
+  MG_PROLOGUE
+  const MgLevel F = d.mg[l], C = d.mg[l + 1];
+  if (i >= C.nc) return;
+  const int Y = (int)(i / C.nx), X = (int)(i - (int64_t)Y * C.nx);
+  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    if (!live[p]) continue;
+    const gdouble* e = gptr(F.e) + (int64_t)p * F.nc;
+    const gdouble* f = gptr(F.f) + (int64_t)p * F.nc;
+    double r = 0.0;
+    for (int y = 2 * Y; y <= yt; ++y)
+      for (int x = 2 * X; x <= xr; ++x) {
+        const int64_t j = (int64_t)y * F.nx + x;
+        r += f[j] - lapply<D>(g, F, p, e, j, x, y);
+      }
+    gptr(C.f)[(int64_t)p * C.nc + i] = r;
+  }
+}
+
+// e(l) += e(l + 1) of the cell's aggregate (items over level l)
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_mg_prolong(const Desc* __restrict__ descs,
+                                                          const int2* __restrict__ map, int ninst,
+                                                          int l) {
+  MG_PROLOGUE
+  const MgLevel F = d.mg[l], C = d.mg[l + 1];
+  if (i >= F.nc) return;
+  const int y = (int)(i / F.nx), x = (int)(i - (int64_t)y * F.nx);
+  const int64_t I = (int64_t)(y >> 1) * C.nx + (x >> 1);
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    if (!live[p]) continue;
+    gptr(F.e)[(int64_t)p * F.nc + i] += kMgCorr * gptr(C.e)[(int64_t)p * C.nc + I];
+  }
+}
+#undef MG_PROLOGUE
 
 // frozen face gradients dQ_p/dx_d at the upper face of every cell: none at an
 // outflow end or for a phase with [div J] = 0 everywhere; clip != 0: limited
@@ -1204,6 +1429,9 @@ struct Inst {
   double* backup = nullptr;
   double* pf = nullptr;            // Phase-Field work arrays (one allocation)
   double* pfs = nullptr;           // Phase-Field scalars (kPfsLen)
+  std::vector<MgLevel> lv;         // multigrid levels (host copy)
+  MgLevel* d_mg = nullptr;         // the same on the device
+  double* mgbuf = nullptr;         // arrays of the levels
 };
 
 // Instances of one (N, d): device descriptor table and tile offsets.
@@ -1220,6 +1448,9 @@ struct Group {
   int swz = -1;                    // XCD order: -1 default rule, 0 off, 1 on
   int* rstart = nullptr;           // reduction-chunk offsets on the device
   size_t part_off = 0;             // this group's reduction partials
+  int nlev = 0;                    // multigrid levels (every instance has them all)
+  int2* lmap[kMgMaxLev] = {};      // work item -> (instance, 256-cell chunk) per level
+  int lcount[kMgMaxLev] = {};
 };
 
 // Optional event pair recorded around one stage (profiling).
@@ -1263,6 +1494,24 @@ void launch_pf_cells(const Group& G, double* part, int flag, double, hipStream_t
   if constexpr (KIND == 5) hipLaunchKernelGGL((k_pf_grad<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, flag);
 }
 
+// multigrid passes over the work items of level l (kind: 0 level-0 weights,
+// 1 coarsen l -> l + 1, 2 diagonal, 3 smooth, 4 restrict l -> l + 1,
+// 5 prolong l + 1 -> l)
+using MgFn = void (*)(const Group&, int kind, int l, int mode, hipStream_t);
+template <int N, int D>
+void launch_mg(const Group& G, int kind, int l, int mode, hipStream_t s) {
+  const int n = (int)G.ids.size();
+  const dim3 blk(kRedBlock);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL((k_mg_weights0<N, D>), dim3(G.lcount[0]), blk, 0, s, G.desc, G.lmap[0], n); break;
+    case 1: hipLaunchKernelGGL((k_mg_coarsen<N, D>), dim3(G.lcount[l + 1]), blk, 0, s, G.desc, G.lmap[l + 1], n, l); break;
+    case 2: hipLaunchKernelGGL((k_mg_diag<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l); break;
+    case 3: hipLaunchKernelGGL((k_mg_smooth<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l, mode); break;
+    case 4: hipLaunchKernelGGL((k_mg_restrict<N, D>), dim3(G.lcount[l + 1]), blk, 0, s, G.desc, G.lmap[l + 1], n, l); break;
+    case 5: hipLaunchKernelGGL((k_mg_prolong<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l); break;
+  }
+}
+
 // kind: 0 setup (M, B), 1 CG start, 2 CG scalars
 template <int N, int KIND>
 void launch_pf_inst(const Group& G, double* part, int, double rtol, hipStream_t s) {
@@ -1296,6 +1545,7 @@ struct Table {
   RedFn diag[kMaxN + 1][3] = {};
   PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
   PfFn pfi[4][kMaxN + 1] = {};             // per-instance PF finishers
+  MgFn mg[kMaxN + 1][3] = {};
 };
 
 template <int N, int D>
@@ -1305,6 +1555,7 @@ void fill_pf(Table& t) {
   t.pfc[2][N][D] = launch_pf_cells<N, D, 2>;
   t.pfc[3][N][D] = launch_pf_cells<N, D, 3>;
   t.pfc[5][N][D] = launch_pf_cells<N, D, 5>;
+  t.mg[N][D] = launch_mg<N, D>;
 }
 
 template <int N, int V>
@@ -1443,6 +1694,45 @@ static mp_status enqueue_dt(mp_weno_ctx* c, int advance) {
   return MP_OK;
 }
 
+// Multigrid: level weights and diagonals for the frozen k (once per solve)
+static void enqueue_mg_setup(mp_weno_ctx* c, hipStream_t st) {
+  const Table& T = table();
+  for (const Group& G : c->groups) {
+    MgFn f = T.mg[G.N][G.D];
+    f(G, 0, 0, 0, st);                               // level-0 weights
+    for (int l = 0; l + 1 < G.nlev; ++l) {
+      f(G, 1, l, 0, st);                             // weights of l + 1
+      f(G, 2, l + 1, 0, st);                         // diagonal of l + 1
+    }
+  }
+}
+
+// u = M^-1 r: one V-cycle per group (two Jacobi sweeps before and after the
+// coarse correction, kMgCoarseSweeps on the coarsest level)
+static void enqueue_vcycle(mp_weno_ctx* c, hipStream_t st) {
+  const Table& T = table();
+  for (const Group& G : c->groups) {
+    MgFn f = T.mg[G.N][G.D];
+    const int Lc = G.nlev - 1;
+    for (int l = 0; l < Lc; ++l) {
+      f(G, 3, l, 0, st);                             // t = omega f / dg
+      f(G, 3, l, 2, st);                             // e = t + omega (f - K t) / dg
+      f(G, 4, l, 0, st);                             // f(l + 1) = R (f - K e)
+    }
+    f(G, 3, Lc, 0, st);
+    f(G, 3, Lc, 2, st);
+    for (int k = 2; k < kMgCoarseSweeps; k += 2) {
+      f(G, 3, Lc, 1, st);
+      f(G, 3, Lc, 2, st);
+    }
+    for (int l = Lc - 1; l >= 0; --l) {
+      f(G, 5, l, 0, st);                             // e += P e(l + 1)
+      f(G, 3, l, 1, st);                             // t = e + omega (f - K e) / dg
+      f(G, 3, l, 2, st);                             // e = t + omega (f - K t) / dg
+    }
+  }
+}
+
 // [div J], the Q solve and the frozen gradients of every instance, from the
 // volume fractions of each descriptor's pfin.  The CG loop is driven from the
 // host: batches of iterations, then a look at the per-phase done flags
@@ -1456,6 +1746,10 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
     T.pfi[0][G.N](G, c->part, 0, rtol, c->stream);          // M, B
     T.pfc[1][G.N][G.D](G, c->part, cold, rtol, c->stream);  // [div J], r, diag
     T.pfi[1][G.N](G, c->part, 0, rtol, c->stream);          // ||b||
+  }
+  enqueue_mg_setup(c, c->stream);
+  enqueue_vcycle(c, c->stream);                              // u = M^-1 r
+  for (const Group& G : c->groups) {
     T.pfc[2][G.N][G.D](G, c->part, 0, rtol, c->stream);     // w = K u, dots
     T.pfi[2][G.N](G, c->part, 0, rtol, c->stream);          // first alpha
   }
@@ -1463,16 +1757,18 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
   const size_t n = c->inst.size();
   if (!c->pf_flags)
     HIPCHK(c, hipHostMalloc((void**)&c->pf_flags, sizeof(double) * n * kPfsLen, 0));
-  // kBatch iterations (p, s, Q, r update; w = K u with the dot products;
-  // alpha, beta, done) for every group; phases that are done skip their work
-  constexpr int kBatch = 32;
+  // kBatch iterations (p, s, Q, r update; u = M^-1 r; w = K u with the dot
+  // products; alpha, beta, done); phases that are done skip their work
+  constexpr int kBatch = 4;
   auto batch = [&](int nb, hipStream_t st) {
-    for (int k = 0; k < nb; ++k)
+    for (int k = 0; k < nb; ++k) {
+      for (const Group& G : c->groups) T.pfc[3][G.N][G.D](G, c->part, 0, rtol, st);
+      enqueue_vcycle(c, st);
       for (const Group& G : c->groups) {
-        T.pfc[3][G.N][G.D](G, c->part, 0, rtol, st);
         T.pfc[2][G.N][G.D](G, c->part, 0, rtol, st);
         T.pfi[2][G.N](G, c->part, 0, rtol, st);
       }
+    }
   };
   if (!c->pf_graph) {
     // captured once on a private stream (a context on the null stream can
@@ -1590,12 +1886,13 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
   }
   for (auto& I : c->inst) {
     (void)hipFree(I.U1); (void)hipFree(I.U2); (void)hipFree(I.acc); (void)hipFree(I.backup);
-    (void)hipFree(I.pf);
+    (void)hipFree(I.pf); (void)hipFree(I.mgbuf); (void)hipFree(I.d_mg);
   }
   for (auto& G : c->groups) {
     (void)hipFree(G.desc); (void)hipFree(G.rmap); (void)hipFree(G.rstart);
     for (auto* m : G.xmap) (void)hipFree(m);
     for (auto* m : G.ymap) (void)hipFree(m);
+    for (auto* m : G.lmap) (void)hipFree(m);
   }
   (void)hipFree(c->dt); (void)hipFree(c->t); (void)hipFree(c->steps); (void)hipFree(c->part);
   (void)hipFree(c->diag); (void)hipFree(c->pfs);
@@ -1703,6 +2000,63 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       for (auto& v : G.xs) v.push_back(0);
       for (auto& v : G.ys) v.push_back(0);
       G.rs.push_back(0);
+      if (opt->phase_field) {
+        // multigrid levels: halve (rounding up) until one cell; every
+        // instance of the group gets the group's largest count (extra
+        // one-cell levels do nothing)
+        for (int id : G.ids) {
+          const Inst& I = c->inst[id];
+          int nx = I.in.n[0], ny = I.D > 1 ? I.in.n[1] : 1, L = 1;
+          while ((nx > 1 || ny > 1) && L < kMgMaxLev) { nx = (nx + 1) / 2; ny = (ny + 1) / 2; ++L; }
+          G.nlev = std::max(G.nlev, L);
+        }
+        for (int id : G.ids) {
+          Inst& I = c->inst[id];
+          int nx = I.in.n[0], ny = I.D > 1 ? I.in.n[1] : 1;
+          size_t tot = 0;
+          std::vector<std::pair<int, int>> dims;
+          for (int l = 0; l < G.nlev; ++l) {
+            dims.emplace_back(nx, ny);
+            tot += (size_t)nx * ny * (l == 0 ? 3 : 6);
+            nx = (nx + 1) / 2;
+            ny = (ny + 1) / 2;
+          }
+          tot *= (size_t)I.N;
+          if (hipMalloc(&I.mgbuf, sizeof(double) * tot) != hipSuccess ||
+              hipMemset(I.mgbuf, 0, sizeof(double) * tot) != hipSuccess ||
+              hipMalloc(&I.d_mg, sizeof(MgLevel) * G.nlev) != hipSuccess) {
+            mp_weno_destroy(c);
+            return MP_ERR_OOM;
+          }
+          double* q = I.mgbuf;
+          const size_t f0 = (size_t)I.N * (size_t)I.nc;
+          for (int l = 0; l < G.nlev; ++l) {
+            MgLevel L;
+            L.nx = dims[l].first;
+            L.ny = dims[l].second;
+            L.nc = (int64_t)L.nx * L.ny;
+            const size_t f = (size_t)I.N * (size_t)L.nc;
+            L.wx = q; q += f;
+            L.wy = q; q += f;
+            L.t = q; q += f;
+            if (l == 0) {
+              L.e = I.pf + 8 * f0;          // u
+              L.f = I.pf + 3 * f0;          // the CG residual
+              L.dg = I.pf + 7 * f0;         // diagonal of K
+            } else {
+              L.e = q; q += f;
+              L.f = q; q += f;
+              L.dg = q; q += f;
+            }
+            I.lv.push_back(L);
+          }
+          if (hipMemcpy(I.d_mg, I.lv.data(), sizeof(MgLevel) * G.nlev,
+                        hipMemcpyHostToDevice) != hipSuccess) {
+            mp_weno_destroy(c);
+            return MP_ERR_HIP;
+          }
+        }
+      }
       for (int id : G.ids) {
         const Inst& I = c->inst[id];
         const mp_weno_instance& s = I.in;
@@ -1755,7 +2109,10 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           d.pf_ap = I.pf + 5 * f;
           d.pf_w = I.pf + 6 * f;
           d.pf_dg = I.pf + 7 * f;
-          d.pf_g = I.pf + 8 * f;
+          d.pf_u = I.pf + 8 * f;
+          d.pf_g = I.pf + 9 * f;
+          d.mg = I.d_mg;
+          d.nlev = (int)I.lv.size();
           double h = s.dx[0];
           for (int k = 1; k < I.D; ++k) h = std::min(h, s.dx[k]);
           d.eta = opt->eta_over_dx * h;
@@ -1787,6 +2144,14 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       G.part_off = part_total;
       part_total += (size_t)G.rs.back();
       const size_t m = G.ids.size();
+      std::vector<int2> lm[kMgMaxLev];
+      for (int l = 0; l < G.nlev; ++l) {
+        for (size_t k = 0; k < m; ++k) {
+          const int64_t ncl = c->inst[G.ids[k]].lv[l].nc;
+          for (int64_t ch = 0; ch * kRedBlock < ncl; ++ch) lm[l].push_back(make_int2((int)k, (int)ch));
+        }
+        G.lcount[l] = (int)lm[l].size();
+      }
       auto tile_map = [m](const std::vector<int>& st) {
         std::vector<int2> v((size_t)st[m]);
         for (size_t k = 0; k < m; ++k)
@@ -1825,6 +2190,10 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         okc = okc && (ym[v].empty() ||
                       hipMemcpy(H.ymap[v], ym[v].data(), sizeof(int2) * ym[v].size(),
                                 hipMemcpyHostToDevice) == hipSuccess);
+      for (int l = 0; l < H.nlev; ++l)
+        okc = okc && hipMalloc(&H.lmap[l], sizeof(int2) * lm[l].size()) == hipSuccess &&
+              hipMemcpy(H.lmap[l], lm[l].data(), sizeof(int2) * lm[l].size(),
+                        hipMemcpyHostToDevice) == hipSuccess;
       if (!okc) {
         mp_weno_destroy(c);
         return MP_ERR_HIP;
@@ -1930,7 +2299,7 @@ mp_status mp_weno_pf_fields(mp_weno_ctx* c, const double* const* U_in, double* c
         HIPCHK(c, hipMemcpyAsync(divj[i], I.pf + f, sizeof(double) * f,
                                  hipMemcpyDeviceToDevice, c->stream));
       if (grad && grad[i])
-        HIPCHK(c, hipMemcpyAsync(grad[i], I.pf + 8 * f, sizeof(double) * I.D * f,
+        HIPCHK(c, hipMemcpyAsync(grad[i], I.pf + 9 * f, sizeof(double) * I.D * f,
                                  hipMemcpyDeviceToDevice, c->stream));
     }
     if (dUdt) st = enqueue_stage(c, 3, 1);
