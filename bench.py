@@ -30,6 +30,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "stage_traffic.md")
+
+
+def kernel_source_hash():
+    """sha256 over the HIP sources (the counters below hold for this code)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2608_00746_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, tiles):
+    """HBM bytes per RK stage (x + y sweep) from the counter table in
+    profiles/ (FETCH_SIZE and WRITE_SIZE runs, scaled by the reference copy),
+    or None when no row matches this workload, precision, tile choice and
+    kernel source."""
+    if not os.path.exists(TRAFFIC_TABLE):
+        return None
+    key = kernel_source_hash()
+    for line in open(TRAFFIC_TABLE):
+        cols = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cols) != 7 or cols[0] in ("workload", "---"):
+            continue
+        wl, prec, tl, src, fetch_kib, write_kib, _ = cols
+        if (wl, prec, tl, src) == (workload, precision, tiles, key):
+            return (float(fetch_kib) + float(write_kib)) * 1024.0
+    return None
 
 
 def workload(name, precision):
@@ -101,6 +132,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="copy a buffer of this many MiB device-to-device once before the "
                          "timed region (a reference kernel of known traffic for counters)")
+    ap.add_argument("--tiles", default=None,
+                    help="fixed tile shapes instead of the autotuner, as "
+                         "x<lanes>/y<X>x<Y>/<plain|xcd> (the form the bench line reports)")
     ap.add_argument("--phase-field", action="store_true",
                     help="end every step with the Phase-Field step (reported separately)")
     args = ap.parse_args()
@@ -113,6 +147,13 @@ def main():
     import torch
     from paper_2608_00746_amd.binding import Solver
 
+    if args.tiles is not None:
+        # shapes by index into the library's candidate lists
+        xs, ys, sw = args.tiles.split("/")
+        yx, yy = (int(v) for v in ys[1:].split("x"))
+        os.environ["MPWENO_XSHAPE"] = str([256, 128, 64].index(int(xs[1:])))
+        os.environ["MPWENO_YSHAPE"] = str([(16, 16), (32, 8), (16, 24), (0, 0)].index((yx, yy)) % 3)
+        os.environ["MPWENO_XCD_SWIZZLE"] = {"plain": "0", "xcd": "1"}[sw]
     ws = workload(args.workload, args.precision)
     from paper_2608_00746_amd import inputs as I
     if args.phase_field:
@@ -122,7 +163,7 @@ def main():
     stream = torch.cuda.Stream()
     s = Solver(ws, stream=stream, use_graph=not args.no_graph)
     cells = sum(w.ncells for w in ws)
-    tiles = None if args.no_autotune else s.autotune()
+    tiles = None if (args.no_autotune or args.tiles) else s.autotune()
 
     s.advance(args.warmup)
     torch.cuda.synchronize()
@@ -171,6 +212,10 @@ def main():
     bytes_launch = sum(8 * w.nU * w.ncells for w in ws) * (2 + 3 + 3) / 3.0
     avg_launch_s = (k_ms / 1e3) / max(k_n, 1)
     achieved = bytes_launch / avg_launch_s / 1e9
+    tiles_key = args.tiles if args.tiles else "default" if tiles is None else ",".join(
+        sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
+                for t in tiles.tolist()}))
+    traffic = measured_traffic(args.workload, precision, tiles_key)
     w0 = ws[0]
     out = {
         "metric": "cell-updates/s",
@@ -195,13 +240,13 @@ def main():
             "flux": ["HLLC", "HLL"][w0.opts.flux],
             "cfl": w0.opts.cfl, "graph": not args.no_graph and not args.phase_field,
             "phase_field": bool(args.phase_field),
-            "tiles": "default" if tiles is None else
+            "tiles": [args.tiles] if args.tiles else "default" if tiles is None else
                      sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
                              for t in tiles.tolist()}),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "RK stage (x sweep + y sweep)",
             "avg_launch_ms": avg_launch_s * 1e3, "launches": k_n,
             "timing": "HIP events around each RK stage on the solver stream, "

@@ -114,8 +114,10 @@ int32_t mp_weno_max_phases(void);
  * captures on the stream); every later call is ordered on it.
  * Allocates the scratch: two RK stage buffers and one direction accumulator
  * per instance (3 n_U doubles per cell) plus small reduction buffers; with
- * phase_field, (8 + d) N doubles per cell more (k_p, [div J_p], Q_p, four CG
- * vectors, the Jacobi diagonal and the face gradients).
+ * phase_field, (9 + d) N doubles per cell more (k_p, [div J_p], Q_p, the CG
+ * vectors r, p, K p, w and u, the diagonal and the face gradients) and the
+ * multigrid hierarchy (3 N doubles per cell on the finest level, 6 N per
+ * cell of each coarser one: about 5 N per cell in 2D, 9 N in 1D).
  * Errors: MP_ERR_ARG (bad sizes, gamma <= 1, dx <= 0, phase_field with
  * eta_over_dx <= 0, ...), MP_ERR_UNSUPPORTED (N or ndim beyond the build),
  * MP_ERR_OOM, MP_ERR_HIP.
