@@ -9,13 +9,21 @@ FP64, WENO-C + HLLC, CFL 0.5.  Prints one JSON line.
                   [--precision fp64|mixed] [--cpu-seconds S]
 
 Inputs are synthetic and seeded (paper_2608_00746_amd.inputs) and resident in
-HBM before the timed region.  The roofline entry reports the stage kernel:
-algorithmic bytes per launch (8 n_U bytes per cell read of the stage state,
-8 n_U per cell read of the step-start state in stages 2 and 3, 8 n_U per cell
-written) over its average launch time, measured with HIP events the library
-records on the kernel's stream around each stage, in a short eager pass right
-after the timed steps (those replay a captured graph, which cannot carry
-readable event timestamps).
+HBM before the timed region.  The roofline entry reports the stage kernel
+(x sweep + y sweep of one RK stage) against both roofs, the one it is closer
+to first:
+* HBM: algorithmic bytes per launch (8 n_U bytes per cell read of the stage
+  state, 8 n_U per cell read of the step-start state in stages 2 and 3, 8 n_U
+  per cell written) over the average launch time;
+* ALU: FP64 flops per launch (FP32 flops count half) over the average launch
+  time against the FP64 vector peak, with the per-cell flop and VALU
+  instruction counts of the counter table in profiles/ (counted per launched
+  lane, so halo and ragged-tail lanes are not charged to the method).
+The launch time is measured with HIP events the library records on the
+kernel's stream around each stage, in a short eager pass right after the
+timed steps (those replay a captured graph, which cannot carry readable event
+timestamps).  `traffic` is the measured HBM bytes per launch from the same
+table, when it holds a row for this workload, tile choice and kernel source.
 """
 from __future__ import annotations
 
@@ -30,7 +38,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "stage_traffic.md")
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 1 FMA (2 flops) x 2.4 GHz
+FP64_PEAK_TFLOPS = 78.6
+# VALU issue ceiling: one wave64 instruction per SIMD every 4 clocks, i.e.
+# 256 x 4 x 16 lane-ops per clock at 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+COUNTER_TABLE = os.path.join(ROOT, "profiles", "stage_counters.md")
 
 
 def kernel_source_hash():
@@ -45,22 +58,31 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tiles):
-    """HBM bytes per RK stage (x + y sweep) from the counter table in
-    profiles/ (FETCH_SIZE and WRITE_SIZE runs, scaled by the reference copy),
-    or None when no row matches this workload, precision, tile choice and
-    kernel source."""
-    if not os.path.exists(TRAFFIC_TABLE):
-        return None
+def stage_counters(workload, precision, tiles):
+    """Counter figures of one RK stage (x sweep + y sweep) from the table in
+    profiles/ (rocprofv3 --pmc runs of this script):
+
+    * traffic: HBM bytes per stage (FETCH_SIZE and WRITE_SIZE runs, scaled by
+      a reference copy), only from the row of this workload, precision, tile
+      choice and kernel source (else None);
+    * flops64, flops32, valu: FP64 and FP32 flops and VALU lane-instructions
+      per cell per stage, counted per launched lane (halo and ragged-tail
+      lanes excluded), from the last row of this workload and precision."""
+    out = {"traffic": None, "flops64": None, "flops32": None, "valu": None}
+    if not os.path.exists(COUNTER_TABLE):
+        return out
     key = kernel_source_hash()
-    for line in open(TRAFFIC_TABLE):
+    for line in open(COUNTER_TABLE):
         cols = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cols) != 7 or cols[0] in ("workload", "---"):
+        if len(cols) != 9 or cols[0] in ("workload",) or cols[0].startswith("---"):
             continue
-        wl, prec, tl, src, fetch_kib, write_kib, _ = cols
-        if (wl, prec, tl, src) == (workload, precision, tiles, key):
-            return (float(fetch_kib) + float(write_kib)) * 1024.0
-    return None
+        wl, prec, tl, src, fetch_kib, write_kib, f64, f32, valu = cols
+        if (wl, prec) != (workload, precision):
+            continue
+        out.update(flops64=float(f64), flops32=float(f32), valu=float(valu))
+        if (tl, src) == (tiles, key):
+            out["traffic"] = (float(fetch_kib) + float(write_kib)) * 1024.0
+    return out
 
 
 def workload(name, precision):
@@ -208,14 +230,40 @@ def main():
 
     ms_step = ms / args.steps
     value = cells * args.steps / (ms / 1e3)
-    nU = ws[0].nU
     bytes_launch = sum(8 * w.nU * w.ncells for w in ws) * (2 + 3 + 3) / 3.0
     avg_launch_s = (k_ms / 1e3) / max(k_n, 1)
     achieved = bytes_launch / avg_launch_s / 1e9
     tiles_key = args.tiles if args.tiles else "default" if tiles is None else ",".join(
         sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
                 for t in tiles.tolist()}))
-    traffic = measured_traffic(args.workload, precision, tiles_key)
+    ctr = stage_counters(args.workload, precision, tiles_key)
+    hbm = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": ctr["traffic"],
+        "bytes_per_launch": bytes_launch,
+    }
+    roof = hbm
+    if ctr["flops64"] is not None:
+        # FP64-equivalent flops: an FP32 flop takes half an FP64 slot
+        flops = (ctr["flops64"] + 0.5 * ctr["flops32"]) * cells
+        tf = flops / avg_launch_s / 1e12
+        alu = {
+            "bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS, "traffic": ctr["traffic"],
+            "flops_per_launch": flops,
+            "valu_issue_frac": ctr["valu"] * cells / avg_launch_s / VALU_LANE_OPS_PEAK,
+        }
+        # the roof the stage is closer to binds it
+        if alu["frac"] > hbm["frac"]:
+            roof = dict(alu, hbm=hbm)
+        else:
+            roof = dict(hbm, alu=alu)
+    roof.update({
+        "kernel": "RK stage (x sweep + y sweep)",
+        "avg_launch_ms": avg_launch_s * 1e3, "launches": k_n,
+        "timing": "HIP events around each RK stage on the solver stream, "
+                  "%d eager steps after the timed region" % prof_steps,
+    })
     w0 = ws[0]
     out = {
         "metric": "cell-updates/s",
@@ -244,15 +292,7 @@ def main():
                      sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
                              for t in tiles.tolist()}),
         },
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "RK stage (x sweep + y sweep)",
-            "avg_launch_ms": avg_launch_s * 1e3, "launches": k_n,
-            "timing": "HIP events around each RK stage on the solver stream, "
-                      "%d eager steps after the timed region" % prof_steps,
-            "bytes_per_launch": bytes_launch,
-        },
+        "roofline": roof,
         "wall_s": wall,
     }
     if len(ws) > 1:

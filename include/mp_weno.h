@@ -94,8 +94,11 @@ typedef struct {
                               Sec. 2.2.1 (Eqs. (4), (5), (28)); 0: off       */
   double cfl;              /* CFL number of the time step (> 0)              */
   double eta_over_dx;      /* eta / min_d dx_d of Eq. (28) (> 0; 1 in Sec. 4) */
-  double cg_rtol;          /* Eq. (4) solve: stop at ||res|| <= cg_rtol ||[div J]||
-                              (<= 0: 1e-12)                                  */
+  double cg_rtol;          /* Eq. (4) solve: stop once the true residual
+                              ||res|| = ||-[div J] - K Q|| <= cg_rtol ||[div J]||
+                              + 64 eps || |[div J]| + |K| |Q| || (the second
+                              term: the rounding floor of res itself); <= 0:
+                              1e-12                                          */
   int32_t cg_maxit;        /* iteration limit of that solve (<= 0: 10000)    */
   int32_t check_bounds;    /* 1: mp_weno_step checks the result (see below)  */
   int32_t use_graph;       /* 1: replay mp_weno_step as a captured HIP graph */
@@ -150,7 +153,8 @@ mp_status mp_weno_rhs(mp_weno_ctx *ctx, const double *const *U_in,
  * hold n_inst non-NULL pointers.  The solve of Eq. (4) starts from Q = 0.
  * Needs phase_field = 1 (else MP_ERR_UNSUPPORTED); synchronises the stream
  * (the solve is driven from the host); MP_ERR_SOLVER if the solve did not
- * reach cg_rtol within cg_maxit iterations.  The parity entry point of the
+ * reach cg_rtol within cg_maxit iterations (over at most 16 restarts of the
+ * conjugate gradients from the current Q; the message names the residual).  The parity entry point of the
  * Phase-Field step. */
 mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
                             double *const *divj, double *const *grad,

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -53,8 +54,9 @@ constexpr int kPartSlots = 40;    // partial slots per reduction chunk (stored s
                                   // slot k of chunk b at k * Desc::ps + b)
 // per-instance Phase-Field scalars (offsets into Desc::pfs): mobility,
 // M / eta^2, multipliers B_q, CG iterations and relative residual at exit,
-// and per phase ||b||^2, res.z, alpha, beta, done flag, iterations
-constexpr int kPfsLen = 64;
+// the multigrid correction scale, and per phase ||b||^2, res.z, alpha, beta,
+// done flag, iterations, mean of the preconditioned residual
+constexpr int kPfsLen = 72;
 constexpr int kPfFields = 9;      // Phase-Field work arrays of N fields each
 // floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
 // is solvable for every right side of zero total and stays conditioned; only
@@ -64,9 +66,16 @@ constexpr double kKFloor = 1e-6;
 // Gauss-Lobatto end weight); the solve's gradient is clipped there, which
 // only happens in nearly pure cells where the capped flux is negligible
 constexpr double kPfCfl = 1.0 / 12.0;
+// Scale of the multigrid coarse-grid correction at the start of every solve:
+// the piecewise-constant prolongation of an aggregation hierarchy undershoots
+// the smooth error by about 2x per level, and over-correcting cuts the CG
+// iterations of the Q solve 3-4x.  The cycle stays symmetric, but repeated
+// over-correction down the levels can cost definiteness; a CG breakdown
+// drops the scale to 1 (the plain V-cycle, positive definite) and restarts.
+constexpr double kMgCorr = 1.8;
 constexpr int kPfsM = 0, kPfsMe2 = 1, kPfsB = 2, kPfsIts = 10, kPfsRes = 11,
-              kPfsBB = 16, kPfsRZ = 24, kPfsAlpha = 32, kPfsBeta = 40,
-              kPfsDone = 48, kPfsPits = 56;
+              kPfsCorr = 12, kPfsBB = 16, kPfsRZ = 24, kPfsAlpha = 32, kPfsBeta = 40,
+              kPfsDone = 48, kPfsPits = 56, kPfsUbar = 64;
 
 // The state pointers come from a table in device memory, so the compiler
 // cannot tell their address space and would emit flat loads and stores (which
@@ -590,7 +599,9 @@ __global__ __launch_bounds__(kRedBlock) void k_dt(const Desc* __restrict__ descs
     double rho = 0.0;
 #pragma unroll
     for (int p = 0; p < N; ++p) rho += v.m[p];
-    const double cs = sound_speed(mix_rc2<N>(v.a, v.P, e, g.model), rho);
+    double num, den;
+    mix_rc2_parts<N>(v.a, v.P, e, g.model, num, den);
+    const double cs = sound_speed(num, den, rho);
     double s = (fabs(v.u[0]) + cs) * g.rdx;
     if constexpr (D > 1) s += (fabs(v.u[1]) + cs) * g.rdy;
     smax = fmax(smax, s);
@@ -783,12 +794,13 @@ __device__ __forceinline__ int64_t nbr(const Grid& g, int D, int x, int y, int d
   return (int64_t)yn * g.nx + x;
 }
 
-// (K v)_i and the Jacobi diagonal for phase p at cell i
+// (K v)_i, (|K| |v|)_i and the Jacobi diagonal for phase p at cell i
 template <int D>
 __device__ __forceinline__ void k_apply(const Grid& g, const gdouble* __restrict__ k,
                                         const gdouble* __restrict__ v, int64_t i, int x, int y,
-                                        double& Kv, double& diag) {
+                                        double& Kv, double& aKv, double& diag) {
   Kv = 0.0;
+  aKv = 0.0;
   diag = 0.0;
   const double ki = k[i], vi = v[i];
 #pragma unroll
@@ -800,6 +812,7 @@ __device__ __forceinline__ void k_apply(const Grid& g, const gdouble* __restrict
       if (j >= 0) {
         const double kf = 0.5 * (ki + k[j]) * r2;
         Kv += kf * (vi - v[j]);
+        aKv += kf * (fabs(vi) + fabs(v[j]));
         diag += kf;
       }
     }
@@ -918,10 +931,17 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_setup(const Desc* __restrict__
   s[kPfsMe2] = Me2;
 #pragma unroll
   for (int p = 0; p < N; ++p) s[kPfsB + p] = B[p];
+  s[kPfsIts] = 0.0;
+  s[kPfsRes] = 0.0;
+  s[kPfsCorr] = kMgCorr;
+#pragma unroll
+  for (int p = 0; p < N; ++p) s[kPfsPits + p] = 0.0;
 }
 
-// [div J_p] at every cell; start of the CG solve: the residual of the warm
-// start r = -b - K Q and the Jacobi diagonal; partial [p] ||b||^2
+// [div J_p] at every cell; start (or restart) of the CG solve: the residual
+// of the warm start r = -b - K Q and the Jacobi diagonal; partials [p]
+// ||b||^2, [N + p] ||r||^2 and [2N + p] || |b| + |K| |Q| ||^2 (the scale of
+// the rounding error of r)
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map, int ninst,
@@ -940,9 +960,9 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
   double B[N];
 #pragma unroll
   for (int p = 0; p < N; ++p) B[p] = s[kPfsB + p];
-  double acc[N];
+  double acc[3 * N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 3 * N; ++k) acc[k] = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
     double phi[N], sg = 0.0;
@@ -971,62 +991,96 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
       const int64_t ip = (int64_t)p * nc + i;
       gptr(d.pf_b)[ip] = b;
       // K Q = -b from the previous Q (or 0)
-      double Kq = 0.0, dg = 0.0;
+      double Kq = 0.0, aKq = 0.0, dg = 0.0;
       const gdouble* Kp = K + (int64_t)p * nc;
       if (cold) {
-        double dummy;
+        double dummy, dummy2;
         gptr(d.pf_q)[ip] = 0.0;
-        k_apply<D>(g, Kp, Kp, i, x, y, dummy, dg);
+        k_apply<D>(g, Kp, Kp, i, x, y, dummy, dummy2, dg);
       } else {
-        k_apply<D>(g, Kp, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, dg);
+        k_apply<D>(g, Kp, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, aKq, dg);
       }
-      gptr(d.pf_r)[ip] = -b - Kq;
+      const double r = -b - Kq;
+      gptr(d.pf_r)[ip] = r;
       gptr(d.pf_dg)[ip] = dg;
       acc[p] += b * b;
+      acc[N + p] += r * r;
+      const double sc = fabs(b) + aKq;
+      acc[2 * N + p] += sc * sc;
     }
   }
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
+  for (int k = 0; k < 3 * N; ++k) {
     const double r = block_reduce(acc[k], sh, 0);
     if (threadIdx.x == 0) part[(int64_t)k * d.ps + blockIdx.x] = r;
   }
 }
 
-// one workgroup per instance: ||b||^2 of each phase; a phase with b = 0 has
-// nothing to solve (its Q is cleared by the next pass)
+// one workgroup per instance, at the start of the solve and after every run
+// of iterations: ||b||^2 and the true residual ||r|| = ||-b - K Q|| of each
+// phase.  A phase with b = 0 has nothing to solve (its Q is cleared by the
+// gradient pass); one with ||r|| <= rtol ||b|| + 64 eps || |b| + |K| |Q| ||
+// is done (the second term is the rounding floor of r itself, which a badly
+// scaled Q can lift above rtol ||b||); any other starts CG afresh from its
+// Q.  The residual reported at exit is this true one.
 template <int N>
 __global__ __launch_bounds__(kRedBlock) void k_pf_cg_start(const Desc* __restrict__ descs,
                                                            const int* __restrict__ start,
-                                                           const double* __restrict__ part) {
+                                                           const double* __restrict__ part,
+                                                           double rtol) {
   __shared__ double sh[kRedBlock];
   const Desc& d = descs[blockIdx.x];
   gdouble* s = gptr(d.pfs);
+  double rmax = 0.0;
   for (int p = 0; p < N; ++p) {
     const double bb = reduce_chunks(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
+    const double rr = reduce_chunks(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], N + p, sh, 0);
+    const double fl = reduce_chunks(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], 2 * N + p, sh, 0);
     if (threadIdx.x == 0) {
       s[kPfsBB + p] = bb;
-      s[kPfsDone + p] = bb == 0.0 ? 1.0 : 0.0;
+      const bool done = bb == 0.0 || sqrt(rr) <= rtol * sqrt(bb) + 64.0 * DBL_EPSILON * sqrt(fl);
+      if (bb > 0.0) rmax = fmax(rmax, sqrt(rr / bb));
+      // a phase that iterated and still misses the tolerance: its recurrence
+      // drifted from the true residual; restart with the plain correction
+      if (!done && s[kPfsPits + p] > 0.0) s[kPfsCorr] = 1.0;
+      s[kPfsDone + p] = done ? 1.0 : 0.0;
       s[kPfsPits + p] = 0.0;
     }
   }
-  if (threadIdx.x == 0) {
-    s[kPfsIts] = 0.0;
-    s[kPfsRes] = 0.0;
-  }
+  if (threadIdx.x == 0) s[kPfsRes] = rmax;
 }
 
-// Conjugate gradients with one reduction per iteration (Chronopoulos and
-// Gear), Jacobi preconditioner u = r / diag(K):
-//   spmv:    w = K u, partials [p] r.u, [N + p] w.u, [2N + p] r.r
-//   scalars: beta = g / g_prev, alpha = g / (delta - beta g / alpha_prev)
-//            (beta = 0, alpha = g / delta on the first iteration); done once
-//            ||r|| <= rtol ||b||
-//   axpy:    p = u + beta p, s = w + beta s, Q += alpha p, r -= alpha s
+// Preconditioned conjugate gradients, z = M^-1 r the multigrid V-cycle below.
+// One iteration is five passes (and the V-cycle):
+//   dir:    p = (z - mean z) + beta p_prev (p = z - mean z the first time),
+//           q = K p, partial [p] p.q
+//   alpha:  alpha = r.z / p.q
+//   axpy:   Q += alpha p, r -= alpha q
+//   (V-cycle: z = M^-1 r)
+//   dots:   partials [p] r.z, [N + p] r.r, [2N + p] sum z, [3N + p] sum r
+//   beta:   done once the recurrence's ||r|| <= rtol ||b|| (then checked
+//           against the true residual by the start pass); else
+//           beta = r.z' / (r.z')_prev with z' = z - mean z, i.e.
+//           r.z' = r.z - mean z sum r
+// The directions alternate between two buffers (p at neighbours is read
+// while the new one is written).  K is singular (its null space: the
+// constants; faces at outflow ends carry no flux) and the V-cycle's output
+// carries a constant part, which K maps to zero but which would pile up in Q
+// (the over-corrected cycle amplifies it level by level) until Q's rounding
+// hides the solution: the directions are kept free of it.  A non-positive
+// p.q or r.z (the scaled cycle lost definiteness, or round-off) stops the
+// phase and drops the cycle to the plain correction for the restart.
 // Phases that are done skip their work (the flag is uniform per instance).
+
+// direction buffer of the k-th direction (k >= 1) of a phase
+__device__ __forceinline__ gdouble* pf_dirbuf(const Desc& d, double k) {
+  return gptr(((long long)k & 1) ? d.pf_p : d.pf_w);
+}
+
 template <int N, int D>
-__global__ __launch_bounds__(kRedBlock) void k_pf_cg_spmv(const Desc* __restrict__ descs,
-                                                          const int2* __restrict__ map, int ninst,
-                                                          double* __restrict__ part) {
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_dir(const Desc* __restrict__ descs,
+                                                         const int2* __restrict__ map, int ninst,
+                                                         double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
   const int2 it = locate(map, ninst, blockIdx.x);
   const Desc& d = descs[it.x];
@@ -1040,93 +1094,66 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_spmv(const Desc* __restrict
   if (!any) return;                       // uniform over the workgroup
   const int64_t c0 = (int64_t)it.y * d.chunk;
   const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
-  double acc[3 * N];
+  double acc[N];
 #pragma unroll
-  for (int k = 0; k < 3 * N; ++k) acc[k] = 0.0;
+  for (int k = 0; k < N; ++k) acc[k] = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
     const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       if (!live[p]) continue;
+      const double k = s[kPfsPits + p];
+      const bool first = k == 1.0;
+      const double be = s[kPfsBeta + p], zb = s[kPfsUbar + p];
       const gdouble* K = gptr(d.pf_k) + (int64_t)p * nc;
-      const gdouble* R = gptr(d.pf_r) + (int64_t)p * nc;
-      const gdouble* UU = gptr(d.pf_u) + (int64_t)p * nc;
-      auto u_at = [&](int64_t j) { return UU[j]; };
-      const double ui = u_at(i);
-      double w = 0.0;
+      const gdouble* Z = gptr(d.pf_u) + (int64_t)p * nc;
+      const gdouble* P0 = pf_dirbuf(d, k + 1.0) + (int64_t)p * nc;
+      auto dir_at = [&](int64_t j) { return first ? Z[j] - zb : (Z[j] - zb) + be * P0[j]; };
+      const double pi = dir_at(i);
+      double q = 0.0;
       const double ki = K[i];
 #pragma unroll
-      for (int dir = 0; dir < D; ++dir) {
-        const double r2 = dir == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
+      for (int dd = 0; dd < D; ++dd) {
+        const double r2 = dd == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
 #pragma unroll
         for (int sg = -1; sg <= 1; sg += 2) {
-          const int64_t j = nbr(g, D, x, y, dir, sg);
-          if (j >= 0) w += 0.5 * (ki + K[j]) * r2 * (ui - u_at(j));
+          const int64_t j = nbr(g, D, x, y, dd, sg);
+          if (j >= 0) q += 0.5 * (ki + K[j]) * r2 * (pi - dir_at(j));
         }
       }
-      gptr(d.pf_w)[(int64_t)p * nc + i] = w;
-      const double ri = R[i];
-      acc[p] += ri * ui;
-      acc[N + p] += w * ui;
-      acc[2 * N + p] += ri * ri;
+      pf_dirbuf(d, k)[(int64_t)p * nc + i] = pi;
+      gptr(d.pf_ap)[(int64_t)p * nc + i] = q;
+      acc[p] += pi * q;
     }
   }
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     if (!live[p]) continue;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double r = block_reduce(acc[k * N + p], sh, 0);
-      if (threadIdx.x == 0) part[(int64_t)(k * N + p) * d.ps + blockIdx.x] = r;
-    }
+    const double r = block_reduce(acc[p], sh, 0);
+    if (threadIdx.x == 0) part[(int64_t)p * d.ps + blockIdx.x] = r;
   }
 }
 
 template <int N>
-__global__ __launch_bounds__(kRedBlock) void k_pf_cg_scalars(const Desc* __restrict__ descs,
-                                                             const int* __restrict__ start,
-                                                             const double* __restrict__ part,
-                                                             double rtol) {
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_alpha(const Desc* __restrict__ descs,
+                                                           const int* __restrict__ start,
+                                                           const double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
   const Desc& d = descs[blockIdx.x];
   gdouble* s = gptr(d.pfs);
-  double its = s[kPfsIts], rmax = 0.0;
-  bool stepped = false;
   for (int p = 0; p < N; ++p) {
     if (s[kPfsDone + p] != 0.0) continue;    // uniform over the workgroup
-    const int b0 = start[blockIdx.x], b1 = start[blockIdx.x + 1];
-    const double gam = reduce_chunks(part, d.ps, b0, b1, p, sh, 0);
-    const double del = reduce_chunks(part, d.ps, b0, b1, N + p, sh, 0);
-    const double rr = reduce_chunks(part, d.ps, b0, b1, 2 * N + p, sh, 0);
-    stepped = true;
+    const double pq = reduce_chunks(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
     if (threadIdx.x == 0) {
-      const double bb = s[kPfsBB + p];
-      const double k = s[kPfsPits + p];
-      rmax = fmax(rmax, sqrt(rr / bb));
-      if (sqrt(rr) <= rtol * sqrt(bb)) {
+      const double rz = s[kPfsRZ + p];
+      if (!(pq > 0.0) || !(rz > 0.0)) {
         s[kPfsDone + p] = 1.0;
+        s[kPfsCorr] = 1.0;
       } else {
-        double beta = 0.0, eta = del;
-        if (k > 0.0) {
-          beta = gam / s[kPfsRZ + p];
-          eta = del - beta * gam / s[kPfsAlpha + p];
-        }
-        if (!(eta > 0.0) || !(gam > 0.0)) {
-          s[kPfsDone + p] = 1.0;               // breakdown: nothing left to solve
-        } else {
-          s[kPfsBeta + p] = beta;
-          s[kPfsAlpha + p] = gam / eta;
-          s[kPfsRZ + p] = gam;
-          s[kPfsPits + p] = k + 1.0;
-          its = fmax(its, k + 1.0);
-        }
+        s[kPfsAlpha + p] = rz / pq;
       }
     }
     __syncthreads();
-  }
-  if (threadIdx.x == 0 && stepped) {
-    s[kPfsIts] = its;
-    s[kPfsRes] = rmax;
   }
 }
 
@@ -1137,15 +1164,14 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict
   const Desc& d = descs[it.x];
   const int64_t nc = d.g.nc;
   const gdouble* s = gptr(d.pfs);
-  bool live[N], first[N];
-  double al[N], be[N];
+  bool live[N];
+  double al[N], kk[N];
   bool any = false;
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     live[p] = s[kPfsDone + p] == 0.0;
-    first[p] = s[kPfsPits + p] == 1.0;
     al[p] = s[kPfsAlpha + p];
-    be[p] = s[kPfsBeta + p];
+    kk[p] = s[kPfsPits + p];
     any = any || live[p];
   }
   if (!any) return;
@@ -1156,16 +1182,97 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict
     for (int p = 0; p < N; ++p) {
       if (!live[p]) continue;
       const int64_t ip = (int64_t)p * nc + i;
-      const double r = gptr(d.pf_r)[ip];
-      const double u = gptr(d.pf_u)[ip];
-      const double w = gptr(d.pf_w)[ip];
-      const double pp = first[p] ? u : u + be[p] * gptr(d.pf_p)[ip];
-      const double ss = first[p] ? w : w + be[p] * gptr(d.pf_ap)[ip];
-      gptr(d.pf_p)[ip] = pp;
-      gptr(d.pf_ap)[ip] = ss;
-      gptr(d.pf_q)[ip] += al[p] * pp;
-      gptr(d.pf_r)[ip] = r - al[p] * ss;
+      gptr(d.pf_q)[ip] += al[p] * pf_dirbuf(d, kk[p])[ip];
+      gptr(d.pf_r)[ip] -= al[p] * gptr(d.pf_ap)[ip];
     }
+  }
+}
+
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_dots(const Desc* __restrict__ descs,
+                                                          const int2* __restrict__ map, int ninst,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  const int2 it = locate(map, ninst, blockIdx.x);
+  const Desc& d = descs[it.x];
+  const int64_t nc = d.g.nc;
+  const gdouble* s = gptr(d.pfs);
+  bool live[N];
+  bool any = false;
+#pragma unroll
+  for (int p = 0; p < N; ++p) { live[p] = s[kPfsDone + p] == 0.0; any = any || live[p]; }
+  if (!any) return;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
+  double acc[4 * N];
+#pragma unroll
+  for (int k = 0; k < 4 * N; ++k) acc[k] = 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      if (!live[p]) continue;
+      const int64_t ip = (int64_t)p * nc + i;
+      const double r = gptr(d.pf_r)[ip], z = gptr(d.pf_u)[ip];
+      acc[p] += r * z;
+      acc[N + p] += r * r;
+      acc[2 * N + p] += z;
+      acc[3 * N + p] += r;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    if (!live[p]) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double r = block_reduce(acc[k * N + p], sh, 0);
+      if (threadIdx.x == 0) part[(int64_t)(k * N + p) * d.ps + blockIdx.x] = r;
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict__ descs,
+                                                          const int* __restrict__ start,
+                                                          const double* __restrict__ part,
+                                                          double rtol) {
+  __shared__ double sh[kRedBlock];
+  const Desc& d = descs[blockIdx.x];
+  gdouble* s = gptr(d.pfs);
+  double rmax = 0.0;
+  bool stepped = false, adv = false;
+  for (int p = 0; p < N; ++p) {
+    if (s[kPfsDone + p] != 0.0) continue;    // uniform over the workgroup
+    const int b0 = start[blockIdx.x], b1 = start[blockIdx.x + 1];
+    const double rz0 = reduce_chunks(part, d.ps, b0, b1, p, sh, 0);
+    const double rr = reduce_chunks(part, d.ps, b0, b1, N + p, sh, 0);
+    const double zs = reduce_chunks(part, d.ps, b0, b1, 2 * N + p, sh, 0);
+    const double rs = reduce_chunks(part, d.ps, b0, b1, 3 * N + p, sh, 0);
+    const double zb = zs / (double)d.g.nc;
+    const double rz = rz0 - zb * rs;
+    stepped = true;
+    if (threadIdx.x == 0) {
+      const double bb = s[kPfsBB + p];
+      const double k = s[kPfsPits + p];
+      rmax = fmax(rmax, sqrt(rr / bb));
+      if (sqrt(rr) <= rtol * sqrt(bb)) {
+        s[kPfsDone + p] = 1.0;
+      } else if (!(rz > 0.0)) {
+        s[kPfsDone + p] = 1.0;                 // breakdown: restart
+        s[kPfsCorr] = 1.0;
+      } else {
+        s[kPfsBeta + p] = k > 0.0 ? rz / s[kPfsRZ + p] : 0.0;
+        s[kPfsRZ + p] = rz;
+        s[kPfsUbar + p] = zb;
+        s[kPfsPits + p] = k + 1.0;
+        adv = true;
+      }
+    }
+    __syncthreads();
+  }
+  // iterations of the solve, over its restarts
+  if (threadIdx.x == 0 && stepped) {
+    if (adv) s[kPfsIts] = s[kPfsIts] + 1.0;
+    s[kPfsRes] = rmax;
   }
 }
 
@@ -1174,12 +1281,12 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict
 // before and after the coarse correction, restriction = sum over the 2 x 2
 // aggregate, prolongation = copy to it, the coarse operator the Galerkin
 // product: a coarse face weight is the sum of the fine face weights between
-// the two aggregates).  Symmetric positive semidefinite as CG needs.
+// the two aggregates).  Symmetric; positive semidefinite as CG needs with the
+// plain coarse correction (see kMgCorr for the scaled one).
 // ---------------------------------------------------------------------------
 constexpr int kMgMaxLev = 16;
 constexpr int kMgCoarseSweeps = 8;    // sweeps on the coarsest level (even)
 constexpr double kMgOmega = 2.0 / 3.0;
-constexpr double kMgCorr = 1.0;       // scale of the coarse-grid correction
 
 // neighbour of cell (x, y) of a level one step along dir; -1 if no face
 __device__ __forceinline__ int64_t lnbr(const Grid& g, int nx, int ny, int x, int y, int dir, int s) {
@@ -1367,12 +1474,13 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_prolong(const Desc* __restrict
   MG_PROLOGUE
   const MgLevel F = d.mg[l], C = d.mg[l + 1];
   if (i >= F.nc) return;
+  const double corr = s[kPfsCorr];
   const int y = (int)(i / F.nx), x = (int)(i - (int64_t)y * F.nx);
   const int64_t I = (int64_t)(y >> 1) * C.nx + (x >> 1);
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     if (!live[p]) continue;
-    gptr(F.e)[(int64_t)p * F.nc + i] += kMgCorr * gptr(C.e)[(int64_t)p * C.nc + I];
+    gptr(F.e)[(int64_t)p * F.nc + i] += corr * gptr(C.e)[(int64_t)p * C.nc + I];
   }
 }
 #undef MG_PROLOGUE
@@ -1489,8 +1597,9 @@ void launch_pf_cells(const Group& G, double* part, int flag, double, hipStream_t
   const dim3 grid(G.rs[n]), blk(kRedBlock);
   if constexpr (KIND == 0) hipLaunchKernelGGL((k_pf_prep<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
   if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_divj<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt, flag);
-  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_spmv<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
+  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_dir<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
   if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_axpy<N, D>), grid, blk, 0, s, G.desc, G.rmap, n);
+  if constexpr (KIND == 4) hipLaunchKernelGGL((k_pf_cg_dots<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
   if constexpr (KIND == 5) hipLaunchKernelGGL((k_pf_grad<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, flag);
 }
 
@@ -1518,8 +1627,9 @@ void launch_pf_inst(const Group& G, double* part, int, double rtol, hipStream_t 
   const double* pt = part + G.part_off;
   const dim3 grid((unsigned)G.ids.size()), blk(kRedBlock);
   if constexpr (KIND == 0) hipLaunchKernelGGL((k_pf_setup<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
-  if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_cg_start<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
-  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_scalars<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
+  if constexpr (KIND == 1) hipLaunchKernelGGL((k_pf_cg_start<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
+  if constexpr (KIND == 2) hipLaunchKernelGGL((k_pf_cg_alpha<N>), grid, blk, 0, s, G.desc, G.rstart, pt);
+  if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_beta<N>), grid, blk, 0, s, G.desc, G.rstart, pt, rtol);
 }
 
 template <int N, int D>
@@ -1554,6 +1664,7 @@ void fill_pf(Table& t) {
   t.pfc[1][N][D] = launch_pf_cells<N, D, 1>;
   t.pfc[2][N][D] = launch_pf_cells<N, D, 2>;
   t.pfc[3][N][D] = launch_pf_cells<N, D, 3>;
+  t.pfc[4][N][D] = launch_pf_cells<N, D, 4>;
   t.pfc[5][N][D] = launch_pf_cells<N, D, 5>;
   t.mg[N][D] = launch_mg<N, D>;
 }
@@ -1585,6 +1696,7 @@ void fill(Table& t) {
   t.pfi[0][N] = launch_pf_inst<N, 0>;
   t.pfi[1][N] = launch_pf_inst<N, 1>;
   t.pfi[2][N] = launch_pf_inst<N, 2>;
+  t.pfi[3][N] = launch_pf_inst<N, 3>;
   t.dt[N][1] = launch_dt<N, 1>;
   t.dt[N][2] = launch_dt<N, 2>;
   t.diag[N][1] = launch_diag<N, 1>;
@@ -1741,33 +1853,36 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
   const Table& T = table();
   const double rtol = c->opt.cg_rtol > 0.0 ? c->opt.cg_rtol : 1e-12;
   const int maxit = c->opt.cg_maxit > 0 ? c->opt.cg_maxit : 10000;
+  // CG restarts after a breakdown or a recurrence that drifted from the true
+  // residual (each restart recomputes the residual from Q)
+  constexpr int kMaxRestarts = 16;
   for (const Group& G : c->groups) {
     T.pfc[0][G.N][G.D](G, c->part, 0, rtol, c->stream);     // k, max|u|, integrands
     T.pfi[0][G.N](G, c->part, 0, rtol, c->stream);          // M, B
-    T.pfc[1][G.N][G.D](G, c->part, cold, rtol, c->stream);  // [div J], r, diag
-    T.pfi[1][G.N](G, c->part, 0, rtol, c->stream);          // ||b||
-  }
-  enqueue_mg_setup(c, c->stream);
-  enqueue_vcycle(c, c->stream);                              // u = M^-1 r
-  for (const Group& G : c->groups) {
-    T.pfc[2][G.N][G.D](G, c->part, 0, rtol, c->stream);     // w = K u, dots
-    T.pfi[2][G.N](G, c->part, 0, rtol, c->stream);          // first alpha
   }
   HIPCHK(c, hipGetLastError());
   const size_t n = c->inst.size();
   if (!c->pf_flags)
     HIPCHK(c, hipHostMalloc((void**)&c->pf_flags, sizeof(double) * n * kPfsLen, 0));
-  // kBatch iterations (p, s, Q, r update; u = M^-1 r; w = K u with the dot
-  // products; alpha, beta, done); phases that are done skip their work
+  // z = M^-1 r, the dot products, beta and the done flags
+  auto precondition = [&](hipStream_t st) {
+    enqueue_vcycle(c, st);
+    for (const Group& G : c->groups) {
+      T.pfc[4][G.N][G.D](G, c->part, 0, rtol, st);
+      T.pfi[3][G.N](G, c->part, 0, rtol, st);
+    }
+  };
+  // kBatch iterations (direction and K p, alpha, Q and r, then the above);
+  // phases that are done skip their work
   constexpr int kBatch = 4;
   auto batch = [&](int nb, hipStream_t st) {
     for (int k = 0; k < nb; ++k) {
-      for (const Group& G : c->groups) T.pfc[3][G.N][G.D](G, c->part, 0, rtol, st);
-      enqueue_vcycle(c, st);
       for (const Group& G : c->groups) {
         T.pfc[2][G.N][G.D](G, c->part, 0, rtol, st);
         T.pfi[2][G.N](G, c->part, 0, rtol, st);
+        T.pfc[3][G.N][G.D](G, c->part, 0, rtol, st);
       }
+      precondition(st);
     }
   };
   if (!c->pf_graph) {
@@ -1788,28 +1903,62 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
       return fail(c, MP_ERR_HIP, hipGetErrorString(e3));
     }
   }
-  bool all_done = false;
-  for (int it = 0;;) {
+  // the per-phase done flags, read back (synchronises the stream)
+  auto all_done = [&](bool& done) -> mp_status {
     HIPCHK(c, hipMemcpyAsync(c->pf_flags, c->pfs, sizeof(double) * n * kPfsLen,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    all_done = true;
-    for (size_t i = 0; i < n && all_done; ++i)
+    done = true;
+    for (size_t i = 0; i < n && done; ++i)
       for (int p = 0; p < c->inst[i].N; ++p)
-        if (c->pf_flags[i * kPfsLen + kPfsDone + p] == 0.0) { all_done = false; break; }
-    if (all_done || it >= maxit) break;
-    const int nb = std::min(kBatch, maxit - it);
-    it += nb;
-    if (nb == kBatch) {
-      HIPCHK(c, hipGraphLaunch(c->pf_graph, c->stream));
-    } else {
-      batch(nb, c->stream);
-      HIPCHK(c, hipGetLastError());
+        if (c->pf_flags[i * kPfsLen + kPfsDone + p] == 0.0) { done = false; break; }
+    return MP_OK;
+  };
+  bool converged = false;
+  int it = 0, restart = 0;
+  for (; restart <= kMaxRestarts; ++restart) {
+    // [div J], the true residual r = -b - K Q and the done flags from it
+    for (const Group& G : c->groups) {
+      T.pfc[1][G.N][G.D](G, c->part, cold && restart == 0, rtol, c->stream);
+      T.pfi[1][G.N](G, c->part, 0, rtol, c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
+    bool done = false;
+    mp_status st = all_done(done);
+    if (st != MP_OK) return st;
+    if (done) { converged = true; break; }
+    if (it >= maxit) break;
+    // the hierarchy of the phases left to solve (the multigrid passes skip
+    // phases that are done, so this follows the first start pass)
+    if (restart == 0) enqueue_mg_setup(c, c->stream);
+    precondition(c->stream);
+    HIPCHK(c, hipGetLastError());
+    for (;;) {
+      st = all_done(done);
+      if (st != MP_OK) return st;
+      if (done || it >= maxit) break;
+      const int nb = std::min(kBatch, maxit - it);
+      it += nb;
+      if (nb == kBatch) {
+        HIPCHK(c, hipGraphLaunch(c->pf_graph, c->stream));
+      } else {
+        batch(nb, c->stream);
+        HIPCHK(c, hipGetLastError());
+      }
     }
   }
   for (const Group& G : c->groups) T.pfc[5][G.N][G.D](G, c->part, clip, rtol, c->stream);
   HIPCHK(c, hipGetLastError());
-  if (!all_done) return fail(c, MP_ERR_SOLVER, "Phase-Field CG did not reach cg_rtol within cg_maxit");
+  if (!converged) {
+    // the largest true relative residual of the last start pass
+    double rmax = 0.0;
+    for (size_t i = 0; i < n; ++i) rmax = std::max(rmax, c->pf_flags[i * kPfsLen + kPfsRes]);
+    char msg[160];
+    std::snprintf(msg, sizeof(msg),
+                  "Phase-Field CG did not reach cg_rtol: relative residual %.3e after %d "
+                  "iterations and %d restarts", rmax, it, std::min(restart, kMaxRestarts));
+    return fail(c, MP_ERR_SOLVER, msg);
+  }
   return MP_OK;
 }
 

@@ -64,13 +64,41 @@ template <int N, int D>
 __device__ __forceinline__ constexpr int nU() { return 2 * N + D + 1; }
 
 // -------------------------------------------------------------------------
+// reciprocals
+// -------------------------------------------------------------------------
+
+// Reciprocal: IEEE division in FP64; the hardware reciprocal (1 ulp) in FP32,
+// where only the nonlinear weights and wave-speed coefficients use it.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Reciprocal of a double of magnitude in [2^-1000, 2^1000] without the
+// special-case scaling of the IEEE division sequence: the hardware estimate
+// refined by two Newton steps (within an ulp or two of 1/x).  Used for
+// quotients whose divisor is a physical quantity bounded away from zero and
+// overflow (densities, sums of alpha A, wave-speed differences); a quotient
+// a * rcp_normal(b) then lies within about two ulps of a / b.
+__device__ __forceinline__ double rcp_normal(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_normal(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// -------------------------------------------------------------------------
 // thermodynamics
 // -------------------------------------------------------------------------
 
 // Pressure of Eq. (27) and velocity u = (rho u)/rho.  The operation order is
 // fixed and contraction is off: the pressure of a stiffened-gas mixture loses
-// log10(gamma Pinf / P) digits to cancellation, so every implementation that
-// must agree with another to round-off has to round the same way here.
+// log10(gamma Pinf / P) digits to cancellation in E - ke - sum alpha B, so
+// every implementation that must agree with another to round-off has to
+// round the same way there.  The quotients by rho (u and ke) share one
+// reciprocal, and the last one (by sum alpha A) is a reciprocal product:
+// both lie within about two ulps of the divisions and no cancellation
+// follows them.
 template <int N, int D>
 __device__ __forceinline__ void cons_to_prim(const Cons<N, D>& U, const Eos& e,
                                              Prim<N, D>& V) {
@@ -78,13 +106,14 @@ __device__ __forceinline__ void cons_to_prim(const Cons<N, D>& U, const Eos& e,
   double rho = 0.0;
 #pragma unroll
   for (int p = 0; p < N; ++p) rho = rho + U.m[p];
+  const double ir = rho > 0.0 ? rcp_normal(rho) : 0.0;
   double mom2 = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     mom2 = mom2 + U.mom[k] * U.mom[k];
-    V.u[k] = rho > 0.0 ? U.mom[k] / rho : 0.0;
+    V.u[k] = U.mom[k] * ir;
   }
-  const double ke = rho > 0.0 ? 0.5 * mom2 / rho : 0.0;
+  const double ke = 0.5 * mom2 * ir;
   double sA = 0.0, sB = 0.0, sD = 0.0;
 #pragma unroll
   for (int p = 0; p < N; ++p) {
@@ -94,41 +123,53 @@ __device__ __forceinline__ void cons_to_prim(const Cons<N, D>& U, const Eos& e,
     V.m[p] = U.m[p];
     V.a[p] = U.a[p];
   }
-  V.P = (U.E - ke - sB - sD) / sA;
+  V.P = (U.E - ke - sB - sD) * rcp_normal(sA);
 }
 
-// Mixture rho c^2 (Eq. (2) with the EOS of Eq. (26)): Allaire
-// sum A a gamma (P + Pinf) / sum A a; Kapila (Wood) sum a / sum a/(gamma(P+Pinf)).
-// Non-positive values are returned as 0 (no NaN from strong tension).
+// Mixture rho c^2 (Eq. (2) with the EOS of Eq. (26)) as a quotient
+// num / den: Allaire sum A a gamma (P + Pinf) / sum A a; Kapila (Wood)
+// sum a / sum a/(gamma(P+Pinf)).  num = 0 stands for a value that is not
+// positive (no NaN from strong tension).
 template <int N>
-__device__ __forceinline__ double mix_rc2(const double* a, double P,
-                                          const Eos& e, int model) {
+__device__ __forceinline__ void mix_rc2_parts(const double* a, double P, const Eos& e,
+                                              int model, double& num, double& den) {
+  num = 0.0;
+  den = 0.0;
   if (model == 1) {
     double s = 0.0, sa = 0.0;
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       if (a[p] != 0.0) {
         const double k = e.gam[p] * (P + e.pinf[p]);
-        if (!(k > 0.0)) return 0.0;
+        if (!(k > 0.0)) return;
         s += a[p] / k;
         sa += a[p];
       }
     }
-    return s > 0.0 ? sa / s : 0.0;
+    if (s > 0.0) { num = sa; den = s; }
+    return;
   }
-  double num = 0.0, den = 0.0;
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     const double Aa = e.A[p] * a[p];
     num += Aa * (e.gam[p] * (P + e.pinf[p]));
     den += Aa;
   }
-  const double r = num / den;
-  return r > 0.0 ? r : 0.0;
+  if (!(num > 0.0)) num = 0.0;
 }
 
-__device__ __forceinline__ double sound_speed(double rc2, double rho) {
-  return (rc2 > 0.0 && rho > 0.0) ? sqrt(rc2 / rho) : 0.0;
+template <int N>
+__device__ __forceinline__ double mix_rc2(const double* a, double P,
+                                          const Eos& e, int model) {
+  double num, den;
+  mix_rc2_parts<N>(a, P, e, model, num, den);
+  return num > 0.0 ? num / den : 0.0;
+}
+
+// c = sqrt(rho c^2 / rho) = sqrt(num / (den rho)) with one reciprocal; 0 when
+// rho c^2 or rho is not positive.
+__device__ __forceinline__ double sound_speed(double num, double den, double rho) {
+  return (num > 0.0 && rho > 0.0) ? sqrt(num * rcp_normal(den * rho)) : 0.0;
 }
 
 // psi(U) of Eq. (9) with m_p e_p(Pmin_p, rho_p) = alpha_p EB_p + m_p D_p.
@@ -144,26 +185,10 @@ __device__ __forceinline__ double psi(const double* m, const double* a,
   }
 #pragma unroll
   for (int k = 0; k < D; ++k) mom2 += mom[k] * mom[k];
-  const double ke = rho > 0.0 ? 0.5 * mom2 / rho : 0.0;
+  const double ke = rho > 0.0 ? 0.5 * mom2 * rcp_normal(rho) : 0.0;
   return E - ke - emin;
 }
 
-// Reciprocal: IEEE division in FP64; the hardware reciprocal (1 ulp) in FP32,
-// where only the nonlinear weights and wave-speed coefficients use it.
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Reciprocal of a positive normal double in [2^-1000, 2^1000] without the
-// special-case scaling of the IEEE division sequence: the hardware estimate
-// refined by two Newton steps (within an ulp or two of 1/x).
-__device__ __forceinline__ double rcp_normal(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-__device__ __forceinline__ float rcp_normal(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // -------------------------------------------------------------------------
 // WENO5 with the relative-smoothness weights (Sec. 3.1, 3.3)
@@ -442,7 +467,7 @@ __device__ __forceinline__ void reconstruct(const Prim<N, D> (&s)[5],
 #pragma unroll
     for (int p = 0; p < N; ++p) { sl += fp.a[p]; sr += fm.a[p]; }
     if (sl > 0.0 && sr > 0.0) {
-      const double il = 1.0 / sl, ir = 1.0 / sr;
+      const double il = rcp_normal(sl), ir = rcp_normal(sr);
 #pragma unroll
       for (int p = 0; p < N; ++p) {
         fp.m[p] *= il; fp.a[p] *= il;
@@ -544,12 +569,14 @@ __device__ __forceinline__ void reconstruct(const Prim<N, D> (&s)[5],
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     Face<N, D>& f = side == 0 ? fp : fm;
+    double num, den;
+    mix_rc2_parts<N>(f.a, f.P, e, g.model, num, den);
     if constexpr (MIXED) {
-      const float rc2 = float(mix_rc2<N>(f.a, f.P, e, g.model));
       const float rho = float(f.rho);
-      f.c = (rc2 > 0.f && rho > 0.f) ? double(__builtin_sqrtf(rc2 * rcp(rho))) : 0.0;
+      f.c = (num > 0.0 && rho > 0.f)
+                ? double(__builtin_sqrtf(float(num) * rcp(float(den) * rho))) : 0.0;
     } else {
-      f.c = sound_speed(mix_rc2<N>(f.a, f.P, e, g.model), f.rho);
+      f.c = sound_speed(num, den, f.rho);
     }
   }
 }
@@ -616,7 +643,7 @@ __device__ __forceinline__ void riemann(const Face<N, D>& L,
       cr = 1.0 - cl;
       clr = double(fSL * fSR * inv);
     } else {
-      const double inv = 1.0 / (SR - SL);
+      const double inv = rcp_normal(SR - SL);
       cl = SR * inv;
       cr = -SL * inv;
       clr = SL * SR * inv;
@@ -635,11 +662,12 @@ __device__ __forceinline__ void riemann(const Face<N, D>& L,
   }
   // HLLC
   const double sL = L.rho * (SL - uL), sR = R.rho * (SR - uR);
-  const double Ss = (R.P - L.P + uL * sL - uR * sR) / (sL - sR);
+  // star region (SL < 0 < SR): sL < 0 < sR and SK - uK, SK - Ss are nonzero
+  const double Ss = (R.P - L.P + uL * sL - uR * sR) * rcp_normal(sL - sR);
   const bool left = Ss >= 0.0;
   const Face<N, D>& K = left ? L : R;
   const double SK = left ? SL : SR, uK = K.u[dir];
-  const double chi = (SK - uK) / (SK - Ss);
+  const double chi = (SK - uK) * rcp_normal(SK - Ss);
   double fk[nU<N, D>()];
   phys(K, fk);
 #pragma unroll
@@ -652,7 +680,7 @@ __device__ __forceinline__ void riemann(const Face<N, D>& L,
     const double ms = chi * K.rho * (k == dir ? Ss : K.u[k]);
     F.f[N + k] = fk[N + k] + SK * (ms - K.mom[k]);
   }
-  const double Es = chi * (K.E + (Ss - uK) * (K.rho * Ss + K.P / (SK - uK)));
+  const double Es = chi * (K.E + (Ss - uK) * (K.rho * Ss + K.P * rcp_normal(SK - uK)));
   F.f[NE] = fk[NE] + SK * (Es - K.E);
   F.uh = chi * Ss;
 }
