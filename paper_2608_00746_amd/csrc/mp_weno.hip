@@ -318,17 +318,8 @@ void k_sweep_x(const Desc* __restrict__ descs,
   if (l >= BX - 2) put_prim(x0 - 1 + l + 2, l + 4);
   __syncthreads();
 
-  Prim<N, D> s[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-#pragma unroll
-    for (int p = 0; p < N; ++p) { s[j].m[p] = sprim[p][l + j]; s[j].a[p] = sprim[N + p][l + j]; }
-#pragma unroll
-    for (int k = 0; k < D; ++k) s[j].u[k] = sprim[2 * N + k][l + j];
-    s[j].P = sprim[2 * N + D][l + j];
-  }
   Face<N, D> fm, fp;
-  reconstruct<N, D, W>(s, ub, e, g, g.hdx, fm, fp);
+  reconstruct<N, D, W>([&](int c, int j) { return sprim[c][l + j]; }, ub, e, g, g.hdx, fm, fp);
 
   // publish the minus-side face state for the left neighbour
 #pragma unroll
@@ -473,17 +464,8 @@ void k_sweep_y(const Desc* __restrict__ descs,
   if (ty >= kTY - 2) put_prim(yi + 2, ty + 4);
   __syncthreads();
 
-  Prim<N, D> s[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-#pragma unroll
-    for (int p = 0; p < N; ++p) { s[j].m[p] = sprim[p][ty + j][tx]; s[j].a[p] = sprim[N + p][ty + j][tx]; }
-#pragma unroll
-    for (int k = 0; k < D; ++k) s[j].u[k] = sprim[2 * N + k][ty + j][tx];
-    s[j].P = sprim[2 * N + D][ty + j][tx];
-  }
   Face<N, D> fm, fp;
-  reconstruct<N, D, W>(s, ub, e, g, g.hdy, fm, fp);
+  reconstruct<N, D, W>([&](int c, int j) { return sprim[c][ty + j][tx]; }, ub, e, g, g.hdy, fm, fp);
 
 #pragma unroll
   for (int p = 0; p < N; ++p) { sface[p][ty][tx] = fm.m[p]; sface[N + p][ty][tx] = fm.a[p]; }
@@ -1414,8 +1396,52 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_diag(const Desc* __restrict__ 
   }
 }
 
-// one damped Jacobi sweep on level l: mode 0: t = omega f / dg (from e = 0);
+// One cell of the level passes, shared by the per-level kernels and the
+// fused coarse cycle below.
+// Damped Jacobi on level L: mode 0: t = omega f / dg (from e = 0);
 // mode 1: t = e + omega (f - K e) / dg; mode 2: e = t + omega (f - K t) / dg
+template <int D>
+__device__ __forceinline__ void mg_smooth_cell(const Grid& g, const MgLevel& L, int p,
+                                               int64_t i, int mode) {
+  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
+  const int64_t ip = (int64_t)p * L.nc + i;
+  const double dgv = gptr(L.dg)[ip];
+  const double fv = gptr(L.f)[ip];
+  if (mode == 0) {
+    gptr(L.t)[ip] = dgv > 0.0 ? kMgOmega * fv / dgv : 0.0;
+    return;
+  }
+  const gdouble* src = gptr(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
+  gdouble* dst = gptr(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc;
+  const double kv = lapply<D>(g, L, p, src, i, x, y);
+  dst[i] = dgv > 0.0 ? src[i] + kMgOmega * (fv - kv) / dgv : src[i];
+}
+
+// f(C) at coarse cell i = sum over its aggregate of (f - K e) on F
+template <int D>
+__device__ __forceinline__ void mg_restrict_cell(const Grid& g, const MgLevel& F,
+                                                 const MgLevel& C, int p, int64_t i) {
+  const int Y = (int)(i / C.nx), X = (int)(i - (int64_t)Y * C.nx);
+  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
+  const gdouble* e = gptr(F.e) + (int64_t)p * F.nc;
+  const gdouble* f = gptr(F.f) + (int64_t)p * F.nc;
+  double r = 0.0;
+  for (int y = 2 * Y; y <= yt; ++y)
+    for (int x = 2 * X; x <= xr; ++x) {
+      const int64_t j = (int64_t)y * F.nx + x;
+      r += f[j] - lapply<D>(g, F, p, e, j, x, y);
+    }
+  gptr(C.f)[(int64_t)p * C.nc + i] = r;
+}
+
+// e(F) at fine cell i += corr e(C) of its aggregate
+__device__ __forceinline__ void mg_prolong_cell(const MgLevel& F, const MgLevel& C, int p,
+                                                int64_t i, double corr) {
+  const int y = (int)(i / F.nx), x = (int)(i - (int64_t)y * F.nx);
+  const int64_t I = (int64_t)(y >> 1) * C.nx + (x >> 1);
+  gptr(F.e)[(int64_t)p * F.nc + i] += corr * gptr(C.e)[(int64_t)p * C.nc + I];
+}
+
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_mg_smooth(const Desc* __restrict__ descs,
                                                          const int2* __restrict__ map, int ninst,
@@ -1423,25 +1449,12 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_smooth(const Desc* __restrict_
   MG_PROLOGUE
   const MgLevel L = d.mg[l];
   if (i >= L.nc) return;
-  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
 #pragma unroll
-  for (int p = 0; p < N; ++p) {
-    if (!live[p]) continue;
-    const int64_t ip = (int64_t)p * L.nc + i;
-    const double dgv = gptr(L.dg)[ip];
-    const double fv = gptr(L.f)[ip];
-    if (mode == 0) {
-      gptr(L.t)[ip] = dgv > 0.0 ? kMgOmega * fv / dgv : 0.0;
-      continue;
-    }
-    const gdouble* src = gptr(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
-    gdouble* dst = gptr(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc;
-    const double kv = lapply<D>(g, L, p, src, i, x, y);
-    dst[i] = dgv > 0.0 ? src[i] + kMgOmega * (fv - kv) / dgv : src[i];
-  }
+  for (int p = 0; p < N; ++p)
+    if (live[p]) mg_smooth_cell<D>(g, L, p, i, mode);
 }
 
-// f(l + 1) = sum over the aggregate of (f - K e) on level l (items over l + 1)
+// f(l + 1) from level l (items over l + 1)
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_mg_restrict(const Desc* __restrict__ descs,
                                                            const int2* __restrict__ map, int ninst,
@@ -1449,24 +1462,12 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_restrict(const Desc* __restric
   MG_PROLOGUE
   const MgLevel F = d.mg[l], C = d.mg[l + 1];
   if (i >= C.nc) return;
-  const int Y = (int)(i / C.nx), X = (int)(i - (int64_t)Y * C.nx);
-  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
 #pragma unroll
-  for (int p = 0; p < N; ++p) {
-    if (!live[p]) continue;
-    const gdouble* e = gptr(F.e) + (int64_t)p * F.nc;
-    const gdouble* f = gptr(F.f) + (int64_t)p * F.nc;
-    double r = 0.0;
-    for (int y = 2 * Y; y <= yt; ++y)
-      for (int x = 2 * X; x <= xr; ++x) {
-        const int64_t j = (int64_t)y * F.nx + x;
-        r += f[j] - lapply<D>(g, F, p, e, j, x, y);
-      }
-    gptr(C.f)[(int64_t)p * C.nc + i] = r;
-  }
+  for (int p = 0; p < N; ++p)
+    if (live[p]) mg_restrict_cell<D>(g, F, C, p, i);
 }
 
-// e(l) += e(l + 1) of the cell's aggregate (items over level l)
+// e(l) += corr e(l + 1) (items over level l)
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_mg_prolong(const Desc* __restrict__ descs,
                                                           const int2* __restrict__ map, int ninst,
@@ -1475,15 +1476,70 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_prolong(const Desc* __restrict
   const MgLevel F = d.mg[l], C = d.mg[l + 1];
   if (i >= F.nc) return;
   const double corr = s[kPfsCorr];
-  const int y = (int)(i / F.nx), x = (int)(i - (int64_t)y * F.nx);
-  const int64_t I = (int64_t)(y >> 1) * C.nx + (x >> 1);
 #pragma unroll
-  for (int p = 0; p < N; ++p) {
-    if (!live[p]) continue;
-    gptr(F.e)[(int64_t)p * F.nc + i] += corr * gptr(C.e)[(int64_t)p * C.nc + I];
-  }
+  for (int p = 0; p < N; ++p)
+    if (live[p]) mg_prolong_cell(F, C, p, i, corr);
 }
 #undef MG_PROLOGUE
+
+// The V-cycle below level lf (the levels of at most kMgFuseCells cells) in
+// one workgroup per instance: the same passes as the per-level kernels, in
+// the same order, separated by workgroup barriers instead of launches (the
+// coarse levels are otherwise launch-bound).  Input f(lf), output e(lf).
+constexpr int kMgFuseCells = 4096;
+constexpr int kMgFuseBlock = 1024;
+
+template <int N, int D>
+__global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restrict__ descs,
+                                                           int lf, int nlev) {
+  const Desc& d = descs[blockIdx.x];
+  const Grid& g = d.g;
+  const gdouble* s = gptr(d.pfs);
+  bool live[N];
+  bool any = false;
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    live[p] = s[kPfsDone + p] == 0.0;
+    any = any || live[p];
+  }
+  if (!any) return;                       // uniform over the workgroup
+  const double corr = s[kPfsCorr];
+  auto smooth = [&](int l, int mode) {
+    const MgLevel L = d.mg[l];
+    for (int64_t i = threadIdx.x; i < L.nc; i += kMgFuseBlock)
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+        if (live[p]) mg_smooth_cell<D>(g, L, p, i, mode);
+    __syncthreads();
+  };
+  const int lc = nlev - 1;
+  for (int l = lf; l < lc; ++l) {
+    smooth(l, 0);
+    smooth(l, 2);
+    const MgLevel F = d.mg[l], C = d.mg[l + 1];
+    for (int64_t i = threadIdx.x; i < C.nc; i += kMgFuseBlock)
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+        if (live[p]) mg_restrict_cell<D>(g, F, C, p, i);
+    __syncthreads();
+  }
+  smooth(lc, 0);
+  smooth(lc, 2);
+  for (int k = 2; k < kMgCoarseSweeps; k += 2) {
+    smooth(lc, 1);
+    smooth(lc, 2);
+  }
+  for (int l = lc - 1; l >= lf; --l) {
+    const MgLevel F = d.mg[l], C = d.mg[l + 1];
+    for (int64_t i = threadIdx.x; i < F.nc; i += kMgFuseBlock)
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+        if (live[p]) mg_prolong_cell(F, C, p, i, corr);
+    __syncthreads();
+    smooth(l, 1);
+    smooth(l, 2);
+  }
+}
 
 // frozen face gradients dQ_p/dx_d at the upper face of every cell: none at an
 // outflow end or for a phase with [div J] = 0 everywhere; clip != 0: limited
@@ -1557,6 +1613,7 @@ struct Group {
   int* rstart = nullptr;           // reduction-chunk offsets on the device
   size_t part_off = 0;             // this group's reduction partials
   int nlev = 0;                    // multigrid levels (every instance has them all)
+  int mg_fuse = 0;                 // first level run by the fused coarse cycle
   int2* lmap[kMgMaxLev] = {};      // work item -> (instance, 256-cell chunk) per level
   int lcount[kMgMaxLev] = {};
 };
@@ -1605,7 +1662,7 @@ void launch_pf_cells(const Group& G, double* part, int flag, double, hipStream_t
 
 // multigrid passes over the work items of level l (kind: 0 level-0 weights,
 // 1 coarsen l -> l + 1, 2 diagonal, 3 smooth, 4 restrict l -> l + 1,
-// 5 prolong l + 1 -> l)
+// 5 prolong l + 1 -> l, 6 the fused cycle from level l down)
 using MgFn = void (*)(const Group&, int kind, int l, int mode, hipStream_t);
 template <int N, int D>
 void launch_mg(const Group& G, int kind, int l, int mode, hipStream_t s) {
@@ -1618,6 +1675,7 @@ void launch_mg(const Group& G, int kind, int l, int mode, hipStream_t s) {
     case 3: hipLaunchKernelGGL((k_mg_smooth<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l, mode); break;
     case 4: hipLaunchKernelGGL((k_mg_restrict<N, D>), dim3(G.lcount[l + 1]), blk, 0, s, G.desc, G.lmap[l + 1], n, l); break;
     case 5: hipLaunchKernelGGL((k_mg_prolong<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l); break;
+    case 6: hipLaunchKernelGGL((k_mg_fused<N, D>), dim3(n), dim3(kMgFuseBlock), 0, s, G.desc, l, G.nlev); break;
   }
 }
 
@@ -1820,24 +1878,20 @@ static void enqueue_mg_setup(mp_weno_ctx* c, hipStream_t st) {
 }
 
 // u = M^-1 r: one V-cycle per group (two Jacobi sweeps before and after the
-// coarse correction, kMgCoarseSweeps on the coarsest level)
+// coarse correction, kMgCoarseSweeps on the coarsest level); the levels of at
+// most kMgFuseCells cells run in one launch (k_mg_fused)
 static void enqueue_vcycle(mp_weno_ctx* c, hipStream_t st) {
   const Table& T = table();
   for (const Group& G : c->groups) {
     MgFn f = T.mg[G.N][G.D];
-    const int Lc = G.nlev - 1;
-    for (int l = 0; l < Lc; ++l) {
+    const int Lf = G.mg_fuse;                        // fused from here down
+    for (int l = 0; l < Lf; ++l) {
       f(G, 3, l, 0, st);                             // t = omega f / dg
       f(G, 3, l, 2, st);                             // e = t + omega (f - K t) / dg
       f(G, 4, l, 0, st);                             // f(l + 1) = R (f - K e)
     }
-    f(G, 3, Lc, 0, st);
-    f(G, 3, Lc, 2, st);
-    for (int k = 2; k < kMgCoarseSweeps; k += 2) {
-      f(G, 3, Lc, 1, st);
-      f(G, 3, Lc, 2, st);
-    }
-    for (int l = Lc - 1; l >= 0; --l) {
+    f(G, 6, Lf, 0, st);                              // levels Lf .. nlev - 1
+    for (int l = Lf - 1; l >= 0; --l) {
       f(G, 5, l, 0, st);                             // e += P e(l + 1)
       f(G, 3, l, 1, st);                             // t = e + omega (f - K e) / dg
       f(G, 3, l, 2, st);                             // e = t + omega (f - K t) / dg
@@ -2300,6 +2354,18 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           for (int64_t ch = 0; ch * kRedBlock < ncl; ++ch) lm[l].push_back(make_int2((int)k, (int)ch));
         }
         G.lcount[l] = (int)lm[l].size();
+      }
+      // the fused cycle takes every level with at most kMgFuseCells cells in
+      // each instance of the group
+      if (G.nlev > 0) {
+        G.mg_fuse = G.nlev - 1;
+        while (G.mg_fuse > 0) {
+          bool small = true;
+          for (size_t k = 0; k < m; ++k)
+            small = small && c->inst[G.ids[k]].lv[G.mg_fuse - 1].nc <= kMgFuseCells;
+          if (!small) break;
+          --G.mg_fuse;
+        }
       }
       auto tile_map = [m](const std::vector<int>& st) {
         std::vector<int2> v((size_t)st[m]);

@@ -383,12 +383,14 @@ __device__ __forceinline__ void consistent_limiter(const double* S,
 // -------------------------------------------------------------------------
 // reconstruction of one cell along one direction
 // -------------------------------------------------------------------------
-// s[0..4]: primitive averages of cells i-2..i+2 along the direction;
-// ub: conserved average of cell i.  Outputs: fm = U^R_{i-1/2} (the cell's
+// st(c, j): component c of the primitive averages of cell i-2+j (j = 0..4)
+// along the direction, in the order m_1..m_N, alpha_1..alpha_N, u_1..u_D,
+// P (read where it is used, from the caller's LDS rows, so that the stencil
+// never sits in registers as a whole); ub: conserved average of cell i.  Outputs: fm = U^R_{i-1/2} (the cell's
 // face on the minus side), fp = U^L_{i+1/2} (plus side), each with its face
 // primitives, density and sound speed.  hdx = dx/2 of the direction.
-template <int N, int D, typename W>
-__device__ __forceinline__ void reconstruct(const Prim<N, D> (&s)[5],
+template <int N, int D, typename W, typename S>
+__device__ __forceinline__ void reconstruct(const S& st,
                                             const Cons<N, D>& ub,
                                             const Eos& e, const Grid& g,
                                             double hdx, Face<N, D>& fm,
@@ -397,9 +399,9 @@ __device__ __forceinline__ void reconstruct(const Prim<N, D> (&s)[5],
   // u and P: WENO5-W on each primitive (Sec. 3.4)
 #pragma unroll
   for (int k = 0; k <= D; ++k) {
-    const double q2 = k < D ? s[2].u[k] : s[2].P;
-    const Diff df = k < D ? diffs(s[0].u[k], s[1].u[k], q2, s[3].u[k], s[4].u[k])
-                          : diffs(s[0].P, s[1].P, q2, s[3].P, s[4].P);
+    const int c = 2 * N + k;                 // u_k, then P
+    const double q2 = st(c, 2);
+    const Diff df = diffs(st(c, 0), st(c, 1), q2, st(c, 3), st(c, 4));
     W b[3], wl[3], wr[3];
     beta3<W>(df, b);
     wenow_weights<W>(b, wl, wr);
@@ -415,10 +417,10 @@ __device__ __forceinline__ void reconstruct(const Prim<N, D> (&s)[5],
   double mb[N], ab[N];
 #pragma unroll
   for (int p = 0; p < N; ++p) {
-    mb[p] = s[2].m[p];
-    ab[p] = s[2].a[p];
-    const Diff dm = diffs(s[0].m[p], s[1].m[p], mb[p], s[3].m[p], s[4].m[p]);
-    const Diff da = diffs(s[0].a[p], s[1].a[p], ab[p], s[3].a[p], s[4].a[p]);
+    mb[p] = st(p, 2);
+    ab[p] = st(N + p, 2);
+    const Diff dm = diffs(st(p, 0), st(p, 1), mb[p], st(p, 3), st(p, 4));
+    const Diff da = diffs(st(N + p, 0), st(N + p, 1), ab[p], st(N + p, 3), st(N + p, 4));
     W b[3], wl[3], wr[3];
     beta3<W>(dm, b);
     wenow_weights<W>(b, wl, wr);
