@@ -17,8 +17,8 @@ to first:
   per cell written) over the average launch time;
 * ALU: FP64 flops per launch (FP32 flops count half) over the average launch
   time against the FP64 vector peak, with the per-cell flop and VALU
-  instruction counts of the counter table in profiles/ (counted per launched
-  lane, so halo and ragged-tail lanes are not charged to the method).
+  instruction counts of the counter table in profiles/ (per cell: every
+  lane of a launch runs one cell's chain).
 The launch time is measured with HIP events the library records on the
 kernel's stream around each stage, in a short eager pass right after the
 timed steps (those replay a captured graph, which cannot carry readable event
@@ -66,12 +66,14 @@ def stage_counters(workload, precision, tiles):
       a reference copy), only from the row of this workload, precision, tile
       choice and kernel source (else None);
     * flops64, flops32, valu: FP64 and FP32 flops and VALU lane-instructions
-      per cell per stage, counted per launched lane (halo and ragged-tail
-      lanes excluded), from the last row of this workload and precision."""
+      per cell per stage (counted per launched lane: every lane runs one
+      cell's chain), from the row of this tile choice, else the last row of
+      this workload and precision."""
     out = {"traffic": None, "flops64": None, "flops32": None, "valu": None}
     if not os.path.exists(COUNTER_TABLE):
         return out
     key = kernel_source_hash()
+    exact = False
     for line in open(COUNTER_TABLE):
         cols = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cols) != 9 or cols[0] in ("workload",) or cols[0].startswith("---"):
@@ -79,7 +81,9 @@ def stage_counters(workload, precision, tiles):
         wl, prec, tl, src, fetch_kib, write_kib, f64, f32, valu = cols
         if (wl, prec) != (workload, precision):
             continue
-        out.update(flops64=float(f64), flops32=float(f32), valu=float(valu))
+        if tl == tiles or not exact:
+            out.update(flops64=float(f64), flops32=float(f32), valu=float(valu))
+            exact = exact or tl == tiles
         if (tl, src) == (tiles, key):
             out["traffic"] = (float(fetch_kib) + float(write_kib)) * 1024.0
     return out
