@@ -212,8 +212,10 @@ mp_status mp_weno_advance(mp_weno_ctx *ctx, int32_t nsteps);
  *   k = 24         : min over cells of psi(U) (Eq. (9))
  *   k = 25         : number of non-finite entries
  *   k = 26, 27     : instance time t and number of steps taken
- *   k = 29, 30     : Phase-Field step: CG iterations and relative residual
- *                    of the last solve of Eq. (4) (0 when it is off)
+ *   k = 29, 30     : Phase-Field step: CG iterations (over restarts) and
+ *                    the true relative residual ||-[div J] - K Q|| /
+ *                    ||[div J]|| (largest over phases) of the last solve of
+ *                    Eq. (4) (0 when it is off)
  * where = MP_WHERE_HOST (synchronises) or MP_WHERE_DEVICE. */
 mp_status mp_weno_diag(mp_weno_ctx *ctx, double *out, int32_t where);
 

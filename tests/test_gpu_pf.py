@@ -208,3 +208,38 @@ def test_pf_solver_failure_restores_state():
     assert np.array_equal(s.host(0), before)
     assert s.diag()[0][27] == 0
     s.close()
+
+
+@pytest.mark.parametrize("which", ["shock_bubble_2048x1024", "batched_256"])
+def test_pf_full_size_invariants(which):
+    """The Phase-Field step at the benchmark sizes, where the oracle's direct
+    solve is out of reach: every solve ends on a converged true residual, and
+    the steps keep the state finite, sum alpha = 1 and the bounds (Sec. 2.2.1:
+    the Phase-Field fluxes of Eq. (5) move no phase below 0 or above 1) up to
+    round-off: an average is a sum of fluxes, so where a phase is absent its
+    mass and volume fraction may land a few ulps below 0 (seen: -1e-35 kg/m^3
+    in the batch); tau = 8 eps in units of the lightest density (1 kg/m^3)
+    and of alpha."""
+    if which == "batched_256":
+        ws, K = I.batched(), 2
+    else:
+        ws, K = [I.shock_bubble_2d(2048, 1024)], 3
+    for w in ws:
+        w.opts.phase_field = 1
+    s = _solver(ws)
+    for _ in range(K):
+        s.step()
+    d = s.diag()
+    s.close()
+    nmax = max(w.N for w in ws)
+    print(which, "CG iterations of the last solve: max", d[:, 29].max(),
+          "residual max", d[:, 30].max())
+    assert (d[:, 25] == 0).all()
+    assert (d[:, 27] == K).all()
+    assert (d[:, 30] <= 1e-10).all(), d[:, 30].max()
+    assert (d[:, 20] <= 16 * nmax * EPS * np.sqrt(K)).all(), d[:, 20].max()
+    tau = 8 * EPS
+    assert (d[:, 21] >= -tau).all(), d[:, 21].min()
+    assert (d[:, 22] >= -tau).all(), d[:, 22].min()
+    assert (d[:, 23] <= 1 + tau).all(), d[:, 23].max()
+
