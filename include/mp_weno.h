@@ -97,8 +97,10 @@ typedef struct {
   double cg_rtol;          /* Eq. (4) solve: stop once the true residual
                               ||res|| = ||-[div J] - K Q|| <= cg_rtol ||[div J]||
                               + 64 eps || |[div J]| + |K| |Q| || (the second
-                              term: the rounding floor of res itself); <= 0:
-                              1e-12                                          */
+                              term: the rounding floor of res itself), or
+                              once a restart no longer halves it while it is
+                              <= 1000 cg_rtol ||[div J]|| (stagnation at the
+                              attainable accuracy); <= 0: 1e-12              */
   int32_t cg_maxit;        /* iteration limit of that solve (<= 0: 10000)    */
   int32_t check_bounds;    /* 1: mp_weno_step checks the result (see below)  */
   int32_t use_graph;       /* 1: replay mp_weno_step as a captured HIP graph */
@@ -163,7 +165,8 @@ mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
 /* Autotuner: for every group of instances with the same (N, d), time the
  * tile shapes of the two sweeps (x strips of 256, 128 or 64 lanes; y tiles
  * of 16 x 16, 32 x 8 or 16 x 24 lanes) and the XCD-aware tile order (off / on) on the
- * current states, reps launches each (0: 5), and keep the fastest for the
+ * current states, reps launches each (0: 8) in two interleaved rounds (the
+ * faster round counts), and keep the fastest for the
  * hyperbolic sweeps of later calls.  The timing evaluates L(U) into the
  * context's stage buffer: the states, the time and the step count are not
  * touched.  Synchronises the stream; drops a captured step graph (the next

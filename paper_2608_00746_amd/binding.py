@@ -225,7 +225,7 @@ class Solver:
         self._leave()
         return out
 
-    def autotune(self, reps=5):
+    def autotune(self, reps=8):
         """Pick the fastest sweep tile shapes and tile order per group; returns
         per instance (x strip, y tile width, y tile height, XCD order)."""
         out = (C.c_int32 * (4 * len(self.U)))()
