@@ -604,23 +604,50 @@ void mpo_flux(const mpo_problem *pb, int dir, const double *UL,
 
 /* Ghost cells (Sec. 4.1 periodic, Sec. 4.2 outflow).  Reading: outflow is a
  * zero-gradient copy of the nearest interior cell. */
-static long ghost_index(long i, long n, int bclo, int bchi) {
+/* Cell that stands in for index i of a line of n cells: periodic wrap,
+ * outflow (zero-gradient) copy of the end cell, or, at a symmetry plane, the
+ * mirror image across the end face (cell -1-i below, 2n-1-i above), clamped
+ * into the line when it has fewer cells than the stencil reaches.  *flip is
+ * set when the stand-in is a mirror image: its normal momentum changes sign
+ * (the plane is a wall the flow does not cross). */
+static long ghost_index_flip(long i, long n, int bclo, int bchi, int *flip) {
+  *flip = 0;
   if (i < 0) {
     if (bclo == MPO_BC_PERIODIC) return ((i % n) + n) % n;
+    if (bclo == MPO_BC_SYMMETRY) {
+      long m = -1 - i;
+      *flip = 1;
+      return m < n ? m : n - 1;
+    }
     return 0;
   }
   if (i >= n) {
     if (bchi == MPO_BC_PERIODIC) return i % n;
+    if (bchi == MPO_BC_SYMMETRY) {
+      long m = 2 * n - 1 - i;
+      *flip = 1;
+      return m >= 0 ? m : 0;
+    }
     return n - 1;
   }
   return i;
 }
 
+static long ghost_index(long i, long n, int bclo, int bchi) {
+  int flip;
+  return ghost_index_flip(i, n, bclo, bchi, &flip);
+}
+
 static int check_problem(const mpo_problem *pb) {
   if (!pb || pb->ndim < 1 || pb->ndim > 3) return MPO_ERR_ARG;
   if (pb->nphase < 1 || pb->nphase > MPO_MAXP) return MPO_ERR_ARG;
-  for (int d = 0; d < pb->ndim; ++d)
+  for (int d = 0; d < pb->ndim; ++d) {
     if (pb->n[d] < 1 || !(pb->dx[d] > 0.0)) return MPO_ERR_ARG;
+    for (int e = 0; e < 2; ++e)
+      if (pb->bc[d][e] < MPO_BC_PERIODIC || pb->bc[d][e] > MPO_BC_SYMMETRY) return MPO_ERR_ARG;
+    /* a periodic direction is periodic at both ends */
+    if ((pb->bc[d][0] == MPO_BC_PERIODIC) != (pb->bc[d][1] == MPO_BC_PERIODIC)) return MPO_ERR_ARG;
+  }
   return MPO_OK;
 }
 
@@ -675,8 +702,10 @@ int mpo_rhs(const mpo_problem *pb, const double *U, double *L) {
         const long base = j1 * sx[o1] + j2 * sx[o2];
         for (long i = -1; i <= n; ++i) {
           for (int j = 0; j < 5; ++j) {
-            long g = ghost_index(i - 2 + j, n, pb->bc[dir][0], pb->bc[dir][1]);
+            int flip;
+            long g = ghost_index_flip(i - 2 + j, n, pb->bc[dir][0], pb->bc[dir][1], &flip);
             for (int c = 0; c < nU; ++c) Us[j * nU + c] = U[c * nc + base + g * s];
+            if (flip) Us[j * nU + IMOM(pb, dir)] = -Us[j * nU + IMOM(pb, dir)];
           }
           mpo_reconstruct_cell(pb, Us, dir, UL + (i + 1) * nU, UR + (i + 1) * nU,
                                VL + (i + 1) * nU, VR + (i + 1) * nU, NULL);
@@ -1022,8 +1051,10 @@ int mpo_pf_rhs(const mpo_problem *pb, const double *U, const double *G,
         const long base = j1 * sx[o1] + j2 * sx[o2];
         for (long i = -1; i <= n; ++i) {
           for (int j = 0; j < 5; ++j) {
-            long g = ghost_index(i - 2 + j, n, pb->bc[dir][0], pb->bc[dir][1]);
+            int flip;
+            long g = ghost_index_flip(i - 2 + j, n, pb->bc[dir][0], pb->bc[dir][1], &flip);
             for (int c = 0; c < nU; ++c) Us[j * nU + c] = U[c * nc + base + g * s];
+            if (flip) Us[j * nU + IMOM(pb, dir)] = -Us[j * nU + IMOM(pb, dir)];
           }
           mpo_reconstruct_cell(pb, Us, dir, UL + (i + 1) * nU, UR + (i + 1) * nU,
                                VL + (i + 1) * nU, VR + (i + 1) * nU, NULL);

@@ -25,7 +25,7 @@ extern "C" {
 
 #define MPO_MAXP 8
 
-enum { MPO_BC_PERIODIC = 0, MPO_BC_OUTFLOW = 1 };
+enum { MPO_BC_PERIODIC = 0, MPO_BC_OUTFLOW = 1, MPO_BC_SYMMETRY = 2 };
 enum { MPO_RECON_WENO_C = 0, MPO_RECON_WENO_CL = 1 };
 enum { MPO_FLUX_HLLC = 0, MPO_FLUX_HLL = 1 };
 enum { MPO_MODEL_ALLAIRE = 0, MPO_MODEL_KAPILA = 1 };

@@ -28,7 +28,7 @@ PF_KFLOOR = 1e-6
 # medium of conductivity ~ PF_KFLOOR and the capped flux is negligible.
 PF_CFL = 1.0 / 12.0
 
-BC_PERIODIC, BC_OUTFLOW = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY = 0, 1, 2
 RECON_WENO_C, RECON_WENO_CL = 0, 1
 FLUX_HLLC, FLUX_HLL = 0, 1
 MODEL_ALLAIRE, MODEL_KAPILA = 0, 1

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-BC_PERIODIC, BC_OUTFLOW = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY = 0, 1, 2
 RECON_WENO_C, RECON_WENO_CL = 0, 1
 FLUX_HLLC, FLUX_HLL = 0, 1
 MODEL_ALLAIRE, MODEL_KAPILA = 0, 1
