@@ -59,7 +59,13 @@ typedef enum {
   MP_ERR_UNSUPPORTED = -7   /* valid but not built (e.g. N above the build) */
 } mp_status;
 
-enum { MP_BC_PERIODIC = 0, MP_BC_OUTFLOW = 1 };
+/* Boundary conditions per end: periodic (both ends of the direction),
+ * outflow (zero-gradient ghost cells), or a symmetry plane (ghost cells are
+ * the mirror images of the interior cells with the normal momentum negated:
+ * no mass crosses it; the planes of the shock-vessel-bubble problem,
+ * Sec. "Shock-vessel-bubble interaction").  The Phase-Field flux and
+ * Eq. (4) treat outflow ends and symmetry planes alike: no face. */
+enum { MP_BC_PERIODIC = 0, MP_BC_OUTFLOW = 1, MP_BC_SYMMETRY = 2 };
 enum { MP_RECON_WENO_C = 0, MP_RECON_WENO_CL = 1 };
 enum { MP_FLUX_HLLC = 0, MP_FLUX_HLL = 1 };
 enum { MP_MODEL_ALLAIRE = 0, MP_MODEL_KAPILA = 1 };

@@ -177,9 +177,23 @@ __device__ __forceinline__ int xcd_item(int b, int G, int swz) {
 }
 
 __device__ __forceinline__ int bc_map(int i, int n, int lo, int hi) {
-  if (i < 0) return lo == MP_BC_PERIODIC ? ((i % n) + n) % n : 0;
-  if (i >= n) return hi == MP_BC_PERIODIC ? i % n : n - 1;
+  if (i < 0) {
+    if (lo == MP_BC_PERIODIC) return ((i % n) + n) % n;
+    if (lo == MP_BC_SYMMETRY) return min(-1 - i, n - 1);
+    return 0;
+  }
+  if (i >= n) {
+    if (hi == MP_BC_PERIODIC) return i % n;
+    if (hi == MP_BC_SYMMETRY) return max(2 * n - 1 - i, 0);
+    return n - 1;
+  }
   return i;
+}
+
+// true when bc_map(i) is the mirror image across a symmetry plane: the
+// stand-in cell's normal momentum then changes sign
+__device__ __forceinline__ bool bc_mirror(int i, int n, int lo, int hi) {
+  return (i < 0 && lo == MP_BC_SYMMETRY) || (i >= n && hi == MP_BC_SYMMETRY);
 }
 
 template <int N, int D>
@@ -294,6 +308,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
     const int xm = bc_map(x, g.nx, g.bcx0, g.bcx1);
     Cons<N, D> c;
     load_cons<N, D>(a.Uk, nc, row + xm, c);
+    if (bc_mirror(x, g.nx, g.bcx0, g.bcx1)) c.mom[0] = -c.mom[0];
     Prim<N, D> v;
     cons_to_prim<N, D>(c, e, v);
 #pragma unroll
@@ -306,6 +321,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
   const int xm = bc_map(xi, g.nx, g.bcx0, g.bcx1);
   Cons<N, D> ub;
   load_cons<N, D>(a.Uk, nc, row + xm, ub);
+  if (bc_mirror(xi, g.nx, g.bcx0, g.bcx1)) ub.mom[0] = -ub.mom[0];
   {
     Prim<N, D> v;
     cons_to_prim<N, D>(ub, e, v);
@@ -440,6 +456,7 @@ void k_sweep_y(const Desc* __restrict__ descs,
     const int ym = bc_map(y, g.ny, g.bcy0, g.bcy1);
     Cons<N, D> c;
     load_cons<N, D>(a.Uk, nc, (int64_t)ym * g.nx + xc, c);
+    if (bc_mirror(y, g.ny, g.bcy0, g.bcy1)) c.mom[1] = -c.mom[1];
     Prim<N, D> v;
     cons_to_prim<N, D>(c, e, v);
 #pragma unroll
@@ -452,6 +469,7 @@ void k_sweep_y(const Desc* __restrict__ descs,
   const int ym = bc_map(yi, g.ny, g.bcy0, g.bcy1);
   Cons<N, D> ub;
   load_cons<N, D>(a.Uk, nc, (int64_t)ym * g.nx + xc, ub);
+  if (bc_mirror(yi, g.ny, g.bcy0, g.bcy1)) ub.mom[1] = -ub.mom[1];
   {
     Prim<N, D> v;
     cons_to_prim<N, D>(ub, e, v);
@@ -2135,7 +2153,8 @@ static mp_status validate(int32_t n_inst, const mp_weno_instance* inst,
     for (int d = 0; d < s.ndim; ++d) {
       if (s.n[d] < 1 || !(s.dx[d] > 0.0)) return MP_ERR_ARG;
       for (int k = 0; k < 2; ++k)
-        if (s.bc[d][k] != MP_BC_PERIODIC && s.bc[d][k] != MP_BC_OUTFLOW) return MP_ERR_ARG;
+        if (s.bc[d][k] < MP_BC_PERIODIC || s.bc[d][k] > MP_BC_SYMMETRY) return MP_ERR_ARG;
+      if ((s.bc[d][0] == MP_BC_PERIODIC) != (s.bc[d][1] == MP_BC_PERIODIC)) return MP_ERR_ARG;
     }
     for (int p = 0; p < s.nphase; ++p)
       if (!(s.gamma[p] > 1.0) || !std::isfinite(s.pinf[p]) || !std::isfinite(s.D[p]) ||
