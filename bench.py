@@ -10,7 +10,7 @@ FP64, WENO-C + HLLC, CFL 0.5.  Prints one JSON line.
 
 Inputs are synthetic and seeded (paper_2608_00746_amd.inputs) and resident in
 HBM before the timed region.  The roofline entry reports the stage kernel
-(x sweep + y sweep of one RK stage) against both roofs, the one it is closer
+(x sweep + y sweep, + z sweep in 3D, of one RK stage) against both roofs, the one it is closer
 to first:
 * HBM: algorithmic bytes per launch (8 n_U bytes per cell read of the stage
   state, 8 n_U per cell read of the step-start state in stages 2 and 3, 8 n_U
@@ -104,6 +104,8 @@ def workload(name, precision):
         ws = [I.advection_1d(200)]
     elif name == "batched_256":
         ws = I.batched()
+    elif name == "shock_vessel_bubble_400x200x200":
+        ws = [I.shock_vessel_bubble_3d(400, 200, 200)]
     else:
         raise SystemExit(f"unknown workload {name}")
     if precision is not None:
@@ -149,7 +151,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="advection_2d_512",
                     choices=["advection_2d_512", "shock_bubble_2048x1024",
-                             "shock_interface_n3_1024", "advection_1d_200", "batched_256"])
+                             "shock_interface_n3_1024", "advection_1d_200", "batched_256",
+                             "shock_vessel_bubble_400x200x200"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
@@ -215,7 +218,7 @@ def main():
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
 
-    # the stage kernels (x sweep + y sweep of one RK stage) timed by HIP event
+    # the stage kernels (x sweep + y (+ z) sweep of one RK stage) timed by HIP event
     # pairs the library records on its stream around each stage; a graph
     # cannot carry readable event timestamps, so these steps are launched
     # eagerly right after the timed region, from the state it left
@@ -263,7 +266,7 @@ def main():
         else:
             roof = dict(hbm, alu=alu)
     roof.update({
-        "kernel": "RK stage (x sweep + y sweep)",
+        "kernel": "RK stage (x sweep + transverse sweeps)",
         "avg_launch_ms": avg_launch_s * 1e3, "launches": k_n,
         "timing": "HIP events around each RK stage on the solver stream, "
                   "%d eager steps after the timed region" % prof_steps,

@@ -40,6 +40,7 @@
 namespace mpw {
 
 constexpr int kMaxN = 5;          // phases built
+constexpr int kMaxN3 = 3;         // phases built in 3D
 // Tile shapes (chosen per group by mp_weno_autotune; index 0 is the default):
 // x sweep strips of kXS[v] lanes (kXS[v] - 2 output cells), y sweep tiles of
 // kYX[v] x kYY[v] lanes (kYY[v] - 2 output rows).  The Phase-Field sweeps use
@@ -265,11 +266,12 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
 // ---------------------------------------------------------------------------
 // Waves per SIMD the sweeps are compiled for: one or two phases fit 3 (or 4)
 // waves in the register file with at most a few spilled values, which hides
-// FP64 latency better than 2 waves (measured +7..10 % on N = 2); three and
-// four phases would spill heavily at 3 and keep 2; five need the AGPRs too.
+// FP64 latency better than 2 waves (measured +7..10 % on N = 2 in 2D); two
+// phases in 3D, three and four phases would spill heavily at 3 and keep 2;
+// five need the AGPRs too.
 template <int N, int D>
 constexpr int sweep_waves() {
-  return N == 1 ? (D == 1 ? 4 : 3) : (N == 2 ? 3 : (N <= 4 ? 2 : 1));
+  return N == 1 ? (D == 1 ? 4 : 3) : (N == 2 ? (D == 3 ? 2 : 3) : (N <= 4 ? 2 : 1));
 }
 
 template <int N, int D, typename W, int PFM, int BX>
@@ -409,31 +411,45 @@ void k_sweep_x(const Desc* __restrict__ descs,
 }
 
 // ---------------------------------------------------------------------------
-// y sweep (2D) + RK epilogue
+// transverse sweeps: y (2D, 3D) and z (3D), RK epilogue in the last one
 // ---------------------------------------------------------------------------
-// A workgroup is a tile of kTX columns x kTY rows of lanes, one cell per lane
-// (lane (tx, ty) holds cell (x0 + tx, y0 - 1 + ty)); rows y0 .. y0 + kTY - 3
-// are its outputs.  Primitives of rows y0 - 3 .. y0 + kTY go to LDS (each row
-// segment is kTX contiguous doubles per component, one 128-byte line), every
-// lane reconstructs its cell along y from its column, and face states and
-// fluxes are traded with the neighbour row through LDS, as in the x sweep.
+// A workgroup is a tile of kTX columns x kTY lines of lanes in one plane,
+// one cell per lane (lane (tx, ty) holds cell (x0 + tx, l0 - 1 + ty) of the
+// sweep direction DIR); lines l0 .. l0 + kTY - 3 are its outputs.
+// Primitives of lines l0 - 3 .. l0 + kTY go to LDS (each line segment is kTX
+// x-contiguous doubles per component, one 128-byte line), every lane
+// reconstructs its cell along DIR from its column, and face states and
+// fluxes are traded with the neighbour line through LDS, as in the x sweep.
+// The plane: the whole grid in 2D; a z plane for the y sweep and a y plane
+// for the z sweep in 3D.  Sweeps before the last add their part of L into
+// the accumulator; the last one finishes the RK stage.
 
-template <int N, typename W, int PFM, int kTX, int kTY>
+template <int N, typename W, int PFM, int kTX, int kTY, int D, int DIR>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kTX * kTY),
-                          amdgpu_waves_per_eu(sweep_waves<N, 2>(), 8)))
-void k_sweep_y(const Desc* __restrict__ descs,
+                          amdgpu_waves_per_eu(sweep_waves<N, D>(), 8)))
+void k_sweep_t(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map,
                                                        int ninst, int stage, int swz) {
+  static_assert(D >= 2 && DIR >= 1 && DIR < D && (PFM == 0 || D == 2), "sweep shape");
+  constexpr bool kLast = DIR == D - 1;
   const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));
   const Desc d = descs[it.x];
   const Grid& g = d.g;
   const Eos& e = d.e;
   const StageArgs a = stage_args(d, stage);
+  constexpr int kOY = kTY - 2;      // output lines per tile
+  // the sweep line: its length, stride, end conditions and spacing
+  const int nl = DIR == 1 ? g.ny : g.nz;
+  const int64_t ls = DIR == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny;
+  const int blo = DIR == 1 ? g.bcy0 : g.bcz0, bhi = DIR == 1 ? g.bcy1 : g.bcz1;
+  const double rd = DIR == 1 ? g.rdy : g.rdz, hd = DIR == 1 ? g.hdy : g.hdz;
   const int ntx = (g.nx + kTX - 1) / kTX;
-  const int local = it.y;
+  const int per_plane = ntx * ((nl + kOY - 1) / kOY);
+  const int plane = it.y / per_plane;
+  const int local = it.y - plane * per_plane;
+  // plane base: z plane of the y sweep (3D), y plane of the z sweep
+  const int64_t pb = D == 2 ? 0 : (DIR == 1 ? (int64_t)plane * g.nx * g.ny : (int64_t)plane * g.nx);
   const int tyb = local / ntx, txb = local - tyb * ntx;
-  constexpr int kOY = kTY - 2;      // output rows per tile
-  constexpr int D = 2;
   constexpr int NV = 2 * N + D + 1;
   constexpr int NU = NV;
   constexpr int NF = 2 * N + 2 * D + 4;
@@ -453,10 +469,10 @@ void k_sweep_y(const Desc* __restrict__ descs,
   const int64_t nc = g.nc;
 
   auto put_prim = [&](int y, int slot) {
-    const int ym = bc_map(y, g.ny, g.bcy0, g.bcy1);
+    const int ym = bc_map(y, nl, blo, bhi);
     Cons<N, D> c;
-    load_cons<N, D>(a.Uk, nc, (int64_t)ym * g.nx + xc, c);
-    if (bc_mirror(y, g.ny, g.bcy0, g.bcy1)) c.mom[1] = -c.mom[1];
+    load_cons<N, D>(a.Uk, nc, pb + (int64_t)ym * ls + xc, c);
+    if (bc_mirror(y, nl, blo, bhi)) c.mom[DIR] = -c.mom[DIR];
     Prim<N, D> v;
     cons_to_prim<N, D>(c, e, v);
 #pragma unroll
@@ -466,10 +482,10 @@ void k_sweep_y(const Desc* __restrict__ descs,
     sprim[2 * N + D][slot][tx] = v.P;
   };
 
-  const int ym = bc_map(yi, g.ny, g.bcy0, g.bcy1);
+  const int ym = bc_map(yi, nl, blo, bhi);
   Cons<N, D> ub;
-  load_cons<N, D>(a.Uk, nc, (int64_t)ym * g.nx + xc, ub);
-  if (bc_mirror(yi, g.ny, g.bcy0, g.bcy1)) ub.mom[1] = -ub.mom[1];
+  load_cons<N, D>(a.Uk, nc, pb + (int64_t)ym * ls + xc, ub);
+  if (bc_mirror(yi, nl, blo, bhi)) ub.mom[DIR] = -ub.mom[DIR];
   {
     Prim<N, D> v;
     cons_to_prim<N, D>(ub, e, v);
@@ -484,7 +500,7 @@ void k_sweep_y(const Desc* __restrict__ descs,
   __syncthreads();
 
   Face<N, D> fm, fp;
-  reconstruct<N, D, W>([&](int c, int j) { return sprim[c][ty + j][tx]; }, ub, e, g, g.hdy, fm, fp);
+  reconstruct<N, D, W>([&](int c, int j) { return sprim[c][ty + j][tx]; }, ub, e, g, hd, fm, fp);
 
 #pragma unroll
   for (int p = 0; p < N; ++p) { sface[p][ty][tx] = fm.m[p]; sface[N + p][ty][tx] = fm.a[p]; }
@@ -521,7 +537,7 @@ void k_sweep_y(const Desc* __restrict__ descs,
       }
       pf_flux<N, D>(fp, R, G, kf, e, F);
     } else {
-      riemann<N, D, W>(fp, R, 1, g.flux, F);
+      riemann<N, D, W>(fp, R, DIR, g.flux, F);
     }
 #pragma unroll
     for (int c = 0; c < NU; ++c) sflux[c][ty][tx] = F.f[c];
@@ -529,8 +545,8 @@ void k_sweep_y(const Desc* __restrict__ descs,
   }
   __syncthreads();
 
-  if (ty >= 1 && ty < kTY - 1 && colok && yi < g.ny) {
-    const int64_t idx = (int64_t)yi * g.nx + x;
+  if (ty >= 1 && ty < kTY - 1 && colok && yi < nl) {
+    const int64_t idx = pb + (int64_t)yi * ls + x;
     double L[NU];
     if constexpr (PFM) {
 #pragma unroll
@@ -541,12 +557,17 @@ void k_sweep_y(const Desc* __restrict__ descs,
       one_plus_k<N, D>(ub, e, g.model, opk);
 #pragma unroll
       for (int c = 0; c < NU; ++c)
-        L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
-      const double du = (F.uh - sflux[NU][ty - 1][tx]) * g.rdy;
+        L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * rd;
+      const double du = (F.uh - sflux[NU][ty - 1][tx]) * rd;
 #pragma unroll
       for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
     }
-    finish_cell<N, D>(a, nc, idx, ub, L);
+    if constexpr (kLast) {
+      finish_cell<N, D>(a, nc, idx, ub, L);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NU; ++c) a.acc[(int64_t)c * nc + idx] = L[c];
+    }
   }
 }
 
@@ -605,6 +626,7 @@ __global__ __launch_bounds__(kRedBlock) void k_dt(const Desc* __restrict__ descs
     const double cs = sound_speed(num, den, rho);
     double s = (fabs(v.u[0]) + cs) * g.rdx;
     if constexpr (D > 1) s += (fabs(v.u[1]) + cs) * g.rdy;
+    if constexpr (D > 2) s += (fabs(v.u[2]) + cs) * g.rdz;
     smax = fmax(smax, s);
   }
   const double r = block_max(smax, sh);
@@ -1634,10 +1656,11 @@ struct Group {
   int N = 0, D = 0;
   std::vector<int> ids;            // context instance indices
   std::vector<Desc> hdesc;         // host copy of the descriptors
-  std::vector<int> xs[kXVar], ys[kYVar], rs;  // tile / chunk offsets (n + 1)
+  std::vector<int> xs[kXVar], ys[kYVar], zs[kYVar], rs;  // tile / chunk offsets (n + 1)
   Desc* desc = nullptr;
   int2* xmap[kXVar] = {};          // work item -> (instance, local tile)
   int2* ymap[kYVar] = {};
+  int2* zmap[kYVar] = {};          // z sweep (3D): tiles of the y-sweep shapes
   int2* rmap = nullptr;
   int xv = 0, yv = 0;              // tile shapes in use (autotuned)
   int swz = -1;                    // XCD order: -1 default rule, 0 off, 1 on
@@ -1669,11 +1692,14 @@ void launch_x(const Group& G, int stage, int swz, hipStream_t s) {
                      G.desc, G.xmap[V], n, stage, swz);
 }
 
-template <int N, typename W, int PFM, int V>
-void launch_y(const Group& G, int stage, int swz, hipStream_t s) {
+// transverse sweep along DIR (1: y, 2: z) of a D-dimensional group
+template <int N, typename W, int PFM, int V, int D, int DIR>
+void launch_t(const Group& G, int stage, int swz, hipStream_t s) {
   const int n = (int)G.ids.size();
-  hipLaunchKernelGGL((k_sweep_y<N, W, PFM, kYX[V], kYY[V]>), dim3(G.ys[V][n]),
-                     dim3(kYX[V] * kYY[V]), 0, s, G.desc, G.ymap[V], n, stage, swz);
+  const int tiles = DIR == 1 ? G.ys[V][n] : G.zs[V][n];
+  hipLaunchKernelGGL((k_sweep_t<N, W, PFM, kYX[V], kYY[V], D, DIR>), dim3(tiles),
+                     dim3(kYX[V] * kYY[V]), 0, s, G.desc, DIR == 1 ? G.ymap[V] : G.zmap[V], n,
+                     stage, swz);
 }
 
 // kind: 0 prep, 1 divJ + CG start, 2 K u with the dot products, 3 axpy,
@@ -1738,10 +1764,12 @@ void launch_diag(const Group& G, double* part, hipStream_t s) {
 }
 
 struct Table {
-  StageFn sx[2][kMaxN + 1][3][2][kXVar] = {};   // [PF flux][N][d][precision][shape]
-  StageFn sy[2][kMaxN + 1][2][kYVar] = {};
-  DtFn dt[kMaxN + 1][3] = {};
-  RedFn diag[kMaxN + 1][3] = {};
+  StageFn sx[2][kMaxN + 1][4][2][kXVar] = {};   // [PF flux][N][d][precision][shape]
+  StageFn sy[2][kMaxN + 1][2][kYVar] = {};      // 2D y sweep
+  StageFn sy3[kMaxN3 + 1][2][kYVar] = {};       // 3D y sweep (adds to the accumulator)
+  StageFn sz3[kMaxN3 + 1][2][kYVar] = {};       // 3D z sweep (finishes the stage)
+  DtFn dt[kMaxN + 1][4] = {};
+  RedFn diag[kMaxN + 1][4] = {};
   PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
   PfFn pfi[4][kMaxN + 1] = {};             // per-instance PF finishers
   MgFn mg[kMaxN + 1][3] = {};
@@ -1764,8 +1792,16 @@ void fill_shapes(Table& t) {
   t.sx[0][N][1][1][V] = launch_x<N, 1, float, 0, V>;
   t.sx[0][N][2][0][V] = launch_x<N, 2, double, 0, V>;
   t.sx[0][N][2][1][V] = launch_x<N, 2, float, 0, V>;
-  t.sy[0][N][0][V] = launch_y<N, double, 0, V>;
-  t.sy[0][N][1][V] = launch_y<N, float, 0, V>;
+  t.sy[0][N][0][V] = launch_t<N, double, 0, V, 2, 1>;
+  t.sy[0][N][1][V] = launch_t<N, float, 0, V, 2, 1>;
+  if constexpr (N <= kMaxN3) {
+    t.sx[0][N][3][0][V] = launch_x<N, 3, double, 0, V>;
+    t.sx[0][N][3][1][V] = launch_x<N, 3, float, 0, V>;
+    t.sy3[N][0][V] = launch_t<N, double, 0, V, 3, 1>;
+    t.sy3[N][1][V] = launch_t<N, float, 0, V, 3, 1>;
+    t.sz3[N][0][V] = launch_t<N, double, 0, V, 3, 2>;
+    t.sz3[N][1][V] = launch_t<N, float, 0, V, 3, 2>;
+  }
 }
 
 template <int N>
@@ -1778,8 +1814,8 @@ void fill(Table& t) {
   t.sx[1][N][1][1][0] = launch_x<N, 1, float, 1, 0>;
   t.sx[1][N][2][0][0] = launch_x<N, 2, double, 1, 0>;
   t.sx[1][N][2][1][0] = launch_x<N, 2, float, 1, 0>;
-  t.sy[1][N][0][0] = launch_y<N, double, 1, 0>;
-  t.sy[1][N][1][0] = launch_y<N, float, 1, 0>;
+  t.sy[1][N][0][0] = launch_t<N, double, 1, 0, 2, 1>;
+  t.sy[1][N][1][0] = launch_t<N, float, 1, 0, 2, 1>;
   fill_pf<N, 1>(t);
   fill_pf<N, 2>(t);
   t.pfi[0][N] = launch_pf_inst<N, 0>;
@@ -1790,6 +1826,10 @@ void fill(Table& t) {
   t.dt[N][2] = launch_dt<N, 2>;
   t.diag[N][1] = launch_diag<N, 1>;
   t.diag[N][2] = launch_diag<N, 2>;
+  if constexpr (N <= kMaxN3) {
+    t.dt[N][3] = launch_dt<N, 3>;
+    t.diag[N][3] = launch_diag<N, 3>;
+  }
 }
 
 static const Table& table() {
@@ -1880,8 +1920,12 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
     T.sx[pf][G.N][G.D][prec][pf ? 0 : G.xv](G, s, swz(G), c->stream);
   if (w == 1) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   if (w == 2) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
-  for (const Group& G : c->groups)
+  for (const Group& G : c->groups) {
     if (G.D == 2) T.sy[pf][G.N][prec][pf ? 0 : G.yv](G, s, swz(G), c->stream);
+    if (G.D == 3) T.sy3[G.N][prec][G.yv](G, s, swz(G), c->stream);
+  }
+  for (const Group& G : c->groups)
+    if (G.D == 3) T.sz3[G.N][prec][G.yv](G, s, swz(G), c->stream);
   if (w == 2 || w == 3) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -2126,6 +2170,7 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
     (void)hipFree(G.desc); (void)hipFree(G.rmap); (void)hipFree(G.rstart);
     for (auto* m : G.xmap) (void)hipFree(m);
     for (auto* m : G.ymap) (void)hipFree(m);
+    for (auto* m : G.zmap) (void)hipFree(m);
     for (auto* m : G.lmap) (void)hipFree(m);
   }
   (void)hipFree(c->dt); (void)hipFree(c->t); (void)hipFree(c->steps); (void)hipFree(c->part);
@@ -2147,9 +2192,9 @@ static mp_status validate(int32_t n_inst, const mp_weno_instance* inst,
   for (int i = 0; i < n_inst; ++i) {
     const mp_weno_instance& s = inst[i];
     if (s.ndim < 1 || s.ndim > 3 || !s.U) return MP_ERR_ARG;
-    if (s.ndim > 2) return MP_ERR_UNSUPPORTED;
+    if (s.ndim > 2 && opt->phase_field) return MP_ERR_UNSUPPORTED;   // Eq. (4) in 3D
     if (s.nphase < 1 || s.nphase > MP_MAXP) return MP_ERR_ARG;
-    if (s.nphase > kMaxN) return MP_ERR_UNSUPPORTED;
+    if (s.nphase > kMaxN || (s.ndim == 3 && s.nphase > kMaxN3)) return MP_ERR_UNSUPPORTED;
     for (int d = 0; d < s.ndim; ++d) {
       if (s.n[d] < 1 || !(s.dx[d] > 0.0)) return MP_ERR_ARG;
       for (int k = 0; k < 2; ++k)
@@ -2160,7 +2205,7 @@ static mp_status validate(int32_t n_inst, const mp_weno_instance* inst,
       if (!(s.gamma[p] > 1.0) || !std::isfinite(s.pinf[p]) || !std::isfinite(s.D[p]) ||
           !std::isfinite(s.pmin[p]))
         return MP_ERR_ARG;
-    const int64_t nc = (int64_t)s.n[0] * (s.ndim > 1 ? s.n[1] : 1);
+    const int64_t nc = (int64_t)s.n[0] * (s.ndim > 1 ? s.n[1] : 1) * (s.ndim > 2 ? s.n[2] : 1);
     if (nc > ((int64_t)1 << 31) - 1) return MP_ERR_UNSUPPORTED;
   }
   return MP_OK;
@@ -2201,7 +2246,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
     I.N = inst[i].nphase;
     I.D = inst[i].ndim;
     I.nU = 2 * I.N + I.D + 1;
-    I.nc = (int64_t)inst[i].n[0] * (I.D > 1 ? inst[i].n[1] : 1);
+    I.nc = (int64_t)inst[i].n[0] * (I.D > 1 ? inst[i].n[1] : 1) * (I.D > 2 ? inst[i].n[2] : 1);
     const size_t bytes = sizeof(double) * (size_t)I.nU * (size_t)I.nc;
     const bool ok = hipMalloc(&I.U1, bytes) == hipSuccess &&
                     hipMalloc(&I.U2, bytes) == hipSuccess &&
@@ -2221,7 +2266,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
 
   // group by (N, d); larger instances first inside a group
   size_t part_total = 0;
-  for (int D = 1; D <= 2; ++D)
+  for (int D = 1; D <= 3; ++D)
     for (int N = 1; N <= kMaxN; ++N) {
       Group G;
       G.N = N;
@@ -2234,6 +2279,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       });
       for (auto& v : G.xs) v.push_back(0);
       for (auto& v : G.ys) v.push_back(0);
+      for (auto& v : G.zs) v.push_back(0);
       G.rs.push_back(0);
       if (opt->phase_field) {
         // multigrid levels: halve (rounding up) until one cell; every
@@ -2308,6 +2354,11 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         g.bcx0 = s.bc[0][0]; g.bcx1 = s.bc[0][1];
         g.bcy0 = I.D > 1 ? s.bc[1][0] : 0;
         g.bcy1 = I.D > 1 ? s.bc[1][1] : 0;
+        g.nz = I.D > 2 ? s.n[2] : 1;
+        g.rdz = I.D > 2 ? 1.0 / s.dx[2] : 0.0;
+        g.hdz = I.D > 2 ? 0.5 * s.dx[2] : 1.0;
+        g.bcz0 = I.D > 2 ? s.bc[2][0] : 0;
+        g.bcz1 = I.D > 2 ? s.bc[2][1] : 0;
         g.recon = opt->recon;
         g.flux = opt->flux;
         g.model = opt->model;
@@ -2360,16 +2411,20 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         G.rs.push_back((int)std::min<int64_t>(top, INT32_MAX));
         for (int v = 0; v < kXVar; ++v) {
           const int64_t nstrip = (g.nx + kXS[v] - 3) / (kXS[v] - 2);
-          const int64_t nx = G.xs[v].back() + g.ny * nstrip;
+          const int64_t nx = G.xs[v].back() + (int64_t)g.ny * g.nz * nstrip;
           top = std::max(top, nx);
           G.xs[v].push_back((int)std::min<int64_t>(nx, INT32_MAX));
         }
         for (int v = 0; v < kYVar; ++v) {
+          // y tiles per z plane, z tiles per y plane (the same shapes)
           const int oy = kYY[v] - 2;
-          const int64_t nty = I.D > 1 ? (int64_t)((g.nx + kYX[v] - 1) / kYX[v]) * ((g.ny + oy - 1) / oy) : 0;
-          const int64_t ny = G.ys[v].back() + nty;
-          top = std::max(top, ny);
+          const int64_t ntx = (g.nx + kYX[v] - 1) / kYX[v];
+          const int64_t nty = I.D > 1 ? ntx * ((g.ny + oy - 1) / oy) * g.nz : 0;
+          const int64_t ntz = I.D > 2 ? ntx * ((g.nz + oy - 1) / oy) * g.ny : 0;
+          const int64_t ny = G.ys[v].back() + nty, nz = G.zs[v].back() + ntz;
+          top = std::max(top, std::max(ny, nz));
           G.ys[v].push_back((int)std::min<int64_t>(ny, INT32_MAX));
+          G.zs[v].push_back((int)std::min<int64_t>(nz, INT32_MAX));
         }
         if (top >= (int64_t)INT32_MAX) {
           mp_weno_destroy(c);
@@ -2406,7 +2461,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         return v;
       };
       const std::vector<int2> rm = tile_map(G.rs);
-      std::vector<int2> xm[kXVar], ym[kYVar];
+      std::vector<int2> xm[kXVar], ym[kYVar], zm[kYVar];
       bool ok = hipMalloc(&G.desc, sizeof(Desc) * m) == hipSuccess &&
                 hipMalloc(&G.rmap, sizeof(int2) * std::max<size_t>(rm.size(), 1)) == hipSuccess &&
                 hipMalloc(&G.rstart, sizeof(int) * (m + 1)) == hipSuccess;
@@ -2417,6 +2472,8 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       for (int v = 0; v < kYVar; ++v) {
         ym[v] = tile_map(G.ys[v]);
         ok = ok && hipMalloc(&G.ymap[v], sizeof(int2) * std::max<size_t>(ym[v].size(), 1)) == hipSuccess;
+        zm[v] = tile_map(G.zs[v]);
+        ok = ok && hipMalloc(&G.zmap[v], sizeof(int2) * std::max<size_t>(zm[v].size(), 1)) == hipSuccess;
       }
       G.xv = xv0;
       G.yv = yv0;
@@ -2436,7 +2493,10 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       for (int v = 0; v < kYVar; ++v)
         okc = okc && (ym[v].empty() ||
                       hipMemcpy(H.ymap[v], ym[v].data(), sizeof(int2) * ym[v].size(),
-                                hipMemcpyHostToDevice) == hipSuccess);
+                                hipMemcpyHostToDevice) == hipSuccess) &&
+              (zm[v].empty() ||
+               hipMemcpy(H.zmap[v], zm[v].data(), sizeof(int2) * zm[v].size(),
+                         hipMemcpyHostToDevice) == hipSuccess);
       for (int l = 0; l < H.nlev; ++l)
         okc = okc && hipMalloc(&H.lmap[l], sizeof(int2) * lm[l].size()) == hipSuccess &&
               hipMemcpy(H.lmap[l], lm[l].data(), sizeof(int2) * lm[l].size(),
@@ -2580,7 +2640,7 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
   for (Group& G : c->groups) {
     // every candidate timed in two interleaved rounds, the faster one kept:
     // a single round is at the mercy of clock and neighbour noise
-    const int nyv = G.D == 2 ? kYVar : 1;
+    const int nyv = G.D >= 2 ? kYVar : 1;
     float tmin[kXVar][kYVar][2];
     for (auto& a : tmin)
       for (auto& b : a) b[0] = b[1] = INFINITY;
@@ -2591,6 +2651,10 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
             auto run = [&]() {
               T.sx[0][G.N][G.D][prec][xv](G, 3, sw, c->stream);
               if (G.D == 2) T.sy[0][G.N][prec][yv](G, 3, sw, c->stream);
+              if (G.D == 3) {
+                T.sy3[G.N][prec][yv](G, 3, sw, c->stream);
+                T.sz3[G.N][prec][yv](G, 3, sw, c->stream);
+              }
             };
             run();   // warm-up
             float ms = 0.0f;
@@ -2625,8 +2689,8 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
     for (const Group& G : c->groups)
       for (int id : G.ids) {
         choice[4 * id + 0] = kXS[G.xv];
-        choice[4 * id + 1] = G.D == 2 ? kYX[G.yv] : 0;
-        choice[4 * id + 2] = G.D == 2 ? kYY[G.yv] : 0;
+        choice[4 * id + 1] = G.D >= 2 ? kYX[G.yv] : 0;
+        choice[4 * id + 2] = G.D >= 2 ? kYY[G.yv] : 0;
         choice[4 * id + 3] = G.swz;
       }
   return MP_OK;

@@ -27,11 +27,11 @@ struct Eos {
 };
 
 struct Grid {
-  int nx, ny;
+  int nx, ny, nz;          // cells per direction (1 beyond the dimension)
   int64_t nc;              // cells
-  double rdx, rdy;         // 1/dx, 1/dy
-  double hdx, hdy;         // dx/2, dy/2 (slopes of the consistent limiter)
-  int bcx0, bcx1, bcy0, bcy1;
+  double rdx, rdy, rdz;    // 1/dx, 1/dy, 1/dz
+  double hdx, hdy, hdz;    // dx/2, dy/2, dz/2 (slopes of the consistent limiter)
+  int bcx0, bcx1, bcy0, bcy1, bcz0, bcz1;
   int recon, flux, model, energy;
 };
 

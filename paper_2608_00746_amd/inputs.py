@@ -397,6 +397,47 @@ def batched(seed=0, count=256, opts=None, select=None):
     return [batched_instance(n[i], N[i], r[i], Ps[i], opts) for i in idx]
 
 
+GELATIN_SI = (6.72, 3.70e8, 0.0)          # 10 % gelatin ("tissue")
+
+
+def shock_vessel_bubble_3d(nx=400, ny=200, nz=200, opts=None):
+    """The shock-vessel-bubble problem (Sec. "Shock-vessel-bubble
+    interaction"): a quarter of the domain, [-50, 50] x [0, 50] x [0, 50] um,
+    with symmetry planes at y = 0 and z = 0 and outflow elsewhere.  Phase 1
+    air bubble r = 10 um at the origin, inside a water vessel (phase 2, the
+    cylinder of radius 13 um about the z axis), in gelatin (phase 3); a
+    40 MPa shock in the gelatin at x > 20 um moving left (u = -24.2 m/s,
+    rho_3 = 1046).  The sharp initial interfaces of the paper are smoothed
+    over one cell (alpha = (1 + tanh(psi / dx)) / 2 at the cell centres) so
+    that the state is a smooth function of position at the grid scale."""
+    g, pi, D = _eos([AIR_SI, WATER_SI, GELATIN_SI])
+    L = 50e-6
+    dx, dy, dz = 2 * L / nx, L / ny, L / nz
+    x = -L + (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    z = (np.arange(nz) + 0.5) * dz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    w = min(dx, dy, dz)
+    a1 = 0.5 * (1.0 + np.tanh((10e-6 - np.sqrt(X ** 2 + Y ** 2 + Z ** 2)) / w))
+    out = 0.5 * (1.0 + np.tanh((np.sqrt(X ** 2 + Y ** 2) - 13e-6) / w))
+    a3 = (1.0 - a1) * out
+    a2 = np.clip(1.0 - a1 - a3, 0.0, 1.0)
+    alpha = np.stack([a1, a2, a3])
+    post = X > 20e-6
+    rho3 = np.where(post, 1046.0, 1030.0)
+    m = np.stack([1.204 * a1, 1000.0 * a2, rho3 * a3])
+    # the shock lies in the gelatin: velocity and pressure follow phase 3
+    u = np.zeros((3,) + X.shape)
+    u[0] = np.where(post, -24.2, 0.0) * a3
+    P = np.where(post, 101325.0 + (4.0e7 - 101325.0) * a3, 101325.0)
+    U = conserved(alpha, m, u, P, g, pi, D)
+    bc = ((BC_OUTFLOW, BC_OUTFLOW), (BC_SYMMETRY, BC_OUTFLOW), (BC_SYMMETRY, BC_OUTFLOW))
+    return Workload("shock_vessel_bubble_%dx%dx%d" % (nx, ny, nz), 3, (nx, ny, nz),
+                    (dx, dy, dz), bc, g, pi, D, default_pmin(pi, 101325.0),
+                    np.zeros(3), U, 0.0,
+                    opts or Options(flux=FLUX_HLL, cfl=0.2))
+
+
 # ---------------------------------------------------------------------------
 # the paper's verification problems (Sec. 4.1)
 # ---------------------------------------------------------------------------

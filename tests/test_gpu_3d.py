@@ -1,0 +1,153 @@
+"""The 3D path (x sweep over rows, y sweep per z plane adding to the
+accumulator, z sweep per y plane finishing the stage) against the oracle and
+against the 2D path, for the shock-vessel-bubble problem (Sec. "Shock-vessel-
+bubble interaction"): 3D, N = 3, symmetry planes at y = 0 and z = 0.
+
+* A 3D grid with one periodic cell along z reproduces the 2D L(U) bit for
+  bit (its z fluxes cancel exactly), FP64 and mixed;
+* L(U) against the oracle to the FP64 bars (1e-12 dt-scaled, 1e-10 raw) on
+  rough random 3D states and the shock-vessel-bubble state, and to the mixed
+  bound (1e-4 raw);
+* a window of CFL steps against the oracle (1e-12 on states);
+* a batch of 3D and 2D instances reproduces solo runs bitwise;
+* the benchmark size (400 x 200 x 200) stays finite, sum alpha = 1 and in
+  bounds over a few steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2608_00746_amd import inputs as I
+from conftest import oracle_problem
+from test_gpu_parity import TOL, _check_rhs, _scales
+from test_oracle_3d import as_3d
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+
+
+def _solver(ws, **kw):
+    from paper_2608_00746_amd.binding import Solver
+    return Solver(ws if isinstance(ws, list) else [ws], **kw)
+
+
+@pytest.mark.parametrize("N,seed", [(1, 11), (2, 12), (3, 13)])
+@pytest.mark.parametrize("precision", [I.PREC_FP64, I.PREC_MIXED])
+def test_3d_with_one_z_cell_is_2d_gpu(N, seed, precision):
+    w = I.random_state((40, 33), nphase=N, seed=seed, lowp=0.0)
+    w.bc = ((I.BC_PERIODIC, I.BC_PERIODIC), (I.BC_OUTFLOW, I.BC_SYMMETRY))
+    w.opts.precision = precision
+    w3 = as_3d(w)
+    s2, s3 = _solver(w), _solver(w3)
+    L2 = s2.rhs()[0].cpu().numpy().reshape(w.nU, -1)
+    L3 = s3.rhs()[0].cpu().numpy().reshape(w3.nU, -1)
+    s2.close()
+    s3.close()
+    keep = [c for c in range(w3.nU) if c != N + 2]
+    assert np.array_equal(L3[keep], L2)
+    assert np.all(L3[N + 2] == 0.0)
+
+
+CASES = [
+    lambda: I.random_state((12, 10, 9), nphase=1, seed=21, lowp=0.0),
+    lambda: I.random_state((11, 9, 10), nphase=2, seed=22, lowp=0.0, bc=I.BC_OUTFLOW),
+    lambda: I.random_state((9, 10, 12), nphase=3, seed=23, lowp=0.0),
+    lambda: I.shock_vessel_bubble_3d(24, 12, 12),
+    lambda: I.shock_vessel_bubble_3d(48, 20, 18),
+    lambda: I.random_state((70, 9, 6), nphase=2, seed=26, lowp=0.0),
+]
+
+
+@pytest.mark.parametrize("make", CASES)
+def test_3d_rhs_vs_oracle(oracle, make):
+    w = make()
+    if w.name.startswith("random"):
+        w.bc = (tuple(w.bc[0]), (I.BC_SYMMETRY, I.BC_OUTFLOW), tuple(w.bc[2]))
+    _check_rhs(oracle, w)
+
+
+@pytest.mark.parametrize("make", [CASES[2], CASES[3]])
+def test_3d_rhs_mixed_vs_oracle(oracle, make):
+    w = make()
+    w.opts.precision = I.PREC_MIXED
+    s = _solver(w)
+    Lg = s.rhs()[0].cpu().numpy().reshape(w.nU, -1)
+    s.close()
+    pb = oracle_problem(oracle, w)
+    U = w.U.reshape(-1)
+    Lo = pb.rhs(U).reshape(w.nU, -1)
+    dt = pb.dt(U, 0.0)
+    sc = _scales(w)
+    Lmax = np.abs(Lo).max(axis=1)
+    raw = np.abs(Lg - Lo).max(axis=1) / np.where(Lmax > 0, Lmax, 1.0)
+    significant = dt * Lmax > 1e-10 * sc
+    print(w.name, "3D mixed rhs rel err:", np.array2string(raw, precision=2))
+    assert np.isfinite(Lg).all()
+    assert (raw[significant] <= 1e-4).all(), raw
+
+
+def test_3d_steps_vs_oracle(oracle):
+    w = I.shock_vessel_bubble_3d(32, 16, 16)
+    w.t_end = 0.0
+    pb = oracle_problem(oracle, w, t_end=0.0)
+    s = _solver(w)
+    U = w.U.reshape(-1).copy()
+    K = 3
+    for _ in range(K):
+        dt = pb.dt(U, 0.0)
+        assert abs(s.dt()[0] - dt) <= 1e-12 * dt
+        U = pb.step(U, dt)
+        s.step()
+    Ug = s.host(0).reshape(w.nU, -1)
+    err = np.abs(Ug - U.reshape(w.nU, -1)).max(axis=1) / _scales(w, U)
+    print("3D shock-vessel-bubble state rel err after", K, "steps:",
+          np.array2string(err, precision=2))
+    assert (err <= TOL).all(), err
+    d = s.diag()[0]
+    assert d[25] == 0 and d[27] == K
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [I.PREC_FP64, I.PREC_MIXED])
+def test_3d_batched_bitwise_vs_solo(precision):
+    ws = [I.shock_vessel_bubble_3d(30, 14, 12), I.random_state((13, 11, 9), nphase=2, seed=24, lowp=0.0),
+          I.random_state((40, 31), nphase=3, seed=25, lowp=0.0),
+          I.shock_vessel_bubble_3d(16, 16, 16)]
+    for w in ws:
+        w.opts.precision = precision
+        w.opts.flux = I.FLUX_HLL
+        w.opts.cfl = 0.2
+    b = _solver(ws)
+    solos = [_solver(w) for w in ws]
+    for _ in range(3):
+        b.step()
+        for s in solos:
+            s.step()
+    for i, s in enumerate(solos):
+        assert np.array_equal(b.host(i), s.host(0)), i
+        s.close()
+    b.close()
+
+
+def test_3d_full_size_invariants():
+    w = I.shock_vessel_bubble_3d(400, 200, 200)
+    s = _solver(w)
+    tiles = s.autotune()
+    K = 4
+    for _ in range(K):
+        s.step()
+    d = s.diag()[0]
+    s.close()
+    print("3D full size: tiles", tiles[0], "dt", d[26], "min m", d[21], "alpha err", d[20])
+    assert d[25] == 0 and d[27] == K
+    assert d[20] <= 16 * 3 * EPS * np.sqrt(K)
+    assert d[21] >= -8 * EPS and d[22] >= -8 * EPS and d[23] <= 1 + 8 * EPS
+
+
+def test_3d_phase_field_unsupported():
+    from paper_2608_00746_amd.binding import MpWenoError, ERR_UNSUPPORTED
+    w = I.shock_vessel_bubble_3d(16, 8, 8)
+    w.opts.phase_field = 1
+    with pytest.raises(MpWenoError) as ei:
+        _solver(w)
+    assert ei.value.status == ERR_UNSUPPORTED

@@ -10,7 +10,11 @@ Metrics (per conserved component c):
   L is a difference of fluxes that can be ~1e3 times larger than L itself
   (the HLLC contact speed sums rho c terms of 1.4e6 in water while the
   momentum RHS of an advected interface is ~1e3), so two correct FP64
-  evaluation orders differ there by ~1e3 ulp of L.
+  evaluation orders differ there by ~1e3 ulp of L.  Where L is a near-total
+  cancellation (transverse momentum across a planar shock, ~1e-7 of the
+  state per step) that ratio has no bound, so the raw bar is
+  1e-10 max |L_orc| + 64 eps max |U_orc| / dt_cfl, the second term being the
+  rounding of the face fluxes themselves.
 Bitwise checks: absent phases, N vs N-1, graph replay and run-to-run
 determinism.
 """
@@ -74,6 +78,12 @@ def _check_rhs(oracle, w, tol=TOL):
     raw = _rel_err(Lg, Lo, w.nU)
     # the raw relative error is meaningful only where L is above round-off
     significant = dt * Lmax > 1e-10 * sc
+    # L is a difference of face fluxes of size ~ sc / dt (CFL-scaled): each
+    # carries rounding of a few eps of that size, which a component whose L
+    # is itself a near-cancellation (transverse momentum across a planar
+    # shock) sees at full weight; the raw bar sits on top of that floor
+    Dmax = np.abs((Lg - Lo).reshape(w.nU, -1)).max(axis=1)
+    raw_bar = TOL_RAW_RHS * Lmax + 64 * np.finfo(float).eps * sc / dt
     print(w.name, "rhs raw rel err:", np.array2string(raw, precision=2),
           "| dt-scaled:", np.array2string(inc, precision=2))
     if not (inc <= tol).all():
@@ -84,7 +94,7 @@ def _check_rhs(oracle, w, tol=TOL):
               "orc", Lo.reshape(w.nU, -1)[:, i])
     assert np.isfinite(Lg).all()
     assert (inc <= tol).all(), inc
-    assert (raw[significant] <= TOL_RAW_RHS).all(), raw
+    assert (Dmax[significant] <= raw_bar[significant]).all(), raw
     return raw
 
 
@@ -292,14 +302,17 @@ def test_invalid_arguments():
         with pytest.raises(MpWenoError) as ei:
             _solver(w, opts=o)
         assert ei.value.status == ERR_ARG
-    w = I.random_state((16,), nphase=2, seed=1)
-    w.ndim = 3
-    w.n = (16, 1, 1)
-    w.dx = (w.dx[0], 1.0, 1.0)
-    w.bc = w.bc * 3
+    # 3D carries at most three phases (the y and z sweeps hold a register
+    # budget for N <= 3)
+    w = I.random_state((8, 6, 5), nphase=4, seed=1)
     with pytest.raises(MpWenoError) as ei:
         _solver(w)
     assert ei.value.status == ERR_UNSUPPORTED
+    w = I.random_state((8, 6, 5), nphase=2, seed=1)
+    w.bc = ((I.BC_PERIODIC, I.BC_OUTFLOW),) + tuple(w.bc[1:])
+    with pytest.raises(MpWenoError) as ei:
+        _solver(w)
+    assert ei.value.status == ERR_ARG
 
 
 def test_shock_bubble_stays_finite():
