@@ -74,7 +74,7 @@ enum { MP_WHERE_DEVICE = 0, MP_WHERE_HOST = 1 };
 
 /* One uniform-grid problem instance (Sec. 2.1 and Eq. (26)). */
 typedef struct {
-  int32_t ndim;            /* 1 or 2                                         */
+  int32_t ndim;            /* 1, 2 or 3 (3: N <= 3, no Phase-Field step)    */
   int32_t n[3];            /* cells per direction, n[k] >= 1; unused = 1     */
   double dx[3];            /* uniform cell size per direction, > 0           */
   int32_t bc[3][2];        /* MP_BC_* at the low/high end of each direction  */
@@ -129,8 +129,11 @@ int32_t mp_weno_max_phases(void);
  * vectors r, p, K p, w and u, the diagonal and the face gradients) and the
  * multigrid hierarchy (3 N doubles per cell on the finest level, 6 N per
  * cell of each coarser one: about 5 N per cell in 2D, 9 N in 1D).
- * Errors: MP_ERR_ARG (bad sizes, gamma <= 1, dx <= 0, phase_field with
- * eta_over_dx <= 0, ...), MP_ERR_UNSUPPORTED (N or ndim beyond the build),
+ * Errors: MP_ERR_ARG (ndim outside 1..3, bad sizes, gamma <= 1, dx <= 0, a
+ * boundary code out of range, periodic at one end of a direction only,
+ * phase_field with eta_over_dx <= 0, ...), MP_ERR_UNSUPPORTED (valid but
+ * beyond the build: N > mp_weno_max_phases(), or in 3D N > 3 or
+ * phase_field),
  * MP_ERR_OOM, MP_ERR_HIP.
  * On error *ctx is NULL. */
 mp_status mp_weno_init(mp_weno_ctx **ctx, int32_t n_inst,
@@ -169,8 +172,9 @@ mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
                             double *const *dUdt);
 
 /* Autotuner: for every group of instances with the same (N, d), time the
- * tile shapes of the two sweeps (x strips of 256, 128 or 64 lanes; y tiles
- * of 16 x 16, 32 x 8 or 16 x 24 lanes) and the XCD-aware tile order (off / on) on the
+ * tile shapes of the sweeps (x strips of 256, 128 or 64 lanes; y tiles, and
+ * in 3D z tiles of the same shape, of 16 x 16, 32 x 8 or 16 x 24 lanes) and
+ * the XCD-aware tile order (off / on) on the
  * current states, reps launches each (0: 8) in two interleaved rounds (the
  * faster round counts), and keep the fastest for the
  * hyperbolic sweeps of later calls.  The timing evaluates L(U) into the

@@ -5,19 +5,21 @@
 // of instance descriptors (grid, EOS, buffer pointers), and every kernel
 // launch covers all tiles of all instances of the group: a workgroup finds its
 // instance by binary search over per-instance tile offsets, so a batch of
-// uneven instances is one launch per sweep.  One RK stage of a 2D group is two
-// launches:
-//   k_sweep_x : one workgroup per (instance, row, 254-cell strip).  Each lane
-//               converts one cell to primitives into an LDS row, reconstructs
-//               its cell along x from the five LDS neighbours, trades its
-//               minus-side face state with the left neighbour through LDS,
-//               computes the flux of its plus-side face, trades fluxes, and
-//               writes the x part of L(U) to a direction accumulator (1D:
-//               finishes the RK stage directly).
-//   k_sweep_y : the same exchange pattern on 16 x 16 tiles of lanes (one
-//               cell per lane, neighbours in y through LDS, 128-byte row
-//               segments); it adds the accumulator and applies the RK stage.
-// Both sweeps read the same stage state (unsplit, dimension by dimension).
+// uneven instances is one launch per sweep.  One RK stage of a d-dimensional
+// group is d launches:
+//   k_sweep_x : one workgroup per (instance, row, strip of up to 254 cells).
+//               Each lane converts one cell to primitives into an LDS row,
+//               reconstructs its cell along x from the five LDS neighbours,
+//               trades its minus-side face state with the left neighbour
+//               through LDS, computes the flux of its plus-side face, trades
+//               fluxes, and writes the x part of L(U) to a direction
+//               accumulator (1D: finishes the RK stage directly).
+//   k_sweep_t : the same exchange pattern along y (2D, 3D) or z (3D) on
+//               16 x 16 tiles of lanes in one plane (one cell per lane,
+//               neighbours along the sweep through LDS, 128-byte row
+//               segments); it adds its part to the accumulator, and the last
+//               direction applies the RK stage.
+// Every sweep reads the same stage state (unsplit, dimension by dimension).
 // Workgroup indices can be remapped so that consecutive tiles (which share
 // halo rows) run on the same XCD and its L2.  The CFL step and the
 // diagnostics are per-instance reductions with a fixed order (no
@@ -42,8 +44,9 @@ namespace mpw {
 constexpr int kMaxN = 5;          // phases built
 constexpr int kMaxN3 = 3;         // phases built in 3D
 // Tile shapes (chosen per group by mp_weno_autotune; index 0 is the default):
-// x sweep strips of kXS[v] lanes (kXS[v] - 2 output cells), y sweep tiles of
-// kYX[v] x kYY[v] lanes (kYY[v] - 2 output rows).  The Phase-Field sweeps use
+// x sweep strips of kXS[v] lanes (kXS[v] - 2 output cells), y and z sweep
+// tiles of kYX[v] x kYY[v] lanes (kYY[v] - 2 output lines; one shape for both
+// in 3D).  The Phase-Field sweeps use
 // the defaults.
 constexpr int kXVar = 3, kYVar = 3;
 constexpr int kXS[kXVar] = {256, 128, 64};

@@ -48,6 +48,11 @@ def test_3d_with_one_z_cell_is_2d_gpu(N, seed, precision):
     assert np.all(L3[N + 2] == 0.0)
 
 
+def _kapila(w):
+    w.opts.model = I.MODEL_KAPILA
+    return w
+
+
 CASES = [
     lambda: I.random_state((12, 10, 9), nphase=1, seed=21, lowp=0.0),
     lambda: I.random_state((11, 9, 10), nphase=2, seed=22, lowp=0.0, bc=I.BC_OUTFLOW),
@@ -55,6 +60,9 @@ CASES = [
     lambda: I.shock_vessel_bubble_3d(24, 12, 12),
     lambda: I.shock_vessel_bubble_3d(48, 20, 18),
     lambda: I.random_state((70, 9, 6), nphase=2, seed=26, lowp=0.0),
+    # the paper runs this problem with both models (Sec. "Shock-vessel-bubble
+    # interaction")
+    lambda: _kapila(I.shock_vessel_bubble_3d(24, 12, 12)),
 ]
 
 
