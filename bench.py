@@ -24,6 +24,10 @@ kernel's stream around each stage, in a short eager pass right after the
 timed steps (those replay a captured graph, which cannot carry readable event
 timestamps).  `traffic` is the measured HBM bytes per launch from the same
 table, when it holds a row for this workload, tile choice and kernel source.
+
+`with_phase_field` times the same workload with every step followed by the
+Phase-Field step (the whole path of the method, Eqs. (28), (4) and (5)
+included); `value` is the hyperbolic step alone, the workload as stated.
 """
 from __future__ import annotations
 
@@ -144,6 +148,37 @@ def cpu_baseline(ws, seconds):
                       f"{el:.1f} s, OpenMP over grid lines"}
 
 
+def pf_rate(name, precision, stream, steps):
+    """The whole path per step: the hyperbolic step followed by the
+    Phase-Field step (Eqs. (28), (4), (5)), same workload, eager steps (the
+    solve checks convergence on the host), timed with events on the solver
+    stream after two warm-up steps."""
+    import torch
+    from paper_2608_00746_amd.binding import MpWenoError, Solver
+    ws = workload(name, precision)
+    for w in ws:
+        w.opts.phase_field = 1
+    try:
+        s = Solver(ws, stream=stream)
+    except MpWenoError as err:
+        return {"value": None, "note": str(err)}
+    cells = sum(w.ncells for w in ws)
+    s.advance(2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.advance(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    its = float(s.diag()[:, 29].max())
+    s.close()
+    return {"value": cells * steps / (ms / 1e3), "unit": "cell-updates/s",
+            "ms_per_step": ms / steps, "steps": steps,
+            "cg_iterations_last_step": its}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +201,9 @@ def main():
                          "x<lanes>/y<X>x<Y>/<plain|xcd> (the form the bench line reports)")
     ap.add_argument("--phase-field", action="store_true",
                     help="end every step with the Phase-Field step (reported separately)")
+    ap.add_argument("--pf-steps", type=int, default=10,
+                    help="after the main line's measurement, time this many steps of the "
+                         "same workload with the Phase-Field step on (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -306,9 +344,11 @@ def main():
         out["instances_per_s"] = len(ws) * args.steps / (ms / 1e3)
     if args.phase_field:
         out["pf_cg_iterations_last_step"] = cg_its
+    s.close()
+    if args.pf_steps > 0 and not args.phase_field:
+        out["with_phase_field"] = pf_rate(args.workload, args.precision, stream, args.pf_steps)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_seconds)
-    s.close()
     print(json.dumps(out), flush=True)
 
 

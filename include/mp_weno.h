@@ -125,10 +125,10 @@ int32_t mp_weno_max_phases(void);
  * captures on the stream); every later call is ordered on it.
  * Allocates the scratch: two RK stage buffers and one direction accumulator
  * per instance (3 n_U doubles per cell) plus small reduction buffers; with
- * phase_field, (9 + d) N doubles per cell more (k_p, [div J_p], Q_p, the CG
- * vectors r, p, K p, w and u, the diagonal and the face gradients) and the
- * multigrid hierarchy (3 N doubles per cell on the finest level, 6 N per
- * cell of each coarser one: about 5 N per cell in 2D, 9 N in 1D).
+ * phase_field, (8 + d) N doubles per cell more (k_p, [div J_p], Q_p, the CG
+ * vectors r, p, K p, w and u, and the face gradients) and the FP32
+ * multigrid hierarchy (6 N floats per cell of every level: about 8 N floats
+ * per cell in 2D, 12 N in 1D).
  * Errors: MP_ERR_ARG (ndim outside 1..3, bad sizes, gamma <= 1, dx <= 0, a
  * boundary code out of range, periodic at one end of a direction only,
  * phase_field with eta_over_dx <= 0, ...), MP_ERR_UNSUPPORTED (valid but

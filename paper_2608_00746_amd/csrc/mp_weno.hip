@@ -62,7 +62,7 @@ constexpr int kPartSlots = 40;    // partial slots per reduction chunk (stored s
 // done flag, iterations, mean of the preconditioned residual, true relative
 // residual at the previous start
 constexpr int kPfsLen = 80;
-constexpr int kPfFields = 9;      // Phase-Field work arrays of N fields each
+constexpr int kPfFields = 8;      // Phase-Field work arrays of N fields each
 // floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
 // is solvable for every right side of zero total and stays conditioned; only
 // cells with phi or 1 - phi below ~1e-6 see it
@@ -87,8 +87,11 @@ constexpr int kPfsM = 0, kPfsMe2 = 1, kPfsB = 2, kPfsIts = 10, kPfsRes = 11,
 // also count against the LDS wait counter).  They always point to global
 // memory; these types say so.
 using gdouble = __attribute__((address_space(1))) double;
+using gfloat = __attribute__((address_space(1))) float;
 __device__ __forceinline__ const gdouble* gptr(const double* p) { return (const gdouble*)p; }
 __device__ __forceinline__ gdouble* gptr(double* p) { return (gdouble*)p; }
+__device__ __forceinline__ const gfloat* gptr(const float* p) { return (const gfloat*)p; }
+__device__ __forceinline__ gfloat* gptr(float* p) { return (gfloat*)p; }
 
 struct StageArgs {
   const gdouble* Uk;  // stage state (stencils)
@@ -103,16 +106,20 @@ struct StageArgs {
 // One level of the multigrid preconditioner of Eq. (4) for one instance
 // (every array holds the N phases one after the other, [N][nc]).  Level 0 is
 // the grid itself; level l + 1 aggregates 2 x 2 cells of level l (a single
-// cell or row at an odd end) down to one cell.
+// cell or row at an odd end) down to one cell.  The preconditioner works in
+// FP32 (half the bytes of every pass; CG, its residual and the convergence
+// test stay FP64): level 0 reads the FP64 CG residual once, scaled by a power
+// of two near the rms of [div J_p] (exact, and far from the FP32 range
+// limits), and writes the FP64 preconditioned residual once, scaled back.
 struct MgLevel {
   int nx, ny;
   int64_t nc;
-  double* wx;        // weight of the face to the +x neighbour (0: no face)
-  double* wy;        // weight of the face to the +y neighbour
-  double* dg;        // diagonal: sum of the cell's face weights
-  double* e;         // correction
-  double* t;         // Jacobi ping-pong
-  double* f;         // right-hand side (level 0: the CG residual)
+  float* wx;         // weight of the face to the +x neighbour (0: no face)
+  float* wy;         // weight of the face to the +y neighbour
+  float* dg;         // diagonal: sum of the cell's face weights
+  float* e;          // correction
+  float* t;          // Jacobi ping-pong
+  float* f;          // right-hand side (level 0: the scaled CG residual)
 };
 
 // One instance as the kernels see it (device memory, read with scalar loads).
@@ -142,7 +149,6 @@ struct Desc {
   double* pf_p;              // CG direction                       [N][cells]
   double* pf_ap;             // CG s = K p                         [N][cells]
   double* pf_w;              // CG w = K u                         [N][cells]
-  double* pf_dg;             // diagonal of K                      [N][cells]
   double* pf_u;              // preconditioned residual u = M^-1 r [N][cells]
   const struct MgLevel* mg;  // multigrid levels of the preconditioner
   int nlev;
@@ -820,14 +826,13 @@ __device__ __forceinline__ int64_t nbr(const Grid& g, int D, int x, int y, int d
   return (int64_t)yn * g.nx + x;
 }
 
-// (K v)_i, (|K| |v|)_i and the Jacobi diagonal for phase p at cell i
+// (K v)_i and (|K| |v|)_i for phase p at cell i
 template <int D>
 __device__ __forceinline__ void k_apply(const Grid& g, const gdouble* __restrict__ k,
                                         const gdouble* __restrict__ v, int64_t i, int x, int y,
-                                        double& Kv, double& aKv, double& diag) {
+                                        double& Kv, double& aKv) {
   Kv = 0.0;
   aKv = 0.0;
-  diag = 0.0;
   const double ki = k[i], vi = v[i];
 #pragma unroll
   for (int dir = 0; dir < D; ++dir) {
@@ -839,7 +844,6 @@ __device__ __forceinline__ void k_apply(const Grid& g, const gdouble* __restrict
         const double kf = 0.5 * (ki + k[j]) * r2;
         Kv += kf * (vi - v[j]);
         aKv += kf * (fabs(vi) + fabs(v[j]));
-        diag += kf;
       }
     }
   }
@@ -965,7 +969,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_setup(const Desc* __restrict__
 }
 
 // [div J_p] at every cell; start (or restart) of the CG solve: the residual
-// of the warm start r = -b - K Q and the Jacobi diagonal; partials [p]
+// of the warm start r = -b - K Q; partials [p]
 // ||b||^2, [N + p] ||r||^2 and [2N + p] || |b| + |K| |Q| ||^2 (the scale of
 // the rounding error of r)
 template <int N, int D>
@@ -1017,18 +1021,13 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
       const int64_t ip = (int64_t)p * nc + i;
       gptr(d.pf_b)[ip] = b;
       // K Q = -b from the previous Q (or 0)
-      double Kq = 0.0, aKq = 0.0, dg = 0.0;
-      const gdouble* Kp = K + (int64_t)p * nc;
-      if (cold) {
-        double dummy, dummy2;
+      double Kq = 0.0, aKq = 0.0;
+      if (cold)
         gptr(d.pf_q)[ip] = 0.0;
-        k_apply<D>(g, Kp, Kp, i, x, y, dummy, dummy2, dg);
-      } else {
-        k_apply<D>(g, Kp, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, aKq, dg);
-      }
+      else
+        k_apply<D>(g, K + (int64_t)p * nc, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, aKq);
       const double r = -b - Kq;
       gptr(d.pf_r)[ip] = r;
-      gptr(d.pf_dg)[ip] = dg;
       acc[p] += b * b;
       acc[N + p] += r * r;
       const double sc = fabs(b) + aKq;
@@ -1344,12 +1343,12 @@ __device__ __forceinline__ int64_t lnbr(const Grid& g, int nx, int ny, int x, in
 
 // (K v)_i of a level from its face weights
 template <int D>
-__device__ __forceinline__ double lapply(const Grid& g, const MgLevel& L, int p, const gdouble* v,
-                                         int64_t i, int x, int y) {
-  const gdouble* wx = gptr(L.wx) + (int64_t)p * L.nc;
-  const gdouble* wy = gptr(L.wy) + (int64_t)p * L.nc;
-  const double vi = v[i];
-  double r = 0.0;
+__device__ __forceinline__ float lapply(const Grid& g, const MgLevel& L, int p, const gfloat* v,
+                                        int64_t i, int x, int y) {
+  const gfloat* wx = gptr(L.wx) + (int64_t)p * L.nc;
+  const gfloat* wy = gptr(L.wy) + (int64_t)p * L.nc;
+  const float vi = v[i];
+  float r = 0.0f;
   int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
   if (j >= 0) r += wx[i] * (vi - v[j]);
   j = lnbr(g, L.nx, L.ny, x, y, 0, -1);
@@ -1390,10 +1389,10 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_weights0(const Desc* __restric
   for (int p = 0; p < N; ++p) {
     const gdouble* K = gptr(d.pf_k) + (int64_t)p * L.nc;
     int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
-    gptr(L.wx)[(int64_t)p * L.nc + i] = j >= 0 ? 0.5 * (K[i] + K[j]) * g.rdx * g.rdx : 0.0;
+    gptr(L.wx)[(int64_t)p * L.nc + i] = j >= 0 ? (float)(0.5 * (K[i] + K[j]) * g.rdx * g.rdx) : 0.0f;
     if constexpr (D > 1) {
       j = lnbr(g, L.nx, L.ny, x, y, 1, 1);
-      gptr(L.wy)[(int64_t)p * L.nc + i] = j >= 0 ? 0.5 * (K[i] + K[j]) * g.rdy * g.rdy : 0.0;
+      gptr(L.wy)[(int64_t)p * L.nc + i] = j >= 0 ? (float)(0.5 * (K[i] + K[j]) * g.rdy * g.rdy) : 0.0f;
     }
   }
 }
@@ -1410,9 +1409,9 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_coarsen(const Desc* __restrict
   const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
 #pragma unroll
   for (int p = 0; p < N; ++p) {
-    const gdouble* wx = gptr(F.wx) + (int64_t)p * F.nc;
-    const gdouble* wy = gptr(F.wy) + (int64_t)p * F.nc;
-    double cx = 0.0, cy = 0.0;
+    const gfloat* wx = gptr(F.wx) + (int64_t)p * F.nc;
+    const gfloat* wy = gptr(F.wy) + (int64_t)p * F.nc;
+    float cx = 0.0f, cy = 0.0f;
     if (C.nx > 1)
       for (int y = 2 * Y; y <= yt; ++y) cx += wx[(int64_t)y * F.nx + xr];
     if constexpr (D > 1) {
@@ -1435,9 +1434,9 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_diag(const Desc* __restrict__ 
   const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
 #pragma unroll
   for (int p = 0; p < N; ++p) {
-    const gdouble* wx = gptr(L.wx) + (int64_t)p * L.nc;
-    const gdouble* wy = gptr(L.wy) + (int64_t)p * L.nc;
-    double dgv = 0.0;
+    const gfloat* wx = gptr(L.wx) + (int64_t)p * L.nc;
+    const gfloat* wy = gptr(L.wy) + (int64_t)p * L.nc;
+    float dgv = 0.0f;
     int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
     if (j >= 0) dgv += wx[i];
     j = lnbr(g, L.nx, L.ny, x, y, 0, -1);
@@ -1454,23 +1453,44 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_diag(const Desc* __restrict__ 
 
 // One cell of the level passes, shared by the per-level kernels and the
 // fused coarse cycle below.
+// Power-of-two scale of phase p's level-0 right-hand side: near the rms of
+// [div J_p] over the grid (||b||^2 of the start pass, > 0 for a live phase).
+__device__ __forceinline__ int mg_scale_exp(const gdouble* s, int p, int64_t nc) {
+  return ilogb(sqrt(s[kPfsBB + p]) / sqrt((double)nc));   // no underflow to 0
+}
+
 // Damped Jacobi on level L: mode 0: t = omega f / dg (from e = 0);
-// mode 1: t = e + omega (f - K e) / dg; mode 2: e = t + omega (f - K t) / dg
+// mode 1: t = e + omega (f - K e) / dg; mode 2: e = t + omega (f - K t) / dg;
+// level 0 only: mode 3 is mode 0 after f = r 2^-k (the FP64 CG residual
+// scaled), mode 4 is mode 2 writing u = 2^k (t + omega (f - K t) / dg) to
+// the FP64 preconditioned residual instead of e (k = mg_scale_exp).
 template <int D>
-__device__ __forceinline__ void mg_smooth_cell(const Grid& g, const MgLevel& L, int p,
+__device__ __forceinline__ void mg_smooth_cell(const Desc& d, const MgLevel& L, int p,
                                                int64_t i, int mode) {
+  const Grid& g = d.g;
   const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
   const int64_t ip = (int64_t)p * L.nc + i;
-  const double dgv = gptr(L.dg)[ip];
-  const double fv = gptr(L.f)[ip];
-  if (mode == 0) {
-    gptr(L.t)[ip] = dgv > 0.0 ? mg_omega<D>() * fv / dgv : 0.0;
+  const float dgv = gptr(L.dg)[ip];
+  const float w = (float)mg_omega<D>();
+  if (mode == 0 || mode == 3) {
+    float fv;
+    if (mode == 3) {
+      fv = (float)ldexp(gptr(d.pf_r)[ip], -mg_scale_exp(gptr(d.pfs), p, L.nc));
+      gptr(L.f)[ip] = fv;
+    } else {
+      fv = gptr(L.f)[ip];
+    }
+    gptr(L.t)[ip] = dgv > 0.0f ? w * fv / dgv : 0.0f;
     return;
   }
-  const gdouble* src = gptr(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
-  gdouble* dst = gptr(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc;
-  const double kv = lapply<D>(g, L, p, src, i, x, y);
-  dst[i] = dgv > 0.0 ? src[i] + mg_omega<D>() * (fv - kv) / dgv : src[i];
+  const float fv = gptr(L.f)[ip];
+  const gfloat* src = gptr(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
+  const float kv = lapply<D>(g, L, p, src, i, x, y);
+  const float v = dgv > 0.0f ? src[i] + w * (fv - kv) / dgv : src[i];
+  if (mode == 4)
+    gptr(d.pf_u)[ip] = ldexp((double)v, mg_scale_exp(gptr(d.pfs), p, L.nc));
+  else
+    (gptr(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc)[i] = v;
 }
 
 // f(C) at coarse cell i = sum over its aggregate of (f - K e) on F
@@ -1479,9 +1499,9 @@ __device__ __forceinline__ void mg_restrict_cell(const Grid& g, const MgLevel& F
                                                  const MgLevel& C, int p, int64_t i) {
   const int Y = (int)(i / C.nx), X = (int)(i - (int64_t)Y * C.nx);
   const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
-  const gdouble* e = gptr(F.e) + (int64_t)p * F.nc;
-  const gdouble* f = gptr(F.f) + (int64_t)p * F.nc;
-  double r = 0.0;
+  const gfloat* e = gptr(F.e) + (int64_t)p * F.nc;
+  const gfloat* f = gptr(F.f) + (int64_t)p * F.nc;
+  float r = 0.0f;
   for (int y = 2 * Y; y <= yt; ++y)
     for (int x = 2 * X; x <= xr; ++x) {
       const int64_t j = (int64_t)y * F.nx + x;
@@ -1492,7 +1512,7 @@ __device__ __forceinline__ void mg_restrict_cell(const Grid& g, const MgLevel& F
 
 // e(F) at fine cell i += corr e(C) of its aggregate
 __device__ __forceinline__ void mg_prolong_cell(const MgLevel& F, const MgLevel& C, int p,
-                                                int64_t i, double corr) {
+                                                int64_t i, float corr) {
   const int y = (int)(i / F.nx), x = (int)(i - (int64_t)y * F.nx);
   const int64_t I = (int64_t)(y >> 1) * C.nx + (x >> 1);
   gptr(F.e)[(int64_t)p * F.nc + i] += corr * gptr(C.e)[(int64_t)p * C.nc + I];
@@ -1507,7 +1527,7 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_smooth(const Desc* __restrict_
   if (i >= L.nc) return;
 #pragma unroll
   for (int p = 0; p < N; ++p)
-    if (live[p]) mg_smooth_cell<D>(g, L, p, i, mode);
+    if (live[p]) mg_smooth_cell<D>(d, L, p, i, mode);
 }
 
 // f(l + 1) from level l (items over l + 1)
@@ -1531,7 +1551,7 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_prolong(const Desc* __restrict
   MG_PROLOGUE
   const MgLevel F = d.mg[l], C = d.mg[l + 1];
   if (i >= F.nc) return;
-  const double corr = s[kPfsCorr];
+  const float corr = (float)s[kPfsCorr];
 #pragma unroll
   for (int p = 0; p < N; ++p)
     if (live[p]) mg_prolong_cell(F, C, p, i, corr);
@@ -1559,19 +1579,22 @@ __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restric
     any = any || live[p];
   }
   if (!any) return;                       // uniform over the workgroup
-  const double corr = s[kPfsCorr];
-  auto smooth = [&](int l, int mode) {
+  const float corr = (float)s[kPfsCorr];
+  // on level 0 (a grid of at most kMgFuseCells cells) the first pass reads
+  // the CG residual and the last one writes the preconditioned residual
+  auto smooth = [&](int l, int mode, bool last) {
     const MgLevel L = d.mg[l];
+    const int m = l > 0 ? mode : (mode == 0 ? 3 : (last ? 4 : mode));
     for (int64_t i = threadIdx.x; i < L.nc; i += kMgFuseBlock)
 #pragma unroll
       for (int p = 0; p < N; ++p)
-        if (live[p]) mg_smooth_cell<D>(g, L, p, i, mode);
+        if (live[p]) mg_smooth_cell<D>(d, L, p, i, m);
     __syncthreads();
   };
   const int lc = nlev - 1;
   for (int l = lf; l < lc; ++l) {
-    smooth(l, 0);
-    smooth(l, 2);
+    smooth(l, 0, false);
+    smooth(l, 2, false);
     const MgLevel F = d.mg[l], C = d.mg[l + 1];
     for (int64_t i = threadIdx.x; i < C.nc; i += kMgFuseBlock)
 #pragma unroll
@@ -1579,11 +1602,11 @@ __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restric
         if (live[p]) mg_restrict_cell<D>(g, F, C, p, i);
     __syncthreads();
   }
-  smooth(lc, 0);
-  smooth(lc, 2);
+  smooth(lc, 0, false);
+  smooth(lc, 2, kMgCoarseSweeps <= 2);
   for (int k = 2; k < kMgCoarseSweeps; k += 2) {
-    smooth(lc, 1);
-    smooth(lc, 2);
+    smooth(lc, 1, false);
+    smooth(lc, 2, k + 2 >= kMgCoarseSweeps);
   }
   for (int l = lc - 1; l >= lf; --l) {
     const MgLevel F = d.mg[l], C = d.mg[l + 1];
@@ -1592,8 +1615,8 @@ __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restric
       for (int p = 0; p < N; ++p)
         if (live[p]) mg_prolong_cell(F, C, p, i, corr);
     __syncthreads();
-    smooth(l, 1);
-    smooth(l, 2);
+    smooth(l, 1, false);
+    smooth(l, 2, true);
   }
 }
 
@@ -1651,7 +1674,7 @@ struct Inst {
   double* pfs = nullptr;           // Phase-Field scalars (kPfsLen)
   std::vector<MgLevel> lv;         // multigrid levels (host copy)
   MgLevel* d_mg = nullptr;         // the same on the device
-  double* mgbuf = nullptr;         // arrays of the levels
+  float* mgbuf = nullptr;          // arrays of the levels
 };
 
 // Instances of one (N, d): device descriptor table and tile offsets.
@@ -1948,6 +1971,7 @@ static void enqueue_mg_setup(mp_weno_ctx* c, hipStream_t st) {
   for (const Group& G : c->groups) {
     MgFn f = T.mg[G.N][G.D];
     f(G, 0, 0, 0, st);                               // level-0 weights
+    f(G, 2, 0, 0, st);                               // and diagonal
     for (int l = 0; l + 1 < G.nlev; ++l) {
       f(G, 1, l, 0, st);                             // weights of l + 1
       f(G, 2, l + 1, 0, st);                         // diagonal of l + 1
@@ -1964,7 +1988,7 @@ static void enqueue_vcycle(mp_weno_ctx* c, hipStream_t st) {
     MgFn f = T.mg[G.N][G.D];
     const int Lf = G.mg_fuse;                        // fused from here down
     for (int l = 0; l < Lf; ++l) {
-      f(G, 3, l, 0, st);                             // t = omega f / dg
+      f(G, 3, l, l == 0 ? 3 : 0, st);                // t = omega f / dg (level 0: f from r)
       f(G, 3, l, 2, st);                             // e = t + omega (f - K t) / dg
       f(G, 4, l, 0, st);                             // f(l + 1) = R (f - K e)
     }
@@ -1972,7 +1996,7 @@ static void enqueue_vcycle(mp_weno_ctx* c, hipStream_t st) {
     for (int l = Lf - 1; l >= 0; --l) {
       f(G, 5, l, 0, st);                             // e += P e(l + 1)
       f(G, 3, l, 1, st);                             // t = e + omega (f - K e) / dg
-      f(G, 3, l, 2, st);                             // e = t + omega (f - K t) / dg
+      f(G, 3, l, l == 0 ? 4 : 2, st);                // e = t + omega (f - K t) / dg (level 0: u)
     }
   }
 }
@@ -2301,19 +2325,18 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           std::vector<std::pair<int, int>> dims;
           for (int l = 0; l < G.nlev; ++l) {
             dims.emplace_back(nx, ny);
-            tot += (size_t)nx * ny * (l == 0 ? 3 : 6);
+            tot += (size_t)nx * ny * 6;
             nx = (nx + 1) / 2;
             ny = (ny + 1) / 2;
           }
           tot *= (size_t)I.N;
-          if (hipMalloc(&I.mgbuf, sizeof(double) * tot) != hipSuccess ||
-              hipMemset(I.mgbuf, 0, sizeof(double) * tot) != hipSuccess ||
+          if (hipMalloc(&I.mgbuf, sizeof(float) * tot) != hipSuccess ||
+              hipMemset(I.mgbuf, 0, sizeof(float) * tot) != hipSuccess ||
               hipMalloc(&I.d_mg, sizeof(MgLevel) * G.nlev) != hipSuccess) {
             mp_weno_destroy(c);
             return MP_ERR_OOM;
           }
-          double* q = I.mgbuf;
-          const size_t f0 = (size_t)I.N * (size_t)I.nc;
+          float* q = I.mgbuf;
           for (int l = 0; l < G.nlev; ++l) {
             MgLevel L;
             L.nx = dims[l].first;
@@ -2323,15 +2346,9 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
             L.wx = q; q += f;
             L.wy = q; q += f;
             L.t = q; q += f;
-            if (l == 0) {
-              L.e = I.pf + 8 * f0;          // u
-              L.f = I.pf + 3 * f0;          // the CG residual
-              L.dg = I.pf + 7 * f0;         // diagonal of K
-            } else {
-              L.e = q; q += f;
-              L.f = q; q += f;
-              L.dg = q; q += f;
-            }
+            L.e = q; q += f;
+            L.f = q; q += f;
+            L.dg = q; q += f;
             I.lv.push_back(L);
           }
           if (hipMemcpy(I.d_mg, I.lv.data(), sizeof(MgLevel) * G.nlev,
@@ -2397,9 +2414,8 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           d.pf_p = I.pf + 4 * f;
           d.pf_ap = I.pf + 5 * f;
           d.pf_w = I.pf + 6 * f;
-          d.pf_dg = I.pf + 7 * f;
-          d.pf_u = I.pf + 8 * f;
-          d.pf_g = I.pf + 9 * f;
+          d.pf_u = I.pf + 7 * f;
+          d.pf_g = I.pf + kPfFields * f;   // after the kPfFields arrays above
           d.mg = I.d_mg;
           d.nlev = (int)I.lv.size();
           double h = s.dx[0];
@@ -2609,7 +2625,7 @@ mp_status mp_weno_pf_fields(mp_weno_ctx* c, const double* const* U_in, double* c
         HIPCHK(c, hipMemcpyAsync(divj[i], I.pf + f, sizeof(double) * f,
                                  hipMemcpyDeviceToDevice, c->stream));
       if (grad && grad[i])
-        HIPCHK(c, hipMemcpyAsync(grad[i], I.pf + 9 * f, sizeof(double) * I.D * f,
+        HIPCHK(c, hipMemcpyAsync(grad[i], I.pf + kPfFields * f, sizeof(double) * I.D * f,
                                  hipMemcpyDeviceToDevice, c->stream));
     }
     if (dUdt) st = enqueue_stage(c, 3, 1);
