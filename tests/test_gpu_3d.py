@@ -10,8 +10,9 @@ bubble interaction"): 3D, N = 3, symmetry planes at y = 0 and z = 0.
   bound (1e-4 raw);
 * a window of CFL steps against the oracle (1e-12 on states);
 * a batch of 3D and 2D instances reproduces solo runs bitwise;
-* the benchmark size (400 x 200 x 200) stays finite, sum alpha = 1 and in
-  bounds over a few steps.
+* the benchmark size (400 x 200 x 200): L(U) against the oracle at every
+  cell with the autotuned tiles, and finite, sum alpha = 1 and in bounds
+  over a few steps.
 """
 import numpy as np
 import pytest
@@ -135,6 +136,12 @@ def test_3d_batched_bitwise_vs_solo(precision):
         assert np.array_equal(b.host(i), s.host(0)), i
         s.close()
     b.close()
+
+
+def test_3d_full_size_rhs_vs_oracle(oracle):
+    """L(U) of the full 400 x 200 x 200 shock-vessel-bubble grid, every cell,
+    with the autotuned tiles of the benchmark."""
+    _check_rhs(oracle, I.shock_vessel_bubble_3d(400, 200, 200), tune=True)
 
 
 def test_3d_full_size_invariants():

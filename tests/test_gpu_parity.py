@@ -64,8 +64,10 @@ def _rel_err(a, b, nU, scale=None):
     return d / np.where(sc > 0, sc, 1.0)
 
 
-def _check_rhs(oracle, w, tol=TOL):
+def _check_rhs(oracle, w, tol=TOL, tune=False):
     s = _solver(w)
+    if tune:                       # the tile shapes the benchmark runs with
+        s.autotune()
     Lg = s.rhs()[0].cpu().numpy().reshape(-1)
     s.close()
     pb = oracle_problem(oracle, w)
