@@ -1341,12 +1341,19 @@ __device__ __forceinline__ int64_t lnbr(const Grid& g, int nx, int ny, int x, in
   return (int64_t)yn * nx + x;
 }
 
+// A level's arrays are read and written in global memory (AS = 1) by the
+// per-level kernels, or in the LDS copy of the fused coarse cycle (AS = 3).
+template <int AS>
+using lfloat = __attribute__((address_space(AS))) float;
+template <int AS>
+__device__ __forceinline__ lfloat<AS>* lp(float* p) { return (lfloat<AS>*)p; }
+
 // (K v)_i of a level from its face weights
-template <int D>
-__device__ __forceinline__ float lapply(const Grid& g, const MgLevel& L, int p, const gfloat* v,
-                                        int64_t i, int x, int y) {
-  const gfloat* wx = gptr(L.wx) + (int64_t)p * L.nc;
-  const gfloat* wy = gptr(L.wy) + (int64_t)p * L.nc;
+template <int D, int AS>
+__device__ __forceinline__ float lapply(const Grid& g, const MgLevel& L, int p, const lfloat<AS>* v,
+                                        int i, int x, int y) {
+  const lfloat<AS>* wx = lp<AS>(L.wx) + (int64_t)p * L.nc;
+  const lfloat<AS>* wy = lp<AS>(L.wy) + (int64_t)p * L.nc;
   const float vi = v[i];
   float r = 0.0f;
   int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
@@ -1464,58 +1471,59 @@ __device__ __forceinline__ int mg_scale_exp(const gdouble* s, int p, int64_t nc)
 // level 0 only: mode 3 is mode 0 after f = r 2^-k (the FP64 CG residual
 // scaled), mode 4 is mode 2 writing u = 2^k (t + omega (f - K t) / dg) to
 // the FP64 preconditioned residual instead of e (k = mg_scale_exp).
-template <int D>
+template <int D, int AS>
 __device__ __forceinline__ void mg_smooth_cell(const Desc& d, const MgLevel& L, int p,
-                                               int64_t i, int mode) {
+                                               int i, int mode) {
   const Grid& g = d.g;
-  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
+  const int y = i / L.nx, x = i - y * L.nx;          // levels hold < 2^31 cells
   const int64_t ip = (int64_t)p * L.nc + i;
-  const float dgv = gptr(L.dg)[ip];
+  const float dgv = lp<AS>(L.dg)[ip];
   const float w = (float)mg_omega<D>();
   if (mode == 0 || mode == 3) {
     float fv;
     if (mode == 3) {
       fv = (float)ldexp(gptr(d.pf_r)[ip], -mg_scale_exp(gptr(d.pfs), p, L.nc));
-      gptr(L.f)[ip] = fv;
+      lp<AS>(L.f)[ip] = fv;
     } else {
-      fv = gptr(L.f)[ip];
+      fv = lp<AS>(L.f)[ip];
     }
-    gptr(L.t)[ip] = dgv > 0.0f ? w * fv / dgv : 0.0f;
+    lp<AS>(L.t)[ip] = dgv > 0.0f ? w * fv / dgv : 0.0f;
     return;
   }
-  const float fv = gptr(L.f)[ip];
-  const gfloat* src = gptr(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
-  const float kv = lapply<D>(g, L, p, src, i, x, y);
+  const float fv = lp<AS>(L.f)[ip];
+  const lfloat<AS>* src = lp<AS>(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
+  const float kv = lapply<D, AS>(g, L, p, src, i, x, y);
   const float v = dgv > 0.0f ? src[i] + w * (fv - kv) / dgv : src[i];
   if (mode == 4)
     gptr(d.pf_u)[ip] = ldexp((double)v, mg_scale_exp(gptr(d.pfs), p, L.nc));
   else
-    (gptr(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc)[i] = v;
+    (lp<AS>(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc)[i] = v;
 }
 
 // f(C) at coarse cell i = sum over its aggregate of (f - K e) on F
-template <int D>
+template <int D, int AS>
 __device__ __forceinline__ void mg_restrict_cell(const Grid& g, const MgLevel& F,
-                                                 const MgLevel& C, int p, int64_t i) {
-  const int Y = (int)(i / C.nx), X = (int)(i - (int64_t)Y * C.nx);
+                                                 const MgLevel& C, int p, int i) {
+  const int Y = i / C.nx, X = i - Y * C.nx;
   const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
-  const gfloat* e = gptr(F.e) + (int64_t)p * F.nc;
-  const gfloat* f = gptr(F.f) + (int64_t)p * F.nc;
+  const lfloat<AS>* e = lp<AS>(F.e) + (int64_t)p * F.nc;
+  const lfloat<AS>* f = lp<AS>(F.f) + (int64_t)p * F.nc;
   float r = 0.0f;
   for (int y = 2 * Y; y <= yt; ++y)
     for (int x = 2 * X; x <= xr; ++x) {
-      const int64_t j = (int64_t)y * F.nx + x;
-      r += f[j] - lapply<D>(g, F, p, e, j, x, y);
+      const int j = y * F.nx + x;
+      r += f[j] - lapply<D, AS>(g, F, p, e, j, x, y);
     }
-  gptr(C.f)[(int64_t)p * C.nc + i] = r;
+  lp<AS>(C.f)[(int64_t)p * C.nc + i] = r;
 }
 
 // e(F) at fine cell i += corr e(C) of its aggregate
+template <int AS>
 __device__ __forceinline__ void mg_prolong_cell(const MgLevel& F, const MgLevel& C, int p,
-                                                int64_t i, float corr) {
-  const int y = (int)(i / F.nx), x = (int)(i - (int64_t)y * F.nx);
-  const int64_t I = (int64_t)(y >> 1) * C.nx + (x >> 1);
-  gptr(F.e)[(int64_t)p * F.nc + i] += corr * gptr(C.e)[(int64_t)p * C.nc + I];
+                                                int i, float corr) {
+  const int y = i / F.nx, x = i - y * F.nx;
+  const int I = (y >> 1) * C.nx + (x >> 1);
+  lp<AS>(F.e)[(int64_t)p * F.nc + i] += corr * lp<AS>(C.e)[(int64_t)p * C.nc + I];
 }
 
 template <int N, int D>
@@ -1527,7 +1535,7 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_smooth(const Desc* __restrict_
   if (i >= L.nc) return;
 #pragma unroll
   for (int p = 0; p < N; ++p)
-    if (live[p]) mg_smooth_cell<D>(d, L, p, i, mode);
+    if (live[p]) mg_smooth_cell<D, 1>(d, L, p, (int)i, mode);
 }
 
 // f(l + 1) from level l (items over l + 1)
@@ -1540,7 +1548,7 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_restrict(const Desc* __restric
   if (i >= C.nc) return;
 #pragma unroll
   for (int p = 0; p < N; ++p)
-    if (live[p]) mg_restrict_cell<D>(g, F, C, p, i);
+    if (live[p]) mg_restrict_cell<D, 1>(g, F, C, p, (int)i);
 }
 
 // e(l) += corr e(l + 1) (items over level l)
@@ -1554,20 +1562,42 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_prolong(const Desc* __restrict
   const float corr = (float)s[kPfsCorr];
 #pragma unroll
   for (int p = 0; p < N; ++p)
-    if (live[p]) mg_prolong_cell(F, C, p, i, corr);
+    if (live[p]) mg_prolong_cell<1>(F, C, p, (int)i, corr);
 }
 #undef MG_PROLOGUE
 
-// The V-cycle below level lf (the levels of at most kMgFuseCells cells) in
-// one workgroup per instance: the same passes as the per-level kernels, in
-// the same order, separated by workgroup barriers instead of launches (the
-// coarse levels are otherwise launch-bound).  Input f(lf), output e(lf).
-constexpr int kMgFuseCells = 4096;
+// The V-cycle below level lf in one workgroup per instance.  Levels lf ..
+// nlev - 1 are copied into LDS (face weights and diagonals, and f(lf)); every
+// pass of the per-level kernels runs there, in the same order, separated by
+// workgroup barriers instead of launches (the coarse levels are otherwise
+// launch- and latency-bound); e(lf) goes back to global memory for the
+// prolongation to level lf - 1.  With lf = 0 the first pass reads the CG
+// residual and the last one writes the preconditioned residual.  The host
+// picks lf so that these levels fit the dynamic LDS of the launch (6 N floats
+// per cell of each level).
 constexpr int kMgFuseBlock = 1024;
+constexpr int kMgFusedStatic = 4096;     // bytes kept for its static LDS
+
+// level l's arrays in the LDS image, which holds levels lf .. l - 1 before it
+__device__ __forceinline__ MgLevel mg_lds_level(const Desc& d, float* lds, int N, int lf, int l) {
+  int64_t off = 0;
+  for (int k = lf; k < l; ++k) off += 6 * (int64_t)N * d.mg[k].nc;
+  MgLevel L = d.mg[l];
+  const int64_t f = (int64_t)N * L.nc;
+  float* b = lds + off;
+  L.wx = b;
+  L.wy = b + f;
+  L.dg = b + 2 * f;
+  L.e = b + 3 * f;
+  L.t = b + 4 * f;
+  L.f = b + 5 * f;
+  return L;
+}
 
 template <int N, int D>
 __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restrict__ descs,
                                                            int lf, int nlev) {
+  extern __shared__ float mg_lds[];
   const Desc& d = descs[blockIdx.x];
   const Grid& g = d.g;
   const gdouble* s = gptr(d.pfs);
@@ -1580,26 +1610,42 @@ __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restric
   }
   if (!any) return;                       // uniform over the workgroup
   const float corr = (float)s[kPfsCorr];
-  // on level 0 (a grid of at most kMgFuseCells cells) the first pass reads
-  // the CG residual and the last one writes the preconditioned residual
+  // the levels' LDS descriptors, built once (the level table is global memory,
+  // which every barrier below would make the passes read again)
+  __shared__ MgLevel lv[kMgMaxLev];
+  static_assert(sizeof(lv) <= kMgFusedStatic, "static LDS of the fused cycle");
+  if (threadIdx.x >= lf && threadIdx.x < nlev)
+    lv[threadIdx.x] = mg_lds_level(d, mg_lds, N, lf, threadIdx.x);
+  for (int l = lf; l < nlev; ++l) {
+    const MgLevel G = d.mg[l];
+    const MgLevel L = mg_lds_level(d, mg_lds, N, lf, l);
+    const int f = N * (int)G.nc;
+    for (int i = threadIdx.x; i < f; i += kMgFuseBlock) {
+      lp<3>(L.wx)[i] = gptr(G.wx)[i];
+      lp<3>(L.wy)[i] = gptr(G.wy)[i];
+      lp<3>(L.dg)[i] = gptr(G.dg)[i];
+      if (l == lf && lf > 0) lp<3>(L.f)[i] = gptr(G.f)[i];
+    }
+  }
+  __syncthreads();
   auto smooth = [&](int l, int mode, bool last) {
-    const MgLevel L = d.mg[l];
+    const MgLevel L = lv[l];
     const int m = l > 0 ? mode : (mode == 0 ? 3 : (last ? 4 : mode));
-    for (int64_t i = threadIdx.x; i < L.nc; i += kMgFuseBlock)
+    for (int i = threadIdx.x; i < (int)L.nc; i += kMgFuseBlock)
 #pragma unroll
       for (int p = 0; p < N; ++p)
-        if (live[p]) mg_smooth_cell<D>(d, L, p, i, m);
+        if (live[p]) mg_smooth_cell<D, 3>(d, L, p, i, m);
     __syncthreads();
   };
   const int lc = nlev - 1;
   for (int l = lf; l < lc; ++l) {
     smooth(l, 0, false);
     smooth(l, 2, false);
-    const MgLevel F = d.mg[l], C = d.mg[l + 1];
-    for (int64_t i = threadIdx.x; i < C.nc; i += kMgFuseBlock)
+    const MgLevel F = lv[l], C = lv[l + 1];
+    for (int i = threadIdx.x; i < (int)C.nc; i += kMgFuseBlock)
 #pragma unroll
       for (int p = 0; p < N; ++p)
-        if (live[p]) mg_restrict_cell<D>(g, F, C, p, i);
+        if (live[p]) mg_restrict_cell<D, 3>(g, F, C, p, i);
     __syncthreads();
   }
   smooth(lc, 0, false);
@@ -1609,15 +1655,31 @@ __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restric
     smooth(lc, 2, k + 2 >= kMgCoarseSweeps);
   }
   for (int l = lc - 1; l >= lf; --l) {
-    const MgLevel F = d.mg[l], C = d.mg[l + 1];
-    for (int64_t i = threadIdx.x; i < F.nc; i += kMgFuseBlock)
+    const MgLevel F = lv[l], C = lv[l + 1];
+    for (int i = threadIdx.x; i < (int)F.nc; i += kMgFuseBlock)
 #pragma unroll
       for (int p = 0; p < N; ++p)
-        if (live[p]) mg_prolong_cell(F, C, p, i, corr);
+        if (live[p]) mg_prolong_cell<3>(F, C, p, i, corr);
     __syncthreads();
     smooth(l, 1, false);
     smooth(l, 2, true);
   }
+  if (lf > 0) {
+    const MgLevel G = d.mg[lf], L = lv[lf];
+    const int nc = (int)G.nc;
+#pragma unroll
+    for (int p = 0; p < N; ++p)
+      if (live[p])
+        for (int i = threadIdx.x; i < nc; i += kMgFuseBlock)
+          gptr(G.e)[p * nc + i] = lp<3>(L.e)[p * nc + i];
+  }
+}
+
+// allow the fused cycle's launches up to `bytes` of dynamic LDS
+template <int N, int D>
+hipError_t mg_fused_lds(int bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_fused<N, D>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // frozen face gradients dQ_p/dx_d at the upper face of every cell: none at an
@@ -1694,6 +1756,7 @@ struct Group {
   size_t part_off = 0;             // this group's reduction partials
   int nlev = 0;                    // multigrid levels (every instance has them all)
   int mg_fuse = 0;                 // first level run by the fused coarse cycle
+  size_t mg_lds = 0;               // its dynamic LDS bytes
   int2* lmap[kMgMaxLev] = {};      // work item -> (instance, 256-cell chunk) per level
   int lcount[kMgMaxLev] = {};
 };
@@ -1758,7 +1821,7 @@ void launch_mg(const Group& G, int kind, int l, int mode, hipStream_t s) {
     case 3: hipLaunchKernelGGL((k_mg_smooth<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l, mode); break;
     case 4: hipLaunchKernelGGL((k_mg_restrict<N, D>), dim3(G.lcount[l + 1]), blk, 0, s, G.desc, G.lmap[l + 1], n, l); break;
     case 5: hipLaunchKernelGGL((k_mg_prolong<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l); break;
-    case 6: hipLaunchKernelGGL((k_mg_fused<N, D>), dim3(n), dim3(kMgFuseBlock), 0, s, G.desc, l, G.nlev); break;
+    case 6: hipLaunchKernelGGL((k_mg_fused<N, D>), dim3(n), dim3(kMgFuseBlock), G.mg_lds, s, G.desc, l, G.nlev); break;
   }
 }
 
@@ -1799,6 +1862,7 @@ struct Table {
   PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
   PfFn pfi[4][kMaxN + 1] = {};             // per-instance PF finishers
   MgFn mg[kMaxN + 1][3] = {};
+  hipError_t (*mg_lds[kMaxN + 1][3])(int) = {};
 };
 
 template <int N, int D>
@@ -1810,6 +1874,7 @@ void fill_pf(Table& t) {
   t.pfc[4][N][D] = launch_pf_cells<N, D, 4>;
   t.pfc[5][N][D] = launch_pf_cells<N, D, 5>;
   t.mg[N][D] = launch_mg<N, D>;
+  t.mg_lds[N][D] = mg_fused_lds<N, D>;
 }
 
 template <int N, int V>
@@ -1980,8 +2045,8 @@ static void enqueue_mg_setup(mp_weno_ctx* c, hipStream_t st) {
 }
 
 // u = M^-1 r: one V-cycle per group (two Jacobi sweeps before and after the
-// coarse correction, kMgCoarseSweeps on the coarsest level); the levels of at
-// most kMgFuseCells cells run in one launch (k_mg_fused)
+// coarse correction, kMgCoarseSweeps on the coarsest level); the coarsest
+// levels that fit in LDS run in one launch (k_mg_fused)
 static void enqueue_vcycle(mp_weno_ctx* c, hipStream_t st) {
   const Table& T = table();
   for (const Group& G : c->groups) {
@@ -2461,17 +2526,34 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         }
         G.lcount[l] = (int)lm[l].size();
       }
-      // the fused cycle takes every level with at most kMgFuseCells cells in
-      // each instance of the group
+      // the fused cycle takes the coarsest levels whose LDS image (6 N floats
+      // per cell) fits the workgroup's LDS in every instance of the group:
+      // the device's limit when the kernel accepts it, else 64 KiB
       if (G.nlev > 0) {
-        G.mg_fuse = G.nlev - 1;
-        while (G.mg_fuse > 0) {
-          bool small = true;
-          for (size_t k = 0; k < m; ++k)
-            small = small && c->inst[G.ids[k]].lv[G.mg_fuse - 1].nc <= kMgFuseCells;
-          if (!small) break;
-          --G.mg_fuse;
+        // (less kMgFusedStatic for the kernel's own LDS)
+        size_t lds_budget = 65536 - kMgFusedStatic;
+        int dev = 0, lmax = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lmax > 65536) {
+          if (table().mg_lds[G.N][G.D](lmax - kMgFusedStatic) == hipSuccess)
+            lds_budget = (size_t)(lmax - kMgFusedStatic);
+          else
+            (void)hipGetLastError();     // keep 64 KiB; clear the error
         }
+        auto lds_from = [&](int l) {
+          size_t mx = 0;
+          for (size_t k = 0; k < m; ++k) {
+            size_t b = 0;
+            for (int j = l; j < G.nlev; ++j)
+              b += 6 * sizeof(float) * (size_t)G.N * (size_t)c->inst[G.ids[k]].lv[j].nc;
+            mx = std::max(mx, b);
+          }
+          return mx;
+        };
+        G.mg_fuse = G.nlev - 1;
+        while (G.mg_fuse > 0 && lds_from(G.mg_fuse - 1) <= lds_budget) --G.mg_fuse;
+        G.mg_lds = lds_from(G.mg_fuse);
       }
       auto tile_map = [m](const std::vector<int>& st) {
         std::vector<int2> v((size_t)st[m]);
