@@ -800,6 +800,35 @@ __device__ __forceinline__ double block_reduce(double v, double* sh, int op) {
   return r;
 }
 
+// sums of slots 0 .. K - 1 of an instance's chunk partials at once, fixed
+// order: each thread adds its chunks, each wave reduces with lane exchanges,
+// thread 0 adds the waves in order; the result is valid in thread 0
+template <int K>
+__device__ __forceinline__ void reduce_chunks_n(const double* __restrict__ part, int64_t ps,
+                                                int b0, int b1, double* v, double* sh) {
+  static_assert(K * (kRedBlock / 64) <= kRedBlock, "LDS of the reduction");
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += kRedBlock)
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += part[(int64_t)k * ps + b];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * (kRedBlock / 64) + w] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double t = sh[k * (kRedBlock / 64)];
+      for (int j = 1; j < kRedBlock / 64; ++j) t += sh[k * (kRedBlock / 64) + j];
+      v[k] = t;
+    }
+}
+
 // sum (or max) of slot k of an instance's chunk partials, fixed order
 __device__ __forceinline__ double reduce_chunks(const double* __restrict__ part, int64_t ps,
                                                 int b0, int b1, int k, double* sh, int op) {
@@ -1174,20 +1203,19 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_alpha(const Desc* __restric
   __shared__ double sh[kRedBlock];
   const Desc& d = descs[blockIdx.x];
   gdouble* s = gptr(d.pfs);
-  for (int p = 0; p < N; ++p) {
-    if (s[kPfsDone + p] != 0.0) continue;    // uniform over the workgroup
-    const double pq = reduce_chunks(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], p, sh, 0);
-    if (threadIdx.x == 0) {
+  double pq[N];
+  reduce_chunks_n<N>(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], pq, sh);
+  if (threadIdx.x == 0)
+    for (int p = 0; p < N; ++p) {
+      if (s[kPfsDone + p] != 0.0) continue;
       const double rz = s[kPfsRZ + p];
-      if (!(pq > 0.0) || !(rz > 0.0)) {
+      if (!(pq[p] > 0.0) || !(rz > 0.0)) {
         s[kPfsDone + p] = 1.0;
         s[kPfsCorr] = 1.0;
       } else {
-        s[kPfsAlpha + p] = rz / pq;
+        s[kPfsAlpha + p] = rz / pq[p];
       }
     }
-    __syncthreads();
-  }
 }
 
 template <int N, int D>
@@ -1271,19 +1299,18 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict
   __shared__ double sh[kRedBlock];
   const Desc& d = descs[blockIdx.x];
   gdouble* s = gptr(d.pfs);
+  double v[4 * N];
+  reduce_chunks_n<4 * N>(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], v, sh);
+  if (threadIdx.x != 0) return;
   double rmax = 0.0;
   bool stepped = false, adv = false;
   for (int p = 0; p < N; ++p) {
-    if (s[kPfsDone + p] != 0.0) continue;    // uniform over the workgroup
-    const int b0 = start[blockIdx.x], b1 = start[blockIdx.x + 1];
-    const double rz0 = reduce_chunks(part, d.ps, b0, b1, p, sh, 0);
-    const double rr = reduce_chunks(part, d.ps, b0, b1, N + p, sh, 0);
-    const double zs = reduce_chunks(part, d.ps, b0, b1, 2 * N + p, sh, 0);
-    const double rs = reduce_chunks(part, d.ps, b0, b1, 3 * N + p, sh, 0);
+    if (s[kPfsDone + p] != 0.0) continue;
+    const double rz0 = v[p], rr = v[N + p], zs = v[2 * N + p], rs = v[3 * N + p];
     const double zb = zs / (double)d.g.nc;
     const double rz = rz0 - zb * rs;
     stepped = true;
-    if (threadIdx.x == 0) {
+    {
       const double bb = s[kPfsBB + p];
       const double k = s[kPfsPits + p];
       rmax = fmax(rmax, sqrt(rr / bb));
@@ -1300,10 +1327,9 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict
         adv = true;
       }
     }
-    __syncthreads();
   }
   // iterations of the solve, over its restarts
-  if (threadIdx.x == 0 && stepped) {
+  if (stepped) {
     if (adv) s[kPfsIts] = s[kPfsIts] + 1.0;
     s[kPfsRes] = rmax;
   }
@@ -1348,25 +1374,52 @@ using lfloat = __attribute__((address_space(AS))) float;
 template <int AS>
 __device__ __forceinline__ lfloat<AS>* lp(float* p) { return (lfloat<AS>*)p; }
 
-// (K v)_i of a level from its face weights
+// lnbr that also gives the neighbour's coordinates
+__device__ __forceinline__ int lnbr_xy(const Grid& g, int nx, int ny, int x, int y, int dir,
+                                       int s, int& xn, int& yn) {
+  xn = x;
+  yn = y;
+  if (dir == 0) {
+    if (nx == 1) return -1;
+    xn = x + s;
+    if (xn < 0) { if (g.bcx0 != MP_BC_PERIODIC) return -1; xn += nx; }
+    if (xn >= nx) { if (g.bcx1 != MP_BC_PERIODIC) return -1; xn -= nx; }
+  } else {
+    if (ny == 1) return -1;
+    yn = y + s;
+    if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += ny; }
+    if (yn >= ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= ny; }
+  }
+  return yn * nx + xn;
+}
+
+// (K v)_i of a level from its face weights; val(j, x_j, y_j) gives v at a
+// cell of the level
+template <int D, int AS, typename V>
+__device__ __forceinline__ float lapply_v(const Grid& g, const MgLevel& L, int p, int i, int x,
+                                          int y, V val) {
+  const lfloat<AS>* wx = lp<AS>(L.wx) + (int64_t)p * L.nc;
+  const lfloat<AS>* wy = lp<AS>(L.wy) + (int64_t)p * L.nc;
+  const float vi = val(i, x, y);
+  float r = 0.0f;
+  int xn, yn;
+  int j = lnbr_xy(g, L.nx, L.ny, x, y, 0, 1, xn, yn);
+  if (j >= 0) r += wx[i] * (vi - val(j, xn, yn));
+  j = lnbr_xy(g, L.nx, L.ny, x, y, 0, -1, xn, yn);
+  if (j >= 0) r += wx[j] * (vi - val(j, xn, yn));
+  if constexpr (D > 1) {
+    j = lnbr_xy(g, L.nx, L.ny, x, y, 1, 1, xn, yn);
+    if (j >= 0) r += wy[i] * (vi - val(j, xn, yn));
+    j = lnbr_xy(g, L.nx, L.ny, x, y, 1, -1, xn, yn);
+    if (j >= 0) r += wy[j] * (vi - val(j, xn, yn));
+  }
+  return r;
+}
+
 template <int D, int AS>
 __device__ __forceinline__ float lapply(const Grid& g, const MgLevel& L, int p, const lfloat<AS>* v,
                                         int i, int x, int y) {
-  const lfloat<AS>* wx = lp<AS>(L.wx) + (int64_t)p * L.nc;
-  const lfloat<AS>* wy = lp<AS>(L.wy) + (int64_t)p * L.nc;
-  const float vi = v[i];
-  float r = 0.0f;
-  int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
-  if (j >= 0) r += wx[i] * (vi - v[j]);
-  j = lnbr(g, L.nx, L.ny, x, y, 0, -1);
-  if (j >= 0) r += wx[j] * (vi - v[j]);
-  if constexpr (D > 1) {
-    j = lnbr(g, L.nx, L.ny, x, y, 1, 1);
-    if (j >= 0) r += wy[i] * (vi - v[j]);
-    j = lnbr(g, L.nx, L.ny, x, y, 1, -1);
-    if (j >= 0) r += wy[j] * (vi - v[j]);
-  }
-  return r;
+  return lapply_v<D, AS>(g, L, p, i, x, y, [v](int j, int, int) { return (float)v[j]; });
 }
 
 // per-level work items: (instance, chunk of 256 cells of that level)
@@ -1468,12 +1521,16 @@ __device__ __forceinline__ int mg_scale_exp(const gdouble* s, int p, int64_t nc)
 
 // Damped Jacobi on level L: mode 0: t = omega f / dg (from e = 0);
 // mode 1: t = e + omega (f - K e) / dg; mode 2: e = t + omega (f - K t) / dg;
-// level 0 only: mode 3 is mode 0 after f = r 2^-k (the FP64 CG residual
+// mode 5: mode 1 on e' = e + corr P e(C), the coarse correction of level C
+// (aggregates of 2 x 2 cells, piecewise constant) added on the fly, so the
+// prolongation needs no pass of its own (e' is not kept: the next pass reads
+// t); level 0 only: mode 3 is mode 0 after f = r 2^-k (the FP64 CG residual
 // scaled), mode 4 is mode 2 writing u = 2^k (t + omega (f - K t) / dg) to
 // the FP64 preconditioned residual instead of e (k = mg_scale_exp).
 template <int D, int AS>
 __device__ __forceinline__ void mg_smooth_cell(const Desc& d, const MgLevel& L, int p,
-                                               int i, int mode) {
+                                               int i, int mode, const MgLevel* C = nullptr,
+                                               float corr = 0.0f) {
   const Grid& g = d.g;
   const int y = i / L.nx, x = i - y * L.nx;          // levels hold < 2^31 cells
   const int64_t ip = (int64_t)p * L.nc + i;
@@ -1491,6 +1548,16 @@ __device__ __forceinline__ void mg_smooth_cell(const Desc& d, const MgLevel& L, 
     return;
   }
   const float fv = lp<AS>(L.f)[ip];
+  if (mode == 5) {
+    const lfloat<AS>* e = lp<AS>(L.e) + (int64_t)p * L.nc;
+    const lfloat<AS>* ec = lp<AS>(C->e) + (int64_t)p * C->nc;
+    const int cnx = C->nx;
+    auto ep = [=](int j, int xj, int yj) { return e[j] + corr * ec[(yj >> 1) * cnx + (xj >> 1)]; };
+    const float ei = ep(i, x, y);
+    const float kv = lapply_v<D, AS>(g, L, p, i, x, y, ep);
+    (lp<AS>(L.t) + (int64_t)p * L.nc)[i] = dgv > 0.0f ? ei + w * (fv - kv) / dgv : ei;
+    return;
+  }
   const lfloat<AS>* src = lp<AS>(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
   const float kv = lapply<D, AS>(g, L, p, src, i, x, y);
   const float v = dgv > 0.0f ? src[i] + w * (fv - kv) / dgv : src[i];
@@ -1500,10 +1567,12 @@ __device__ __forceinline__ void mg_smooth_cell(const Desc& d, const MgLevel& L, 
     (lp<AS>(mode == 1 ? L.t : L.e) + (int64_t)p * L.nc)[i] = v;
 }
 
-// f(C) at coarse cell i = sum over its aggregate of (f - K e) on F
+// f(C) at coarse cell i = sum over its aggregate of (f - K e) on F; smooth0:
+// also C's first Jacobi pass (mode 0, pointwise): t = omega f / dg
 template <int D, int AS>
 __device__ __forceinline__ void mg_restrict_cell(const Grid& g, const MgLevel& F,
-                                                 const MgLevel& C, int p, int i) {
+                                                 const MgLevel& C, int p, int i,
+                                                 bool smooth0) {
   const int Y = i / C.nx, X = i - Y * C.nx;
   const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
   const lfloat<AS>* e = lp<AS>(F.e) + (int64_t)p * F.nc;
@@ -1514,16 +1583,12 @@ __device__ __forceinline__ void mg_restrict_cell(const Grid& g, const MgLevel& F
       const int j = y * F.nx + x;
       r += f[j] - lapply<D, AS>(g, F, p, e, j, x, y);
     }
-  lp<AS>(C.f)[(int64_t)p * C.nc + i] = r;
-}
-
-// e(F) at fine cell i += corr e(C) of its aggregate
-template <int AS>
-__device__ __forceinline__ void mg_prolong_cell(const MgLevel& F, const MgLevel& C, int p,
-                                                int i, float corr) {
-  const int y = i / F.nx, x = i - y * F.nx;
-  const int I = (y >> 1) * C.nx + (x >> 1);
-  lp<AS>(F.e)[(int64_t)p * F.nc + i] += corr * lp<AS>(C.e)[(int64_t)p * C.nc + I];
+  const int64_t ci = (int64_t)p * C.nc + i;
+  lp<AS>(C.f)[ci] = r;
+  if (smooth0) {
+    const float dgc = lp<AS>(C.dg)[ci];
+    lp<AS>(C.t)[ci] = dgc > 0.0f ? (float)mg_omega<D>() * r / dgc : 0.0f;
+  }
 }
 
 template <int N, int D>
@@ -1533,36 +1598,28 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_smooth(const Desc* __restrict_
   MG_PROLOGUE
   const MgLevel L = d.mg[l];
   if (i >= L.nc) return;
+  MgLevel C;
+  float corr = 0.0f;
+  if (mode == 5) {
+    C = d.mg[l + 1];
+    corr = (float)s[kPfsCorr];
+  }
 #pragma unroll
   for (int p = 0; p < N; ++p)
-    if (live[p]) mg_smooth_cell<D, 1>(d, L, p, (int)i, mode);
+    if (live[p]) mg_smooth_cell<D, 1>(d, L, p, (int)i, mode, &C, corr);
 }
 
-// f(l + 1) from level l (items over l + 1)
+// f(l + 1) from level l (items over l + 1); smooth0: and t(l + 1)
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_mg_restrict(const Desc* __restrict__ descs,
                                                            const int2* __restrict__ map, int ninst,
-                                                           int l) {
+                                                           int l, int smooth0) {
   MG_PROLOGUE
   const MgLevel F = d.mg[l], C = d.mg[l + 1];
   if (i >= C.nc) return;
 #pragma unroll
   for (int p = 0; p < N; ++p)
-    if (live[p]) mg_restrict_cell<D, 1>(g, F, C, p, (int)i);
-}
-
-// e(l) += corr e(l + 1) (items over level l)
-template <int N, int D>
-__global__ __launch_bounds__(kRedBlock) void k_mg_prolong(const Desc* __restrict__ descs,
-                                                          const int2* __restrict__ map, int ninst,
-                                                          int l) {
-  MG_PROLOGUE
-  const MgLevel F = d.mg[l], C = d.mg[l + 1];
-  if (i >= F.nc) return;
-  const float corr = (float)s[kPfsCorr];
-#pragma unroll
-  for (int p = 0; p < N; ++p)
-    if (live[p]) mg_prolong_cell<1>(F, C, p, (int)i, corr);
+    if (live[p]) mg_restrict_cell<D, 1>(g, F, C, p, (int)i, smooth0 != 0);
 }
 #undef MG_PROLOGUE
 
@@ -1628,40 +1685,36 @@ __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restric
     }
   }
   __syncthreads();
+  // mode as in mg_smooth_cell; on level 0 mode 0 reads the residual (3) and
+  // the last pass writes the preconditioned residual (4)
   auto smooth = [&](int l, int mode, bool last) {
     const MgLevel L = lv[l];
+    const MgLevel* C = l + 1 < nlev ? &lv[l + 1] : nullptr;
     const int m = l > 0 ? mode : (mode == 0 ? 3 : (last ? 4 : mode));
     for (int i = threadIdx.x; i < (int)L.nc; i += kMgFuseBlock)
 #pragma unroll
       for (int p = 0; p < N; ++p)
-        if (live[p]) mg_smooth_cell<D, 3>(d, L, p, i, m);
+        if (live[p]) mg_smooth_cell<D, 3>(d, L, p, i, m, C, corr);
     __syncthreads();
   };
   const int lc = nlev - 1;
+  smooth(lf, 0, false);
   for (int l = lf; l < lc; ++l) {
-    smooth(l, 0, false);
     smooth(l, 2, false);
     const MgLevel F = lv[l], C = lv[l + 1];
     for (int i = threadIdx.x; i < (int)C.nc; i += kMgFuseBlock)
 #pragma unroll
       for (int p = 0; p < N; ++p)
-        if (live[p]) mg_restrict_cell<D, 3>(g, F, C, p, i);
+        if (live[p]) mg_restrict_cell<D, 3>(g, F, C, p, i, true);   // f and t of l + 1
     __syncthreads();
   }
-  smooth(lc, 0, false);
   smooth(lc, 2, kMgCoarseSweeps <= 2);
   for (int k = 2; k < kMgCoarseSweeps; k += 2) {
     smooth(lc, 1, false);
     smooth(lc, 2, k + 2 >= kMgCoarseSweeps);
   }
   for (int l = lc - 1; l >= lf; --l) {
-    const MgLevel F = lv[l], C = lv[l + 1];
-    for (int i = threadIdx.x; i < (int)F.nc; i += kMgFuseBlock)
-#pragma unroll
-      for (int p = 0; p < N; ++p)
-        if (live[p]) mg_prolong_cell<3>(F, C, p, i, corr);
-    __syncthreads();
-    smooth(l, 1, false);
+    smooth(l, 5, false);                   // prolongation folded in
     smooth(l, 2, true);
   }
   if (lf > 0) {
@@ -1807,8 +1860,8 @@ void launch_pf_cells(const Group& G, double* part, int flag, double, hipStream_t
 }
 
 // multigrid passes over the work items of level l (kind: 0 level-0 weights,
-// 1 coarsen l -> l + 1, 2 diagonal, 3 smooth, 4 restrict l -> l + 1,
-// 5 prolong l + 1 -> l, 6 the fused cycle from level l down)
+// 1 coarsen l -> l + 1, 2 diagonal, 3 smooth (mode), 4 restrict l -> l + 1
+// (mode 1: with the first pass on l + 1), 6 the fused cycle from level l down)
 using MgFn = void (*)(const Group&, int kind, int l, int mode, hipStream_t);
 template <int N, int D>
 void launch_mg(const Group& G, int kind, int l, int mode, hipStream_t s) {
@@ -1819,8 +1872,7 @@ void launch_mg(const Group& G, int kind, int l, int mode, hipStream_t s) {
     case 1: hipLaunchKernelGGL((k_mg_coarsen<N, D>), dim3(G.lcount[l + 1]), blk, 0, s, G.desc, G.lmap[l + 1], n, l); break;
     case 2: hipLaunchKernelGGL((k_mg_diag<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l); break;
     case 3: hipLaunchKernelGGL((k_mg_smooth<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l, mode); break;
-    case 4: hipLaunchKernelGGL((k_mg_restrict<N, D>), dim3(G.lcount[l + 1]), blk, 0, s, G.desc, G.lmap[l + 1], n, l); break;
-    case 5: hipLaunchKernelGGL((k_mg_prolong<N, D>), dim3(G.lcount[l]), blk, 0, s, G.desc, G.lmap[l], n, l); break;
+    case 4: hipLaunchKernelGGL((k_mg_restrict<N, D>), dim3(G.lcount[l + 1]), blk, 0, s, G.desc, G.lmap[l + 1], n, l, mode); break;
     case 6: hipLaunchKernelGGL((k_mg_fused<N, D>), dim3(n), dim3(kMgFuseBlock), G.mg_lds, s, G.desc, l, G.nlev); break;
   }
 }
@@ -2052,15 +2104,14 @@ static void enqueue_vcycle(mp_weno_ctx* c, hipStream_t st) {
   for (const Group& G : c->groups) {
     MgFn f = T.mg[G.N][G.D];
     const int Lf = G.mg_fuse;                        // fused from here down
+    if (Lf > 0) f(G, 3, 0, 3, st);                   // t = omega f / dg, f from r
     for (int l = 0; l < Lf; ++l) {
-      f(G, 3, l, l == 0 ? 3 : 0, st);                // t = omega f / dg (level 0: f from r)
       f(G, 3, l, 2, st);                             // e = t + omega (f - K t) / dg
-      f(G, 4, l, 0, st);                             // f(l + 1) = R (f - K e)
+      f(G, 4, l, l + 1 < Lf ? 1 : 0, st);            // f(l + 1) = R (f - K e) (and its t)
     }
     f(G, 6, Lf, 0, st);                              // levels Lf .. nlev - 1
     for (int l = Lf - 1; l >= 0; --l) {
-      f(G, 5, l, 0, st);                             // e += P e(l + 1)
-      f(G, 3, l, 1, st);                             // t = e + omega (f - K e) / dg
+      f(G, 3, l, 5, st);                             // t = e' + omega (f - K e') / dg, e' = e + P e(l + 1)
       f(G, 3, l, l == 0 ? 4 : 2, st);                // e = t + omega (f - K t) / dg (level 0: u)
     }
   }
