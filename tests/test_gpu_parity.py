@@ -292,10 +292,43 @@ def test_check_bounds_restores_state():
     s.close()
 
 
+DEGENERATE = [
+    # shape, bc: one cell, and directions one or two cells wide
+    ((1,), I.BC_PERIODIC), ((1,), I.BC_OUTFLOW), ((1,), I.BC_SYMMETRY), ((2,), I.BC_SYMMETRY),
+    ((1, 1), I.BC_OUTFLOW), ((1, 1), I.BC_SYMMETRY), ((2, 1), I.BC_PERIODIC),
+    ((1, 1, 1), I.BC_PERIODIC), ((2, 1, 3), I.BC_OUTFLOW), ((1, 2, 1), I.BC_SYMMETRY),
+]
+
+
+@pytest.mark.parametrize("shape,bc", DEGENERATE)
+def test_rhs_degenerate_grids(oracle, shape, bc):
+    """Grids of a cell or two along some direction: every stencil holds copies
+    (or mirror images) of the same few cells.  L(U) against the oracle, and
+    exactly 0 for one cell with periodic or outflow ends (all faces see the
+    cell itself on both sides, so every flux difference and the velocity
+    divergence vanish)."""
+    w = I.random_state(shape, nphase=2, seed=51, bc=bc, lowp=0.0)
+    s = _solver(w)
+    Lg = s.rhs()[0].cpu().numpy().reshape(w.nU, -1)
+    s.close()
+    pb = oracle_problem(oracle, w)
+    Lo = pb.rhs(w.U.reshape(-1)).reshape(w.nU, -1)
+    assert np.isfinite(Lg).all()
+    if w.ncells == 1 and bc != I.BC_SYMMETRY:
+        assert np.all(Lg == 0.0) and np.all(Lo == 0.0)
+    sc = np.abs(Lo).max(axis=1) + _scales(w) / pb.dt(w.U.reshape(-1), 0.0)
+    assert (np.abs(Lg - Lo).max(axis=1) <= 1e-12 * sc).all(), np.abs(Lg - Lo).max(axis=1) / sc
+
+
 def test_invalid_arguments():
     from paper_2608_00746_amd.binding import MpWenoError, ERR_ARG, ERR_UNSUPPORTED
     w = I.random_state((16,), nphase=2, seed=1)
     w.gamma = np.array([1.0, 6.12])
+    with pytest.raises(MpWenoError) as ei:
+        _solver(w)
+    assert ei.value.status == ERR_ARG
+    w = I.random_state((16,), nphase=2, seed=1)
+    w.n = (0,)                     # an empty grid
     with pytest.raises(MpWenoError) as ei:
         _solver(w)
     assert ei.value.status == ERR_ARG
