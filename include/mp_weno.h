@@ -156,8 +156,9 @@ mp_status mp_weno_rhs(mp_weno_ctx *ctx, const double *const *U_in,
  *            over the present phases);
  *   grad[i]: the face gradients dQ_p/dx_d of the solution of Eq. (4), d N
  *            fields [d][p][cells], at the upper face of each cell (0 at an
- *            outflow end, across faces where phi(1 - phi) vanishes on both
- *            sides, and for a phase with [div J_p] = 0);
+ *            outflow end or a symmetry plane, across faces where
+ *            phi(1 - phi) vanishes on both sides, and for a phase with
+ *            [div J_p] = 0);
  *   dUdt[i]: the Phase-Field operator of Eq. (5), div F^PF, with those
  *            gradients and the WENO-C/CL face states of U_in (U layout).
  * Any of divj, grad, dUdt may be NULL (not computed); a non-NULL dUdt must
@@ -165,8 +166,8 @@ mp_status mp_weno_rhs(mp_weno_ctx *ctx, const double *const *U_in,
  * Needs phase_field = 1 (else MP_ERR_UNSUPPORTED); synchronises the stream
  * (the solve is driven from the host); MP_ERR_SOLVER if the solve did not
  * reach cg_rtol within cg_maxit iterations (over at most 16 restarts of the
- * conjugate gradients from the current Q; the message names the residual).  The parity entry point of the
- * Phase-Field step. */
+ * conjugate gradients from the current Q; the message names the residual).
+ * The parity entry point of the Phase-Field step. */
 mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
                             double *const *divj, double *const *grad,
                             double *const *dUdt);
@@ -232,13 +233,14 @@ mp_status mp_weno_advance(mp_weno_ctx *ctx, int32_t nsteps);
  * where = MP_WHERE_HOST (synchronises) or MP_WHERE_DEVICE. */
 mp_status mp_weno_diag(mp_weno_ctx *ctx, double *out, int32_t where);
 
-/* Set the time of every instance (host values; asynchronous copy). */
+/* Set the time of every instance (host array of n_inst values; synchronises
+ * the stream). */
 mp_status mp_weno_set_time(mp_weno_ctx *ctx, const double *t);
 
 /* Profiling: which = 0 off; 1, 2, 3 record a HIP event pair on the context's
- * stream around every launch of the x-sweep kernel, the y-sweep kernel, or
- * the whole RK stage (both sweeps) made by mp_weno_step (graph replay is
- * bypassed while profiling).  Resets the recorded launches. */
+ * stream around the x sweeps of every RK stage made by mp_weno_step, around
+ * its transverse sweeps (y, and z in 3D), or around the whole stage (graph
+ * replay is bypassed while profiling).  Resets the recorded launches. */
 mp_status mp_weno_profile(mp_weno_ctx *ctx, int32_t which);
 
 /* Total elapsed milliseconds and number of the launches recorded since the

@@ -1627,8 +1627,9 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_restrict(const Desc* __restric
 // nlev - 1 are copied into LDS (face weights and diagonals, and f(lf)); every
 // pass of the per-level kernels runs there, in the same order, separated by
 // workgroup barriers instead of launches (the coarse levels are otherwise
-// launch- and latency-bound); e(lf) goes back to global memory for the
-// prolongation to level lf - 1.  With lf = 0 the first pass reads the CG
+// launch- and latency-bound); e(lf) goes back to global memory, where the
+// first post-smoothing pass of level lf - 1 adds it (prolonged).  With
+// lf = 0 the first pass reads the CG
 // residual and the last one writes the preconditioned residual.  The host
 // picks lf so that these levels fit the dynamic LDS of the launch (6 N floats
 // per cell of each level).
