@@ -64,6 +64,9 @@ CASES = [
     # the paper runs this problem with both models (Sec. "Shock-vessel-bubble
     # interaction")
     lambda: _kapila(I.shock_vessel_bubble_3d(24, 12, 12)),
+    # the consistent limiter (WENO-CL) with HLLC in all three directions
+    lambda: I.random_state((10, 9, 11), nphase=3, seed=27, lowp=0.0,
+                           opts=I.Options(flux=I.FLUX_HLLC, recon=I.RECON_WENO_CL)),
 ]
 
 

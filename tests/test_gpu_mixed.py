@@ -34,7 +34,10 @@ def _mixed(w):
 @pytest.mark.parametrize("make", [
     lambda: I.shock_bubble_2d(256, 128), lambda: I.shock_interface_n3(128),
     lambda: I.advection_2d(64), lambda: I.batched_instance(160, 3, 0.15, 1.5e9),
-    lambda: I.paper_five_phase(50), lambda: I.air_helium_shock_tube(0.01)])
+    lambda: I.paper_five_phase(50), lambda: I.air_helium_shock_tube(0.01),
+    # Kapila model: the sound speed (Wood) and 1 + K_p in the mixed sweeps
+    lambda: I.random_state((40, 130), nphase=3, seed=21, lowp=0.0,
+                           opts=I.Options(flux=1, model=I.MODEL_KAPILA))])
 def test_rhs_mixed_vs_oracle(oracle, make):
     w = _mixed(make())
     s = _solver(w)
