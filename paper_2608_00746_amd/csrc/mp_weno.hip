@@ -994,7 +994,10 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_setup(const Desc* __restrict__
   s[kPfsRes] = 0.0;
   s[kPfsCorr] = kMgCorr;
 #pragma unroll
-  for (int p = 0; p < N; ++p) s[kPfsPits + p] = 0.0;
+  for (int p = 0; p < N; ++p) {
+    s[kPfsPits + p] = 0.0;
+    s[kPfsPrev + p] = -1.0;            // no start pass of this solve yet
+  }
 }
 
 // [div J_p] at every cell; start (or restart) of the CG solve: the residual
@@ -1096,8 +1099,10 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_start(const Desc* __restric
     if (threadIdx.x == 0) {
       s[kPfsBB + p] = bb;
       const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-      const bool iterated = s[kPfsPits + p] > 0.0;
-      const bool stalled = iterated && rel > 0.5 * s[kPfsPrev + p] && rel <= 1000.0 * rtol;
+      // stagnation: a restart of this solve (iterating or breaking down at
+      // once) did not halve the true residual, which is within 1000 rtol
+      const double prev = s[kPfsPrev + p];
+      const bool stalled = prev >= 0.0 && rel > 0.5 * prev && rel <= 1000.0 * rtol;
       const bool done = bb == 0.0 || sqrt(rr) <= rtol * sqrt(bb) + 64.0 * DBL_EPSILON * sqrt(fl) ||
                         stalled;
       s[kPfsPrev + p] = rel;

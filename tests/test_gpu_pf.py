@@ -223,6 +223,28 @@ def test_pf_solver_failure_restores_state():
     s.close()
 
 
+def test_pf_long_run_converges():
+    """Regression: 300 steps of the 2048 x 1024 shock-bubble with the
+    Phase-Field step.  Around step 250 a solve sits at its attainable
+    accuracy (true residual ~1e-11) and its restarts break down at their
+    first iteration; such a restart must count as stagnation (the residual
+    did not halve and is within 1000 cg_rtol), not run the solve out of
+    restarts (MP_ERR_SOLVER, as it once did)."""
+    import torch
+    w = I.shock_bubble_2d(2048, 1024)
+    w.opts.phase_field = 1
+    w.t_end = 0.0
+    s = _solver(w, stream=torch.cuda.Stream())
+    for _ in range(6):
+        s.advance(50)
+        d = s.diag()[0]
+        assert d[25] == 0 and d[30] <= 1000 * 1e-12, d[30]
+    assert d[27] == 300
+    assert d[20] <= 16 * 2 * EPS * np.sqrt(300)
+    assert d[21] >= -8 * EPS and d[22] >= -8 * EPS and d[23] <= 1 + 8 * EPS
+    s.close()
+
+
 @pytest.mark.parametrize("which", ["shock_bubble_2048x1024", "batched_256"])
 def test_pf_full_size_invariants(which):
     """The Phase-Field step at the benchmark sizes, where the oracle's direct
