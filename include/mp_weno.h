@@ -106,7 +106,9 @@ typedef struct {
                               term: the rounding floor of res itself), or
                               once a restart no longer halves it while it is
                               <= 1000 cg_rtol ||[div J]|| (stagnation at the
-                              attainable accuracy); <= 0: 1e-12              */
+                              attainable accuracy; a run whose recurrence sits
+                              within 1000 cg_rtol without halving for 50
+                              iterations ends for that check); <= 0: 1e-12   */
   int32_t cg_maxit;        /* iteration limit of that solve (<= 0: 10000)    */
   int32_t check_bounds;    /* 1: mp_weno_step checks the result (see below)  */
   int32_t use_graph;       /* 1: replay mp_weno_step as a captured HIP graph */

@@ -60,8 +60,9 @@ constexpr int kPartSlots = 40;    // partial slots per reduction chunk (stored s
 // M / eta^2, multipliers B_q, CG iterations and relative residual at exit,
 // the multigrid correction scale, and per phase ||b||^2, res.z, alpha, beta,
 // done flag, iterations, mean of the preconditioned residual, true relative
-// residual at the previous start
-constexpr int kPfsLen = 80;
+// residual at the previous start, the run's best recurrence residual and the
+// iteration it was reached at
+constexpr int kPfsLen = 96;
 constexpr int kPfFields = 8;      // Phase-Field work arrays of N fields each
 // floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
 // is solvable for every right side of zero total and stays conditioned; only
@@ -80,7 +81,13 @@ constexpr double kPfCfl = 1.0 / 12.0;
 constexpr double kMgCorr = 1.8;
 constexpr int kPfsM = 0, kPfsMe2 = 1, kPfsB = 2, kPfsIts = 10, kPfsRes = 11,
               kPfsCorr = 12, kPfsBB = 16, kPfsRZ = 24, kPfsAlpha = 32, kPfsBeta = 40,
-              kPfsDone = 48, kPfsPits = 56, kPfsUbar = 64, kPfsPrev = 72;
+              kPfsDone = 48, kPfsPits = 56, kPfsUbar = 64, kPfsPrev = 72,
+              kPfsBest = 80, kPfsBestIt = 88;
+// a run whose recurrence residual is within kPfsStallTol cg_rtol and has not
+// halved for kPfsStallIts iterations has stagnated at the attainable accuracy:
+// it ends, and the next start pass judges the true residual
+constexpr double kPfsStallTol = 1000.0;
+constexpr double kPfsStallIts = 50.0;
 
 // The state pointers come from a table in device memory, so the compiler
 // cannot tell their address space and would emit flat loads and stores (which
@@ -1102,7 +1109,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_start(const Desc* __restric
       // stagnation: a restart of this solve (iterating or breaking down at
       // once) did not halve the true residual, which is within 1000 rtol
       const double prev = s[kPfsPrev + p];
-      const bool stalled = prev >= 0.0 && rel > 0.5 * prev && rel <= 1000.0 * rtol;
+      const bool stalled = prev >= 0.0 && rel > 0.5 * prev && rel <= kPfsStallTol * rtol;
       const bool done = bb == 0.0 || sqrt(rr) <= rtol * sqrt(bb) + 64.0 * DBL_EPSILON * sqrt(fl) ||
                         stalled;
       s[kPfsPrev + p] = rel;
@@ -1318,9 +1325,16 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict
     {
       const double bb = s[kPfsBB + p];
       const double k = s[kPfsPits + p];
-      rmax = fmax(rmax, sqrt(rr / bb));
+      const double rel = sqrt(rr / bb);
+      rmax = fmax(rmax, rel);
+      if (k == 0.0 || rel < 0.5 * s[kPfsBest + p]) {
+        s[kPfsBest + p] = rel;
+        s[kPfsBestIt + p] = k;
+      }
       if (sqrt(rr) <= rtol * sqrt(bb)) {
         s[kPfsDone + p] = 1.0;
+      } else if (rel <= kPfsStallTol * rtol && k - s[kPfsBestIt + p] >= kPfsStallIts) {
+        s[kPfsDone + p] = 1.0;                 // stagnated: the start pass judges
       } else if (!(rz > 0.0)) {
         s[kPfsDone + p] = 1.0;                 // breakdown: restart
         s[kPfsCorr] = 1.0;

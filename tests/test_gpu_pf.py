@@ -245,6 +245,28 @@ def test_pf_long_run_converges():
     s.close()
 
 
+def test_pf_batched_long_run_converges():
+    """Regression: 60 steps of the 256-instance batch with the Phase-Field
+    step.  Around step 50 one instance's CG recurrence stagnates at ~2e-11
+    (within 1000 cg_rtol, not below cg_rtol); such a run must end and let the
+    start pass judge the true residual, not iterate to cg_maxit
+    (MP_ERR_SOLVER after 10000 iterations, as it once did)."""
+    import torch
+    ws = I.batched()
+    for w in ws:
+        w.opts.phase_field = 1
+        w.t_end = 0.0
+    s = _solver(ws, stream=torch.cuda.Stream())
+    for _ in range(4):
+        s.advance(15)
+        d = s.diag()
+        assert (d[:, 25] == 0).all() and (d[:, 30] <= 1000 * 1e-12).all(), d[:, 30].max()
+    assert (d[:, 27] == 60).all()
+    tau = 8 * EPS
+    assert (d[:, 21] >= -tau).all() and (d[:, 22] >= -tau).all() and (d[:, 23] <= 1 + tau).all()
+    s.close()
+
+
 @pytest.mark.parametrize("which", ["shock_bubble_2048x1024", "batched_256"])
 def test_pf_full_size_invariants(which):
     """The Phase-Field step at the benchmark sizes, where the oracle's direct
