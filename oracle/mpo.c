@@ -671,7 +671,12 @@ static double one_plus_K(const mpo_problem *pb, const double *U, int p) {
  * same Ubar), reconstruct cells -1..n of every line, take the flux at faces
  * -1/2..n-1/2 from (U^L of cell i, U^R of cell i+1) and add
  *   -(F_{i+1/2} - F_{i-1/2})/dx   and, for alpha_p,
- *   +alphabar_p (1 + K_p)(uhat_{i+1/2} - uhat_{i-1/2})/dx. */
+ *   +(alphabar_p / S)(1 + K_p)(uhat_{i+1/2} - uhat_{i-1/2})/dx,
+ * S = sum_q alphabar_q (1 for a consistent state).  Reading: with S the
+ * sources sum to the u-hat difference that the fluxes' alpha parts sum to,
+ * so sum_q alpha_q - 1 gets no source of its own (with alphabar_p alone it
+ * would grow as (S - 1)(uhat_{i+1/2} - uhat_{i-1/2})/dx where the flow
+ * expands). */
 int mpo_rhs(const mpo_problem *pb, const double *U, double *L) {
   int st = check_problem(pb);
   if (st != MPO_OK) return st;
@@ -720,10 +725,13 @@ int mpo_rhs(const mpo_problem *pb, const double *U, double *L) {
                 L[c * nc + cell] - (F[(i + 1) * nU + c] - F[i * nU + c]) / dx;
           double Uc[4 * MPO_MAXP + 4];
           for (int c = 0; c < nU; ++c) Uc[c] = U[c * nc + cell];
+          double S = 0.0;
+          for (int p = 0; p < N; ++p) S = S + Uc[IA(pb, p)];
           for (int p = 0; p < N; ++p) {
             const int c = IA(pb, p);
+            const double a = S > 0.0 ? Uc[c] / S : 0.0;
             L[c * nc + cell] = L[c * nc + cell] +
-                               Uc[c] * one_plus_K(pb, Uc, p) * (uh[i + 1] - uh[i]) / dx;
+                               a * one_plus_K(pb, Uc, p) * (uh[i + 1] - uh[i]) / dx;
           }
         }
       }

@@ -413,8 +413,14 @@ void k_sweep_x(const Desc* __restrict__ descs,
 #pragma unroll
       for (int c = 0; c < NU; ++c) L[c] = -(F.f[c] - sflux[c][l - 1]) * g.rdx;
       const double du = (F.uh - sflux[NU][l - 1]) * g.rdx;
+      // alpha_p / sum_q alpha_q: the sources sum to du, as the fluxes' alpha
+      // parts do, so sum_q alpha_q - 1 gets no source of its own
+      double sa = 0.0;
 #pragma unroll
-      for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
+      for (int p = 0; p < N; ++p) sa += ub.a[p];
+      const double isa = sa > 0.0 ? 1.0 / sa : 0.0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * isa * opk[p] * du;
     }
     const int64_t idx = row + xi;
     if constexpr (D == 1) {
@@ -575,8 +581,14 @@ void k_sweep_t(const Desc* __restrict__ descs,
       for (int c = 0; c < NU; ++c)
         L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * rd;
       const double du = (F.uh - sflux[NU][ty - 1][tx]) * rd;
+      // alpha_p / sum_q alpha_q: the sources sum to du, as the fluxes' alpha
+      // parts do, so sum_q alpha_q - 1 gets no source of its own
+      double sa = 0.0;
 #pragma unroll
-      for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * opk[p] * du;
+      for (int p = 0; p < N; ++p) sa += ub.a[p];
+      const double isa = sa > 0.0 ? 1.0 / sa : 0.0;
+#pragma unroll
+      for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * isa * opk[p] * du;
     }
     if constexpr (kLast) {
       finish_cell<N, D>(a, nc, idx, ub, L);
