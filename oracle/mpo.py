@@ -436,3 +436,24 @@ def num_threads():
 
 def set_num_threads(n):
     lib().mpo_set_num_threads(int(n))
+
+
+def interface_thickness(alpha, shape, dx, alpha_min=0.05, alpha_max=0.95):
+    """Interface thickness N_I of Eq. (30): the volume where
+    alpha_min <= alpha <= alpha_max, over dx times the integral of
+    |grad alpha|.  Integrals are sums over cells times the cell volume; the
+    gradient is the second-order central difference in the interior and the
+    one-sided difference at the ends of each direction.  alpha: cell values
+    in the state layout ([z][y][x], x fastest); dx: the cell size of each
+    direction (x first); Eq. (30) divides by the cell size, taken as the
+    smallest one."""
+    a = np.asarray(alpha, dtype=np.float64).reshape(tuple(shape)[::-1])
+    vol = float(np.prod(dx))
+    inside = ((a >= alpha_min) & (a <= alpha_max)).sum() * vol
+    g2 = np.zeros_like(a)
+    for d in range(len(shape)):
+        ax = a.ndim - 1 - d
+        if a.shape[ax] > 1:
+            g2 += np.gradient(a, dx[d], axis=ax) ** 2
+    grad = np.sqrt(g2).sum() * vol
+    return inside / (min(dx) * grad) if grad > 0.0 else 0.0
