@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define MP_WENO_ABI_VERSION 1
+#define MP_WENO_ABI_VERSION 2
 #define MP_MAXP 8        /* largest N this header describes                 */
 #define MP_DIAG_LEN 32   /* doubles per instance written by mp_weno_diag    */
 
@@ -66,10 +66,26 @@ typedef enum {
  * Sec. "Shock-vessel-bubble interaction").  The Phase-Field flux and
  * Eq. (4) treat outflow ends and symmetry planes alike: no face. */
 enum { MP_BC_PERIODIC = 0, MP_BC_OUTFLOW = 1, MP_BC_SYMMETRY = 2 };
-enum { MP_RECON_WENO_C = 0, MP_RECON_WENO_CL = 1 };
+/* Reconstructions: WENO-C (Sec. 3.4) and WENO-CL (Sec. 3.4.1) are the
+ * method; WENO_JS and WENO_W are the comparison schemes of Sec. 3.2 and
+ * Sec. 3.3: plain WENO5 on the primitive variables, every variable with its
+ * own weights (Eq. (12) with epsilon = 1e-6, or Eq. (15)), without the
+ * coupling of Eq. (16) and without any limiter (energy_limiter is ignored
+ * for them).  They exist to reproduce the consistency and temperature
+ * errors of Sec. 4.1.1; they preserve neither consistency nor bounds. */
+enum { MP_RECON_WENO_C = 0, MP_RECON_WENO_CL = 1, MP_RECON_WENO_JS = 2,
+       MP_RECON_WENO_W = 3 };
 enum { MP_FLUX_HLLC = 0, MP_FLUX_HLL = 1 };
 enum { MP_MODEL_ALLAIRE = 0, MP_MODEL_KAPILA = 1 };
 enum { MP_PREC_FP64 = 0, MP_PREC_MIXED = 1 };
+/* Cell value of alpha_p in the source alpha_p (1 + K_p) div u of Eq. (1):
+ * MP_SRC_CELL, the cell average (Eq. (3) as written, the default), or
+ * MP_SRC_NORMALIZED, the average over sum_q alpha_q of the cell (equal for
+ * a consistent state; then the phases' sources sum to the face-velocity
+ * difference exactly as their fluxes do, so a rounding deviation of
+ * sum_q alpha_q from 1 is transported but not amplified where the flow
+ * expands). */
+enum { MP_SRC_CELL = 0, MP_SRC_NORMALIZED = 1 };
 enum { MP_WHERE_DEVICE = 0, MP_WHERE_HOST = 1 };
 
 /* One uniform-grid problem instance (Sec. 2.1 and Eq. (26)). */
@@ -91,14 +107,22 @@ typedef struct {
 
 /* Scheme switches shared by all instances of a context. */
 typedef struct {
-  int32_t recon;           /* MP_RECON_WENO_C (Sec. 3.4) or _WENO_CL (3.4.1) */
+  int32_t recon;           /* MP_RECON_WENO_C (Sec. 3.4), _WENO_CL (3.4.1),
+                              or the comparators _WENO_JS, _WENO_W          */
   int32_t flux;            /* MP_FLUX_HLLC (Sec. 4.1) or MP_FLUX_HLL (4.2)   */
   int32_t model;           /* MP_MODEL_ALLAIRE (K_p = 0) or _KAPILA (Sec. 2.1)*/
   int32_t precision;       /* MP_PREC_FP64 or MP_PREC_MIXED                  */
   int32_t energy_limiter;  /* 1: apply Eq. (21) (default); 0: skip it       */
   int32_t phase_field;     /* 1: each step ends with the Phase-Field step of
                               Sec. 2.2.1 (Eqs. (4), (5), (28)); 0: off       */
-  double cfl;              /* CFL number of the time step (> 0)              */
+  double cfl;              /* CFL number of the time step (> 0).  The bounds
+                              of Eq. (8) are guaranteed for the updated
+                              averages only with cfl <= 1/12 and the HLL
+                              flux (Sec. 4.2: Gauss-Lobatto end weight);
+                              above it (the paper runs its applications at
+                              0.2) they are observed, not guaranteed, and
+                              an intermediate RK stage may leave them while
+                              the step's result is back inside           */
   double eta_over_dx;      /* eta / min_d dx_d of Eq. (28) (> 0; 1 in Sec. 4) */
   double cg_rtol;          /* Eq. (4) solve: stop once the true residual
                               ||res|| = ||-[div J] - K Q|| <= cg_rtol ||[div J]||
@@ -110,8 +134,10 @@ typedef struct {
                               within 1000 cg_rtol without halving for 50
                               iterations ends for that check); <= 0: 1e-12   */
   int32_t cg_maxit;        /* iteration limit of that solve (<= 0: 10000)    */
-  int32_t check_bounds;    /* 1: mp_weno_step checks the result (see below)  */
+  int32_t check_bounds;    /* 1: mp_weno_step checks the result of each step
+                              (not the intermediate RK stages; see below)  */
   int32_t use_graph;       /* 1: replay mp_weno_step as a captured HIP graph */
+  int32_t alpha_source;    /* MP_SRC_CELL (0, default) or MP_SRC_NORMALIZED  */
 } mp_weno_opts;
 
 typedef struct mp_weno_ctx mp_weno_ctx;

@@ -382,6 +382,33 @@ void mpo_reconstruct_cell(const mpo_problem *pb, const double *Us, int dir,
   /* Primitive cell averages, Vbar = psi_{U->V}(Ubar) (Sec. 3.4). */
   for (int j = 0; j < 5; ++j) cons_to_prim(pb, Us + j * nU, V[j]);
 
+  if (pb->recon == MPO_RECON_WENO_JS || pb->recon == MPO_RECON_WENO_W) {
+    /* Comparison schemes (Sec. 3.2, Sec. 3.3): every primitive variable
+     * reconstructed with its own weights, Eq. (12) (epsilon 1e-6) or
+     * Eq. (15), as the weighted sum of the candidates (Eqs. (10), (13));
+     * no limiter. */
+    const int nV = nU;
+    for (int c = 0; c < nV; ++c) {
+      double q[5], beta[3], wL[3], wR[3], cL[3], cR[3];
+      for (int j = 0; j < 5; ++j) q[j] = V[j][c];
+      mpo_weno5_beta(q, beta);
+      if (pb->recon == MPO_RECON_WENO_JS) {
+        mpo_wenojs_weights(beta, dL, MPO_WENOJS_EPS, wL);
+        mpo_wenojs_weights(beta, dR, MPO_WENOJS_EPS, wR);
+      } else {
+        mpo_wenow_weights(beta, dL, wL);
+        mpo_wenow_weights(beta, dR, wR);
+      }
+      mpo_weno5_candidates(q, cL, cR);
+      VL[c] = wL[0] * cL[0] + wL[1] * cL[1] + wL[2] * cL[2];
+      VR[c] = wR[0] * cR[0] + wR[1] * cR[1] + wR[2] * cR[2];
+    }
+    prim_to_cons(pb, VL, UL);
+    prim_to_cons(pb, VR, UR);
+    if (info) { info[0] = 1.0; info[1] = 1.0; info[2] = 0.0; }
+    return;
+  }
+
   /* u and P: plain WENO-W on each primitive (Sec. 3.4, Eq. (15)). */
   for (int k = 0; k <= d; ++k) {
     double q[5];
@@ -671,12 +698,13 @@ static double one_plus_K(const mpo_problem *pb, const double *U, int p) {
  * same Ubar), reconstruct cells -1..n of every line, take the flux at faces
  * -1/2..n-1/2 from (U^L of cell i, U^R of cell i+1) and add
  *   -(F_{i+1/2} - F_{i-1/2})/dx   and, for alpha_p,
- *   +(alphabar_p / S)(1 + K_p)(uhat_{i+1/2} - uhat_{i-1/2})/dx,
- * S = sum_q alphabar_q (1 for a consistent state).  Reading: with S the
- * sources sum to the u-hat difference that the fluxes' alpha parts sum to,
- * so sum_q alpha_q - 1 gets no source of its own (with alphabar_p alone it
- * would grow as (S - 1)(uhat_{i+1/2} - uhat_{i-1/2})/dx where the flow
- * expands). */
+ *   +alphabar_p (1 + K_p)(uhat_{i+1/2} - uhat_{i-1/2})/dx
+ * (Eq. (3) with H^HB at the cell average).  With alpha_source =
+ * MPO_SRC_NORMALIZED the cell value is alphabar_p / S, S = sum_q
+ * alphabar_q (1 for a consistent state): the sources then sum to the u-hat
+ * difference that the fluxes' alpha parts sum to, so sum_q alpha_q - 1 gets
+ * no source of its own (with alphabar_p it grows as
+ * (S - 1)(uhat_{i+1/2} - uhat_{i-1/2})/dx where the flow expands). */
 int mpo_rhs(const mpo_problem *pb, const double *U, double *L) {
   int st = check_problem(pb);
   if (st != MPO_OK) return st;
@@ -729,7 +757,8 @@ int mpo_rhs(const mpo_problem *pb, const double *U, double *L) {
           for (int p = 0; p < N; ++p) S = S + Uc[IA(pb, p)];
           for (int p = 0; p < N; ++p) {
             const int c = IA(pb, p);
-            const double a = S > 0.0 ? Uc[c] / S : 0.0;
+            const double a = pb->alpha_source != MPO_SRC_NORMALIZED ? Uc[c]
+                             : (S > 0.0 ? Uc[c] / S : 0.0);
             L[c * nc + cell] = L[c * nc + cell] +
                                a * one_plus_K(pb, Uc, p) * (uh[i + 1] - uh[i]) / dx;
           }

@@ -26,7 +26,17 @@ extern "C" {
 #define MPO_MAXP 8
 
 enum { MPO_BC_PERIODIC = 0, MPO_BC_OUTFLOW = 1, MPO_BC_SYMMETRY = 2 };
-enum { MPO_RECON_WENO_C = 0, MPO_RECON_WENO_CL = 1 };
+/* WENO_JS and WENO_W are the comparison schemes of Sec. 3.2 and Sec. 3.3:
+ * plain WENO5 on the primitive variables, every variable with its own
+ * weights (Eq. (12) with epsilon = MPO_WENOJS_EPS, or Eq. (15)), no
+ * coupling of Eq. (16) and none of the limiters of Sec. 3.4. */
+enum { MPO_RECON_WENO_C = 0, MPO_RECON_WENO_CL = 1, MPO_RECON_WENO_JS = 2,
+       MPO_RECON_WENO_W = 3 };
+#define MPO_WENOJS_EPS 1e-6
+/* Cell value of alpha_p in the source alpha_p (1 + K_p) div u (Eq. (1)):
+ * the cell average itself (the equation as written), or the average over
+ * the cell's sum of volume fractions (equal for a consistent state). */
+enum { MPO_SRC_CELL = 0, MPO_SRC_NORMALIZED = 1 };
 enum { MPO_FLUX_HLLC = 0, MPO_FLUX_HLL = 1 };
 enum { MPO_MODEL_ALLAIRE = 0, MPO_MODEL_KAPILA = 1 };
 
@@ -53,6 +63,7 @@ typedef struct {
   int energy_limiter;       /* 1: apply Eq. (21); 0: skip it (ablation)      */
   double cfl;               /* CFL number for mpo_dt                         */
   double t_end;             /* 0: no clipping                                */
+  int alpha_source;         /* MPO_SRC_CELL (default) or MPO_SRC_NORMALIZED  */
 } mpo_problem;
 
 int mpo_nU(const mpo_problem *pb);

@@ -29,7 +29,8 @@ PF_KFLOOR = 1e-6
 PF_CFL = 1.0 / 12.0
 
 BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY = 0, 1, 2
-RECON_WENO_C, RECON_WENO_CL = 0, 1
+RECON_WENO_C, RECON_WENO_CL, RECON_WENO_JS, RECON_WENO_W = 0, 1, 2, 3
+SRC_CELL, SRC_NORMALIZED = 0, 1
 FLUX_HLLC, FLUX_HLL = 0, 1
 MODEL_ALLAIRE, MODEL_KAPILA = 0, 1
 
@@ -53,7 +54,7 @@ class _Problem(C.Structure):
         ("D", C.c_double * MAXP), ("pmin", C.c_double * MAXP),
         ("cT", C.c_double * MAXP), ("recon", C.c_int), ("flux", C.c_int),
         ("model", C.c_int), ("energy_limiter", C.c_int), ("cfl", C.c_double),
-        ("t_end", C.c_double),
+        ("t_end", C.c_double), ("alpha_source", C.c_int),
     ]
 
 
@@ -121,7 +122,8 @@ class Problem:
 
     def __init__(self, ndim, n, dx, bc, gamma, pinf, D=None, pmin=None,
                  cT=None, recon=RECON_WENO_C, flux=FLUX_HLLC,
-                 model=MODEL_ALLAIRE, energy_limiter=1, cfl=0.5, t_end=0.0):
+                 model=MODEL_ALLAIRE, energy_limiter=1, cfl=0.5, t_end=0.0,
+                 alpha_source=SRC_CELL):
         N = len(gamma)
         assert 1 <= N <= MAXP
         p = _Problem()
@@ -147,6 +149,7 @@ class Problem:
         p.energy_limiter = int(energy_limiter)
         p.cfl = float(cfl)
         p.t_end = float(t_end)
+        p.alpha_source = int(alpha_source)
         self._p = p
         self.ndim, self.N = ndim, N
         self.dx = tuple(float(dd[k]) for k in range(ndim))

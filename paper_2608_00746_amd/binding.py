@@ -45,7 +45,7 @@ class Opts(C.Structure):
         ("phase_field", C.c_int32), ("cfl", C.c_double),
         ("eta_over_dx", C.c_double), ("cg_rtol", C.c_double),
         ("cg_maxit", C.c_int32), ("check_bounds", C.c_int32),
-        ("use_graph", C.c_int32),
+        ("use_graph", C.c_int32), ("alpha_source", C.c_int32),
     ]
 
 
@@ -136,6 +136,7 @@ def make_opts(o, check_bounds=False, use_graph=False):
     x.eta_over_dx = float(o.eta_over_dx)
     x.cg_rtol, x.cg_maxit = float(o.cg_rtol), int(o.cg_maxit)
     x.check_bounds, x.use_graph = int(check_bounds), int(use_graph)
+    x.alpha_source = int(getattr(o, "alpha_source", 0))
     return x
 
 

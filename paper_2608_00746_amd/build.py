@@ -21,7 +21,6 @@ def flags():
         # wrong results without an error on this architecture)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-fno-fast-math", "-ffp-contract=fast-honor-pragmas",
-        "-munsafe-fp-atomics",
         "-I", os.path.join(ROOT, "include"),
     ]
 

@@ -413,12 +413,16 @@ void k_sweep_x(const Desc* __restrict__ descs,
 #pragma unroll
       for (int c = 0; c < NU; ++c) L[c] = -(F.f[c] - sflux[c][l - 1]) * g.rdx;
       const double du = (F.uh - sflux[NU][l - 1]) * g.rdx;
-      // alpha_p / sum_q alpha_q: the sources sum to du, as the fluxes' alpha
-      // parts do, so sum_q alpha_q - 1 gets no source of its own
-      double sa = 0.0;
+      // alpha_p at the cell average, or alpha_p / sum_q alpha_q (then the
+      // sources sum to du, as the fluxes' alpha parts do, and
+      // sum_q alpha_q - 1 gets no source of its own)
+      double isa = 1.0;
+      if (g.asrc) {
+        double sa = 0.0;
 #pragma unroll
-      for (int p = 0; p < N; ++p) sa += ub.a[p];
-      const double isa = sa > 0.0 ? 1.0 / sa : 0.0;
+        for (int p = 0; p < N; ++p) sa += ub.a[p];
+        isa = sa > 0.0 ? 1.0 / sa : 0.0;
+      }
 #pragma unroll
       for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * isa * opk[p] * du;
     }
@@ -581,12 +585,16 @@ void k_sweep_t(const Desc* __restrict__ descs,
       for (int c = 0; c < NU; ++c)
         L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * rd;
       const double du = (F.uh - sflux[NU][ty - 1][tx]) * rd;
-      // alpha_p / sum_q alpha_q: the sources sum to du, as the fluxes' alpha
-      // parts do, so sum_q alpha_q - 1 gets no source of its own
-      double sa = 0.0;
+      // alpha_p at the cell average, or alpha_p / sum_q alpha_q (then the
+      // sources sum to du, as the fluxes' alpha parts do, and
+      // sum_q alpha_q - 1 gets no source of its own)
+      double isa = 1.0;
+      if (g.asrc) {
+        double sa = 0.0;
 #pragma unroll
-      for (int p = 0; p < N; ++p) sa += ub.a[p];
-      const double isa = sa > 0.0 ? 1.0 / sa : 0.0;
+        for (int p = 0; p < N; ++p) sa += ub.a[p];
+        isa = sa > 0.0 ? 1.0 / sa : 0.0;
+      }
 #pragma unroll
       for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * isa * opk[p] * du;
     }
@@ -2020,6 +2028,43 @@ static const Table& table() {
 
 using namespace mpw;
 
+// Grid and EOS part of an instance descriptor (every other field zero).
+// A_p, B_p of Eq. (26) and EB_p = A_p Pmin_p + B_p of Eq. (9).
+static void desc_grid_eos(const mp_weno_instance& s, const mp_weno_opts& opt, Desc& d) {
+  std::memset(&d, 0, sizeof(d));
+  const int D = s.ndim;
+  Grid& g = d.g;
+  g.nx = s.n[0];
+  g.ny = D > 1 ? s.n[1] : 1;
+  g.nz = D > 2 ? s.n[2] : 1;
+  g.nc = (int64_t)g.nx * g.ny * g.nz;
+  g.rdx = 1.0 / s.dx[0];
+  g.hdx = 0.5 * s.dx[0];
+  g.rdy = D > 1 ? 1.0 / s.dx[1] : 0.0;
+  g.hdy = D > 1 ? 0.5 * s.dx[1] : 1.0;
+  g.bcx0 = s.bc[0][0]; g.bcx1 = s.bc[0][1];
+  g.bcy0 = D > 1 ? s.bc[1][0] : 0;
+  g.bcy1 = D > 1 ? s.bc[1][1] : 0;
+  g.rdz = D > 2 ? 1.0 / s.dx[2] : 0.0;
+  g.hdz = D > 2 ? 0.5 * s.dx[2] : 1.0;
+  g.bcz0 = D > 2 ? s.bc[2][0] : 0;
+  g.bcz1 = D > 2 ? s.bc[2][1] : 0;
+  g.recon = opt.recon;
+  g.flux = opt.flux;
+  g.model = opt.model;
+  g.energy = opt.energy_limiter ? 1 : 0;
+  g.asrc = opt.alpha_source;
+  for (int p = 0; p < s.nphase; ++p) {
+    const double gm = s.gamma[p], pi = s.pinf[p];
+    d.e.A[p] = 1.0 / (gm - 1.0);
+    d.e.B[p] = gm * pi / (gm - 1.0);
+    d.e.Dp[p] = s.D[p];
+    d.e.gam[p] = gm;
+    d.e.pinf[p] = pi;
+    d.e.EB[p] = d.e.A[p] * s.pmin[p] + d.e.B[p];
+  }
+}
+
 struct mp_weno_ctx {
   std::vector<Inst> inst;
   std::vector<Group> groups;
@@ -2360,8 +2405,9 @@ static mp_status validate(int32_t n_inst, const mp_weno_instance* inst,
   if (opt->phase_field != 0 && opt->phase_field != 1) return MP_ERR_ARG;
   if (opt->phase_field && !(opt->eta_over_dx > 0.0)) return MP_ERR_ARG;
   if (opt->precision != MP_PREC_FP64 && opt->precision != MP_PREC_MIXED) return MP_ERR_ARG;
-  if (opt->recon < 0 || opt->recon > 1 || opt->flux < 0 || opt->flux > 1 ||
-      opt->model < 0 || opt->model > 1 || !(opt->cfl > 0.0))
+  if (opt->recon < 0 || opt->recon > 3 || opt->flux < 0 || opt->flux > 1 ||
+      opt->model < 0 || opt->model > 1 || !(opt->cfl > 0.0) ||
+      (opt->alpha_source != MP_SRC_CELL && opt->alpha_source != MP_SRC_NORMALIZED))
     return MP_ERR_ARG;
   if (opt->use_graph && !hip_stream) return MP_ERR_ARG;   // no capture on the null stream
   for (int i = 0; i < n_inst; ++i) {
@@ -2510,36 +2556,8 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         const Inst& I = c->inst[id];
         const mp_weno_instance& s = I.in;
         Desc d;
-        std::memset(&d, 0, sizeof(d));
-        Grid& g = d.g;
-        g.nx = s.n[0];
-        g.ny = I.D > 1 ? s.n[1] : 1;
-        g.nc = I.nc;
-        g.rdx = 1.0 / s.dx[0];
-        g.hdx = 0.5 * s.dx[0];
-        g.rdy = I.D > 1 ? 1.0 / s.dx[1] : 0.0;
-        g.hdy = I.D > 1 ? 0.5 * s.dx[1] : 1.0;
-        g.bcx0 = s.bc[0][0]; g.bcx1 = s.bc[0][1];
-        g.bcy0 = I.D > 1 ? s.bc[1][0] : 0;
-        g.bcy1 = I.D > 1 ? s.bc[1][1] : 0;
-        g.nz = I.D > 2 ? s.n[2] : 1;
-        g.rdz = I.D > 2 ? 1.0 / s.dx[2] : 0.0;
-        g.hdz = I.D > 2 ? 0.5 * s.dx[2] : 1.0;
-        g.bcz0 = I.D > 2 ? s.bc[2][0] : 0;
-        g.bcz1 = I.D > 2 ? s.bc[2][1] : 0;
-        g.recon = opt->recon;
-        g.flux = opt->flux;
-        g.model = opt->model;
-        g.energy = opt->energy_limiter ? 1 : 0;
-        for (int p = 0; p < I.N; ++p) {
-          const double gm = s.gamma[p], pi = s.pinf[p];
-          d.e.A[p] = 1.0 / (gm - 1.0);
-          d.e.B[p] = gm * pi / (gm - 1.0);
-          d.e.Dp[p] = s.D[p];
-          d.e.gam[p] = gm;
-          d.e.pinf[p] = pi;
-          d.e.EB[p] = d.e.A[p] * s.pmin[p] + d.e.B[p];
-        }
+        desc_grid_eos(s, *opt, d);
+        const Grid& g = d.g;
         d.U = s.U;
         d.U1 = I.U1;
         d.U2 = I.U2;
@@ -2947,6 +2965,9 @@ mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {
       HIPCHK(c, hipMemcpyAsync(I.backup, I.in.U, sizeof(double) * I.nU * I.nc,
                                hipMemcpyDeviceToDevice, c->stream));
   }
+  // with check_bounds: the time and step count before the step, read back
+  // now (the call synchronises anyway), so no copy into this host buffer is
+  // in flight when an error returns early
   std::vector<double> t_before;
   if (c->opt.check_bounds) {
     t_before.resize(2 * n);
@@ -2954,7 +2975,19 @@ mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(t_before.data() + n, c->steps, sizeof(double) * n,
                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
   }
+  // back to the state, time and step count before the step (check_bounds)
+  auto restore = [&]() -> mp_status {
+    for (auto& I : c->inst)
+      HIPCHK(c, hipMemcpyAsync(I.in.U, I.backup, sizeof(double) * I.nU * I.nc,
+                               hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->t, t_before.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->steps, t_before.data() + n, sizeof(double) * n,
+                        hipMemcpyHostToDevice));
+    return MP_OK;
+  };
   const bool ext = dt_dev != nullptr;
   if (ext)
     HIPCHK(c, hipMemcpyAsync(c->dt, dt_dev, sizeof(double) * n, hipMemcpyDeviceToDevice,
@@ -2976,10 +3009,8 @@ mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {
     mp_status s = enqueue_step(c, ext);
     if (s != MP_OK) {
       if (c->opt.check_bounds) {
-        for (auto& I : c->inst)
-          HIPCHK(c, hipMemcpyAsync(I.in.U, I.backup, sizeof(double) * I.nU * I.nc,
-                                   hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const mp_status r = restore();
+        if (r != MP_OK) return r;
       }
       return s;
     }
@@ -3001,14 +3032,8 @@ mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {
         verdict = MP_ERR_INADMISSIBLE;
     }
     if (verdict != MP_OK) {
-      for (auto& I : c->inst)
-        HIPCHK(c, hipMemcpyAsync(I.in.U, I.backup, sizeof(double) * I.nU * I.nc,
-                                 hipMemcpyDeviceToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(c->t, t_before.data(), sizeof(double) * n,
-                               hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(c->steps, t_before.data() + n, sizeof(double) * n,
-                               hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
+      const mp_status r = restore();
+      if (r != MP_OK) return r;
       return fail(c, verdict, mp_weno_strerror(verdict));
     }
   }

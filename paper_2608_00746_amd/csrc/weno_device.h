@@ -33,6 +33,7 @@ struct Grid {
   double hdx, hdy, hdz;    // dx/2, dy/2, dz/2 (slopes of the consistent limiter)
   int bcx0, bcx1, bcy0, bcy1, bcz0, bcz1;
   int recon, flux, model, energy;
+  int asrc;                // alpha_p of the source: 0 cell average, 1 / sum alpha
 };
 
 // -------------------------------------------------------------------------
@@ -297,6 +298,44 @@ __device__ __forceinline__ void wenow_weights(const W bin[3], W wl[3], W wr[3]) 
   }
 }
 
+// WENO-JS weights, Eq. (12) with three stencils and epsilon = 1e-6 (the
+// comparison scheme of Sec. 3.2 only).
+__device__ __forceinline__ void wenojs_weights(const double b[3], double wl[3], double wr[3]) {
+  const double eps = 1e-6;
+  double q[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double t = b[k] + eps;
+    q[k] = 1.0 / (t * t);
+  }
+  const double l0 = 0.1 * q[0], l1 = 0.6 * q[1], l2 = 0.3 * q[2];
+  const double r0 = 0.3 * q[0], r1 = 0.6 * q[1], r2 = 0.1 * q[2];
+  const double sl = l0 + l1 + l2, sr = r0 + r1 + r2;
+  wl[0] = l0 / sl; wl[1] = l1 / sl; wl[2] = l2 / sl;
+  wr[0] = r0 / sr; wr[1] = r1 / sr; wr[2] = r2 / sr;
+}
+
+// Comparison schemes (Sec. 3.2, 3.3): one primitive variable reconstructed
+// with its own weights, Eq. (12) (js) or Eq. (15), as the weighted candidate
+// sum of Eqs. (10), (13); FP64.
+__device__ __forceinline__ void plain_weno(double q0, double q1, double q2, double q3,
+                                           double q4, bool js, double& fl, double& fr) {
+  const Diff df = diffs(q0, q1, q2, q3, q4);
+  double b[3], wl[3], wr[3];
+  beta3<double>(df, b);
+  if (js) wenojs_weights(b, wl, wr);
+  else wenow_weights<double>(b, wl, wr);
+  const double s6 = 1.0 / 6.0;
+  const double cl0 = (2.0 * q0 - 7.0 * q1 + 11.0 * q2) * s6;
+  const double cl1 = (-q1 + 5.0 * q2 + 2.0 * q3) * s6;
+  const double cl2 = (2.0 * q2 + 5.0 * q3 - q4) * s6;
+  const double cr0 = (-q0 + 5.0 * q1 + 2.0 * q2) * s6;
+  const double cr1 = (2.0 * q1 + 5.0 * q2 - q3) * s6;
+  const double cr2 = (11.0 * q2 - 7.0 * q3 + 2.0 * q4) * s6;
+  fl = wl[0] * cl0 + wl[1] * cl1 + wl[2] * cl2;
+  fr = wr[0] * cr0 + wr[1] * cr1 + wr[2] * cr2;
+}
+
 // Face values of Eq. (10): fbar + sum_s w_s (f^(s) - fbar) (equal to the
 // weighted candidate sum since the weights sum to one, and exact on constant
 // data).  FP64 weights and sums on the FP64 path; on the mixed path the u and
@@ -396,6 +435,24 @@ __device__ __forceinline__ void reconstruct(const S& st,
                                             double hdx, Face<N, D>& fm,
                                             Face<N, D>& fp) {
   constexpr bool MIXED = sizeof(W) == 4;
+  if (g.recon >= 2) {
+    // comparison schemes: every primitive with its own weights, no limiter
+    const bool js = g.recon == 2;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      plain_weno(st(p, 0), st(p, 1), st(p, 2), st(p, 3), st(p, 4), js, fp.m[p], fm.m[p]);
+      plain_weno(st(N + p, 0), st(N + p, 1), st(N + p, 2), st(N + p, 3), st(N + p, 4), js,
+                 fp.a[p], fm.a[p]);
+    }
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+      const int c = 2 * N + k;
+      double vl, vr;
+      plain_weno(st(c, 0), st(c, 1), st(c, 2), st(c, 3), st(c, 4), js, vl, vr);
+      if (k < D) { fp.u[k] = vl; fm.u[k] = vr; }
+      else { fp.P = vl; fm.P = vr; }
+    }
+  } else {
   // u and P: WENO5-W on each primitive (Sec. 3.4)
 #pragma unroll
   for (int k = 0; k <= D; ++k) {
@@ -504,6 +561,8 @@ __device__ __forceinline__ void reconstruct(const S& st,
     fm.a[p] = fmin(fmax(fm.a[p], 0.0), 1.0);
   }
 
+  }  // WENO-C / WENO-CL
+
   // Step 5: U^{L,R} = psi_{V->U}(V^{L,R})
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -523,7 +582,7 @@ __device__ __forceinline__ void reconstruct(const S& st,
     f.rho = rho;
   }
 
-  if (g.energy) {
+  if (g.energy && g.recon < 2) {
     // Eq. (21): one theta^psi from psi at Ubar, U^L, U^R and U^C
     double cm[N], ca[N], cmom[D];
 #pragma unroll

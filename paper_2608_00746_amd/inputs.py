@@ -22,7 +22,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 BC_PERIODIC, BC_OUTFLOW, BC_SYMMETRY = 0, 1, 2
-RECON_WENO_C, RECON_WENO_CL = 0, 1
+RECON_WENO_C, RECON_WENO_CL, RECON_WENO_JS, RECON_WENO_W = 0, 1, 2, 3
+SRC_CELL, SRC_NORMALIZED = 0, 1
 FLUX_HLLC, FLUX_HLL = 0, 1
 MODEL_ALLAIRE, MODEL_KAPILA = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
@@ -40,6 +41,7 @@ class Options:
     eta_over_dx: float = 1.0
     cg_rtol: float = 1e-12
     cg_maxit: int = 10000
+    alpha_source: int = SRC_CELL
 
 
 @dataclass

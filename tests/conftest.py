@@ -26,7 +26,8 @@ def oracle_problem(mpo, w, **over):
     """Oracle Problem for an inputs.Workload (plain field copy)."""
     o = w.opts
     kw = dict(recon=o.recon, flux=o.flux, model=o.model,
-              energy_limiter=o.energy_limiter, cfl=o.cfl, t_end=w.t_end)
+              energy_limiter=o.energy_limiter, cfl=o.cfl, t_end=w.t_end,
+              alpha_source=o.alpha_source)
     kw.update(over)
     return mpo.Problem(w.ndim, w.n, w.dx, w.bc, list(w.gamma), list(w.pinf),
                        list(w.D), list(w.pmin), list(w.cT), **kw)

@@ -170,17 +170,23 @@ def test_dt_cfl(oracle):
     assert pb2.dt(U.reshape(-1), 0.0) == 1e-9
 
 
-def test_alpha_sum_gets_no_source(oracle):
-    """The alpha source alphabar_p (1 + K_p) div u-hat is taken with
-    alphabar_p / sum_q alphabar_q (the same for a consistent state): the
-    sources then sum to the u-hat difference that the fluxes' alpha parts sum
-    to (faces closed to sum 1), so a deviation S - 1 of sum_q alpha_q gets no
-    source.  Rough 1D states whose volume fractions sum to 1 + 1e-6, with
-    random (compressing and expanding) velocities: sum_p L(alpha_p) stays at
-    rounding in every cell, both models; with alphabar_p alone it would be
-    1e-6 of the u-hat difference over dx.  (Cells that fall back to first
-    order take the averages as face values, whose alphas sum to S, so there
-    the cancellation needs S = 1; such cells are absent here.)"""
+def test_alpha_source_forms(oracle):
+    """The alpha source of Eq. (3), alpha_p (1 + K_p) times the u-hat
+    difference over dx, at the cell average alphabar_p (the default, the
+    equation as written) or at alphabar_p / S, S = sum_q alphabar_q (the
+    same for a consistent state).  Rough 1D states whose volume fractions
+    sum to 1 + 1e-6, random (compressing and expanding) velocities:
+    * only the alpha rates differ between the forms, and for the Allaire
+      model (K_p = 0) by alphabar_p (1 - 1/S) times one per-cell factor, the
+      u-hat difference over dx;
+    * with alphabar_p / S the sources sum to the u-hat difference that the
+      fluxes' alpha parts sum to (faces closed to sum 1), so sum_p L(alpha_p)
+      stays at rounding in every cell, both models, while the cell form
+      leaves (S - 1) times that difference.  (A cell limited by theta_i or
+      theta^psi, or falling back to first order, has faces
+      alphabar + theta (alpha^face - alphabar) whose alphas sum to
+      S + theta (1 - S), so there the cancellation needs S = 1; such cells
+      are absent from this state.)"""
     N = 3
     for model in (0, 1):
         w = I.random_state((64,), nphase=N, seed=7, lowp=0.0,
@@ -188,7 +194,28 @@ def test_alpha_sum_gets_no_source(oracle):
         U = w.U.reshape(w.nU, -1).copy()
         ia = slice(N + w.ndim + 1, N + w.ndim + 1 + N)
         U[ia] *= 1.0 + 1e-6
-        pb = oracle_problem(oracle, w)
-        La = pb.rhs(U.reshape(-1)).reshape(w.nU, -1)[ia]
+        S = U[ia].sum(axis=0)
+        Ln = oracle_problem(oracle, w, alpha_source=oracle.SRC_NORMALIZED).rhs(
+            U.reshape(-1)).reshape(w.nU, -1)
+        Lc = oracle_problem(oracle, w, alpha_source=oracle.SRC_CELL).rhs(
+            U.reshape(-1)).reshape(w.nU, -1)
+        La = Ln[ia]
         assert np.abs(La.sum(axis=0)).max() <= 1e-14 * np.abs(La).max()
         assert np.abs(La).max() > 0.0
+        assert np.array_equal(Ln[:ia.start], Lc[:ia.start])
+        d = Lc[ia] - Ln[ia]
+        assert np.abs(d).max() > 0.0
+        if model == 0:
+            # the u-hat difference over dx, from every phase present in a cell
+            pres = U[ia] > 1e-3
+            with np.errstate(divide="ignore", invalid="ignore"):
+                f = np.where(pres, d / (U[ia] * (1.0 - 1.0 / S)), np.nan)
+            fmax, fmin = np.nanmax(f, axis=0), np.nanmin(f, axis=0)
+            big = np.abs(fmax) > 1e-3 * np.nanmax(np.abs(f))
+            assert big.sum() > 10
+            spread = (fmax - fmin)[big] / np.abs(fmax)[big]
+            assert spread.max() <= 1e-6, spread.max()
+            # the cell form's alpha rates sum to (S - 1) times it
+            sc = Lc[ia].sum(axis=0)[big]
+            assert np.allclose(sc, ((S - 1.0) * fmax)[big], rtol=1e-5,
+                               atol=1e-12 * np.abs(Lc[ia]).max())
