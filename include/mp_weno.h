@@ -38,6 +38,7 @@
 #ifndef MP_WENO_H
 #define MP_WENO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -175,6 +176,28 @@ mp_status mp_weno_init(mp_weno_ctx **ctx, int32_t n_inst,
  * context's stream.  This is the parity entry point. */
 mp_status mp_weno_rhs(mp_weno_ctx *ctx, const double *const *U_in,
                       double *const *dUdt);
+
+/* Allocation-free L(U): for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The operator of mp_weno_rhs for ONE instance, without a
+ * context: inst and opt as for mp_weno_init (use_graph and phase_field are
+ * ignored; inst->U is not read unless U_in is NULL), U_in the device state
+ * (or NULL: inst->U), dUdt a caller-owned device output in the U layout.
+ * Enqueued on hip_stream (a hipStream_t; NULL: the null stream) and
+ * asynchronous; calls no allocating routine, so it may be captured into a
+ * graph.  Its scratch (the instance descriptor and, in 2D and 3D, the
+ * direction accumulator of n_U doubles per cell) is one static device array
+ * per GPU of mp_weno_rhs_noalloc_scratch_bytes() bytes (64 MiB), held until
+ * the process ends: 4096 + 8 n_U cells bytes must fit (2D, N = 2: up to
+ * 1.19 M cells), else MP_ERR_UNSUPPORTED.  Every call on a GPU shares that
+ * array, so calls that overlap on one GPU (two streams, two host threads)
+ * race; calls ordered on one stream do not.  Results equal mp_weno_rhs of a
+ * context holding the same instance with its default tile shapes.
+ * Errors: as mp_weno_init's argument checks; MP_ERR_HIP (launch failure or
+ * no scratch address on this device). */
+mp_status mp_weno_rhs_noalloc(const mp_weno_instance *inst, const mp_weno_opts *opt,
+                              const double *U_in, double *dUdt, void *hip_stream);
+size_t mp_weno_rhs_noalloc_scratch_bytes(void);
 
 /* The Phase-Field fields of Sec. 2.2.1 for every instance, from the volume
  * fractions of U_in (host array of n_inst device pointers; NULL or a NULL

@@ -93,6 +93,9 @@ def lib():
         L.mp_weno_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]
         L.mp_weno_timing.restype = C.c_int
+        L.mp_weno_rhs_noalloc.argtypes = [C.POINTER(Instance), C.POINTER(Opts), vp, vp, vp]
+        L.mp_weno_rhs_noalloc.restype = C.c_int
+        L.mp_weno_rhs_noalloc_scratch_bytes.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -101,7 +104,8 @@ EXPORTED = ["mp_weno_abi_version", "mp_weno_max_phases", "mp_weno_init",
             "mp_weno_rhs", "mp_weno_pf_fields", "mp_weno_autotune", "mp_weno_dt",
             "mp_weno_step", "mp_weno_advance", "mp_weno_diag",
             "mp_weno_set_time", "mp_weno_destroy", "mp_weno_strerror",
-            "mp_weno_last_error", "mp_weno_profile", "mp_weno_timing"]
+            "mp_weno_last_error", "mp_weno_profile", "mp_weno_timing",
+            "mp_weno_rhs_noalloc", "mp_weno_rhs_noalloc_scratch_bytes"]
 
 
 def make_instance(w, U_ptr):
@@ -138,6 +142,18 @@ def make_opts(o, check_bounds=False, use_graph=False):
     x.check_bounds, x.use_graph = int(check_bounds), int(use_graph)
     x.alpha_source = int(getattr(o, "alpha_source", 0))
     return x
+
+
+def rhs_noalloc(w, U, out, stream=None, opts=None):
+    """mp_weno_rhs_noalloc for one inputs.Workload: L(U) of the device state
+    U (torch float64 tensor) into out (same shape), on `stream` (a torch
+    stream; default: the current one).  Returns the status code."""
+    import torch
+    st = stream or torch.cuda.current_stream(U.device)
+    inst = make_instance(w, U.data_ptr())
+    o = make_opts(opts or w.opts)
+    return lib().mp_weno_rhs_noalloc(C.byref(inst), C.byref(o), C.c_void_p(U.data_ptr()),
+                                     C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream))
 
 
 class Solver:

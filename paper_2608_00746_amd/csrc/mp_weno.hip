@@ -32,6 +32,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1944,8 +1945,52 @@ void launch_diag(const Group& G, double* part, hipStream_t s) {
                      n, part + G.part_off);
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free L(U) entry point
+// ---------------------------------------------------------------------------
+// One file-scope array per GPU (the loader places it when the library's code
+// object is loaded on a device; it lives until the process ends).  Layout:
+// the instance descriptor in the first kNoallocDescBytes, then the direction
+// accumulator of the x sweep (n_U doubles per cell, 2D and 3D).  Host code
+// never uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr size_t kNoallocDescBytes = 4096;
+static_assert(sizeof(Desc) <= kNoallocDescBytes, "descriptor slot");
+static __device__ __align__(256) double scratch[kNoallocScratchBytes / sizeof(double)];
+
+// The descriptor arrives by value (a kernel argument), so no host buffer
+// has to outlive the launch, and a graph captured around the call holds no
+// copy node.
+__global__ void k_put_desc(Desc d, Desc* dst) {
+  if (threadIdx.x == 0) *dst = d;
+}
+
+// L(U) of one instance (stage 3: rin -> rout) with the default tile shapes,
+// the descriptor at desc (a group of one: no tile map is read)
+template <int N, int D, typename W>
+void launch_rhs_single(const Desc* desc, const Grid& g, hipStream_t s) {
+  const int64_t nstrip = (g.nx + kXS[0] - 3) / (kXS[0] - 2);
+  hipLaunchKernelGGL((k_sweep_x<N, D, W, 0, kXS[0]>), dim3((unsigned)(nstrip * g.ny * g.nz)),
+                     dim3(kXS[0]), 0, s, desc, nullptr, 1, 3, 0);
+  if constexpr (D >= 2) {
+    constexpr int oy = kYY[0] - 2;
+    const int64_t ntx = (g.nx + kYX[0] - 1) / kYX[0];
+    hipLaunchKernelGGL((k_sweep_t<N, W, 0, kYX[0], kYY[0], D, 1>),
+                       dim3((unsigned)(ntx * ((g.ny + oy - 1) / oy) * g.nz)),
+                       dim3(kYX[0] * kYY[0]), 0, s, desc, nullptr, 1, 3, 0);
+    if constexpr (D == 3)
+      hipLaunchKernelGGL((k_sweep_t<N, W, 0, kYX[0], kYY[0], D, 2>),
+                         dim3((unsigned)(ntx * ((g.nz + oy - 1) / oy) * g.ny)),
+                         dim3(kYX[0] * kYY[0]), 0, s, desc, nullptr, 1, 3, 0);
+  }
+}
+
+using RhsSingleFn = void (*)(const Desc*, const Grid&, hipStream_t);
+
 struct Table {
   StageFn sx[2][kMaxN + 1][4][2][kXVar] = {};   // [PF flux][N][d][precision][shape]
+  RhsSingleFn rhs1[kMaxN + 1][4][2] = {};       // allocation-free L(U): [N][d][precision]
   StageFn sy[2][kMaxN + 1][2][kYVar] = {};      // 2D y sweep
   StageFn sy3[kMaxN3 + 1][2][kYVar] = {};       // 3D y sweep (adds to the accumulator)
   StageFn sz3[kMaxN3 + 1][2][kYVar] = {};       // 3D z sweep (finishes the stage)
@@ -1989,6 +2034,14 @@ void fill_shapes(Table& t) {
 
 template <int N>
 void fill(Table& t) {
+  t.rhs1[N][1][0] = launch_rhs_single<N, 1, double>;
+  t.rhs1[N][1][1] = launch_rhs_single<N, 1, float>;
+  t.rhs1[N][2][0] = launch_rhs_single<N, 2, double>;
+  t.rhs1[N][2][1] = launch_rhs_single<N, 2, float>;
+  if constexpr (N <= kMaxN3) {
+    t.rhs1[N][3][0] = launch_rhs_single<N, 3, double>;
+    t.rhs1[N][3][1] = launch_rhs_single<N, 3, float>;
+  }
   fill_shapes<N, 0>(t);
   fill_shapes<N, 1>(t);
   fill_shapes<N, 2>(t);
@@ -2770,6 +2823,56 @@ mp_status mp_weno_rhs(mp_weno_ctx* c, const double* const* U_in, double* const* 
                         hipMemcpyHostToDevice));
   }
   return enqueue_stage(c, 3);
+}
+
+// Device address of `scratch` per device, taken once per device (with that
+// device current) by the first allocation-free call on it.
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+static hipError_t noalloc_scratch(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+size_t mp_weno_rhs_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+mp_status mp_weno_rhs_noalloc(const mp_weno_instance* inst, const mp_weno_opts* opt,
+                              const double* U_in, double* dUdt, void* hip_stream) {
+  if (!inst || !opt || !dUdt) return MP_ERR_ARG;
+  mp_weno_opts o = *opt;
+  o.use_graph = 0;              // nothing is captured here; the caller may capture
+  o.phase_field = 0;            // L(U) of Eq. (3) only
+  const mp_status v = validate(1, inst, &o, hip_stream);
+  if (v != MP_OK) return v;
+  Desc d;
+  desc_grid_eos(*inst, o, d);
+  const int N = inst->nphase, D = inst->ndim;
+  const size_t nU = (size_t)(2 * N + D + 1);
+  const size_t need = kNoallocDescBytes + (D > 1 ? nU * (size_t)d.g.nc * sizeof(double) : 0);
+  if (need > kNoallocScratchBytes) return MP_ERR_UNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MP_ERR_HIP;
+  void* base = nullptr;
+  if (noalloc_scratch(dev, &base) != hipSuccess) return MP_ERR_HIP;
+  Desc* ddesc = static_cast<Desc*>(base);
+  d.U = inst->U;
+  d.rin = U_in ? U_in : inst->U;
+  d.rout = dUdt;
+  d.acc = D > 1 ? reinterpret_cast<double*>(static_cast<char*>(base) + kNoallocDescBytes)
+                : nullptr;
+  d.vol = 1.0;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, st, d, ddesc);
+  table().rhs1[N][D][o.precision](ddesc, d.g, st);
+  return hipGetLastError() == hipSuccess ? MP_OK : MP_ERR_HIP;
 }
 
 mp_status mp_weno_pf_fields(mp_weno_ctx* c, const double* const* U_in, double* const* divj,
