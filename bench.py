@@ -1,40 +1,38 @@
 """Throughput of the WENO-C hyperbolic step on one MI355X.
 
 A step is one full third-order SSP Runge-Kutta step (CFL time step on the
-device, three RK stages) of every instance.  Default workload: the 2D
-two-phase advection problem, 512 x 512 periodic, air bubble in water (SI),
-FP64, WENO-C + HLLC, CFL 0.5.  Prints one JSON line.
+device, three RK stages) of every instance.  Default workload: 256
+independent shock-bubble instances (grids n x n, n drawn from 64..512, two or
+three phases, 27.2 M cells, seed 0), batched in one context, in the mixed
+FP32/FP64 precision, WENO-C + HLL, CFL 0.2: the largest single-GPU
+configuration of the benchmark set.  The same line reports, on the same
+workload and on the 2048 x 1024 two-phase shock-bubble grid, FP64 and mixed
+throughput side by side with the L1 / Linf difference of the mixed states
+from the FP64 states after the same timed steps.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME]
-                  [--precision fp64|mixed] [--cpu-seconds S]
+                  [--precision fp64|mixed] [--no-compare] [--cpu-seconds S]
 
 Inputs are synthetic and seeded (paper_2608_00746_amd.inputs) and resident in
-HBM before the timed region.  The roofline entry reports the stage kernel
-(x sweep + y sweep, + z sweep in 3D, of one RK stage) against both roofs, the one it is closer
-to first:
-* HBM: algorithmic bytes per launch (8 n_U bytes per cell read of the stage
-  state, 8 n_U per cell read of the step-start state in stages 2 and 3, 8 n_U
-  per cell written) over the average launch time;
-* ALU: FP64 flops per launch (FP32 flops count half) over the average launch
-  time against the FP64 vector peak, with the per-cell flop and VALU
-  instruction counts of the counter table in profiles/ (per cell: every
-  lane of a launch runs one cell's chain).
-The launch time is measured with HIP events the library records on the
-kernel's stream around each stage, in a short eager pass right after the
-timed steps (those replay a captured graph, which cannot carry readable event
-timestamps).  `traffic` is the measured HBM bytes per launch from the same
-table, when it holds a row for this workload, tile choice and kernel source.
-
-`with_phase_field` times the same workload with every step followed by the
-Phase-Field step (the whole path of the method, Eqs. (28), (4) and (5)
-included); `value` is the hyperbolic step alone, the workload as stated.
+HBM before the timed region.  The roofline entry reports the RK stage (the
+sweep kernels of one stage over every instance) against the HBM roof:
+algorithmic bytes per stage (8 n_U bytes per cell read of the stage state,
+8 n_U per cell read of the step-start state in stages 2 and 3, 8 n_U per cell
+written; averaged over the three stages) over the average stage time; the
+ALU roof (FP64 flops per stage, FP32 flops at half weight, from the counter
+table in profiles/) is nested beside it.  The stage time is measured with
+HIP events the library records on its stream around each stage, in a short
+eager pass right after the timed steps (those replay a captured graph, whose
+events cannot be read back).  `traffic` is the measured HBM bytes per stage
+from the counter table, when it holds a row for this workload, tile choice
+and kernel source.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
-import subprocess
+import platform
 import sys
 import time
 
@@ -48,6 +46,8 @@ FP64_PEAK_TFLOPS = 78.6
 # 256 x 4 x 16 lane-ops per clock at 2.4 GHz
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 COUNTER_TABLE = os.path.join(ROOT, "profiles", "stage_counters.md")
+WORKLOADS = ["batched_256", "shock_bubble_2048x1024", "shock_interface_n3_1024",
+             "advection_2d_512", "advection_1d_200", "shock_vessel_bubble_400x200x200"]
 
 
 def kernel_source_hash():
@@ -63,33 +63,28 @@ def kernel_source_hash():
 
 
 def stage_counters(workload, precision, tiles):
-    """Counter figures of one RK stage (x sweep + y sweep) from the table in
-    profiles/ (rocprofv3 --pmc runs of this script):
+    """Counter figures of one RK stage from the table in profiles/ (rocprofv3
+    --pmc runs of this script):
 
     * traffic: HBM bytes per stage (FETCH_SIZE and WRITE_SIZE runs, scaled by
       a reference copy), only from the row of this workload, precision, tile
       choice and kernel source (else None);
     * flops64, flops32, valu: FP64 and FP32 flops and VALU lane-instructions
-      per cell per stage (counted per launched lane: every lane runs one
-      cell's chain), from the row of this tile choice, else the last row of
-      this workload and precision."""
+      per cell per stage, from the row of this tile choice and kernel source,
+      else None."""
     out = {"traffic": None, "flops64": None, "flops32": None, "valu": None}
     if not os.path.exists(COUNTER_TABLE):
         return out
     key = kernel_source_hash()
-    exact = False
     for line in open(COUNTER_TABLE):
         cols = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cols) != 9 or cols[0] in ("workload",) or cols[0].startswith("---"):
             continue
         wl, prec, tl, src, fetch_kib, write_kib, f64, f32, valu = cols
-        if (wl, prec) != (workload, precision):
+        if (wl, prec, src) != (workload, precision, key) or tl != tiles:
             continue
-        if tl == tiles or not exact:
-            out.update(flops64=float(f64), flops32=float(f32), valu=float(valu))
-            exact = exact or tl == tiles
-        if (tl, src) == (tiles, key):
-            out["traffic"] = (float(fetch_kib) + float(write_kib)) * 1024.0
+        out.update(flops64=float(f64), flops32=float(f32), valu=float(valu),
+                   traffic=(float(fetch_kib) + float(write_kib)) * 1024.0)
     return out
 
 
@@ -119,6 +114,16 @@ def workload(name, precision):
     return ws
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(ws, seconds):
     """The oracle as it stands, on the host cores, on a bounded sample: the
     first instance, whole steps until `seconds` have elapsed."""
@@ -127,25 +132,125 @@ def cpu_baseline(ws, seconds):
     o = w.opts
     pb = mpo.Problem(w.ndim, w.n, w.dx, w.bc, list(w.gamma), list(w.pinf), list(w.D),
                      list(w.pmin), list(w.cT), recon=o.recon, flux=o.flux, model=o.model,
-                     energy_limiter=o.energy_limiter, cfl=o.cfl, t_end=0.0)
+                     energy_limiter=o.energy_limiter, cfl=o.cfl, t_end=0.0,
+                     alpha_source=o.alpha_source)
     U = w.U.reshape(-1).copy()
     t0 = time.perf_counter()
     steps = 0
-    eta = o.eta_over_dx * min(w.dx)
     while True:
-        if o.phase_field:
-            U, _ = pb.step_pf(U, pb.dt(U, 0.0), eta)
-        else:
-            U = pb.step(U, pb.dt(U, 0.0))
+        U = pb.step(U, pb.dt(U, 0.0))
         steps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
     return {"value": steps * w.ncells / el, "unit": "cell-updates/s",
-            "cores": mpo.num_threads(), "kind": "oracle",
-            "sample": f"{steps} full RK3 steps{' with the Phase-Field step' if o.phase_field else ''} "
-                      f"of {w.name} ({w.ncells} cells), "
-                      f"{el:.1f} s, OpenMP over grid lines"}
+            "cores": mpo.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": f"{steps} full RK3 steps of instance 0 of {len(ws)} "
+                      f"({w.name}, {w.ncells} cells, FP64), {el:.1f} s, "
+                      f"OpenMP over grid lines"}
+
+
+def tiles_key(args, tiles):
+    if args.tiles:
+        return args.tiles
+    if tiles is None:
+        return "default"
+    return ",".join(sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
+                            for t in tiles.tolist()}))
+
+
+def measure(ws, args, stream, keep_state=False):
+    """One timed run: set-up, autotune, W warm-up steps, capture of the
+    16-step graph, K timed steps (events on the solver stream, bracketed by
+    device synchronisation), then an eager pass with stage events."""
+    import torch
+    from paper_2608_00746_amd.binding import Solver
+    s = Solver(ws, stream=stream, use_graph=not args.no_graph)
+    tiles = None if (args.no_autotune or args.tiles) else s.autotune()
+    s.advance(args.warmup)
+    s.advance(0)                    # capture the 16-step graph outside the timed region
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.advance(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    d = s.diag()
+    if (d[:, 25] > 0).any():
+        raise SystemExit("non-finite state after the timed steps")
+    state = [s.host(i).copy() for i in range(len(ws))] if keep_state else None
+    t_reached = d[:, 26].copy()
+    prof_steps = max(1, min(args.steps, 20))
+    s.profile(3)
+    for _ in range(prof_steps):
+        s.step()
+    k_ms, k_n = s.timing(reset=True)
+    s.profile(0)
+    s.close()
+    cells = sum(w.ncells for w in ws)
+    print("measured %d instance(s), %d cells, precision %d: %.4g cell-updates/s, "
+          "%.4g ms/step, stage %.4g ms" % (len(ws), cells, ws[0].opts.precision,
+                                           cells * args.steps / (ms / 1e3), ms / args.steps,
+                                           k_ms / max(k_n, 1)), file=sys.stderr, flush=True)
+    return {"value": cells * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
+            "wall_s": wall, "stage_ms": k_ms / max(k_n, 1), "stages": k_n,
+            "prof_steps": prof_steps, "tiles": tiles, "state": state, "t": t_reached}
+
+
+def state_difference(ws, a, b):
+    """Relative L1 and Linf of states a against b per kind of component
+    (masses, momenta, energy, volume fractions) over every instance:
+    L1 = sum |a - b| dV / sum |b| dV, Linf = max |a - b| / max |b|."""
+    import numpy as np
+    kinds = ("m", "rho_u", "rho_E", "alpha")
+    num = dict.fromkeys(kinds, 0.0)
+    den = dict.fromkeys(kinds, 0.0)
+    mx = dict.fromkeys(kinds, 0.0)
+    mref = dict.fromkeys(kinds, 0.0)
+    for w, ua, ub in zip(ws, a, b):
+        N, d = w.N, w.ndim
+        ua = ua.reshape(w.nU, -1)
+        ub = ub.reshape(w.nU, -1)
+        vol = float(np.prod(w.dx))
+        sl = {"m": slice(0, N), "rho_u": slice(N, N + d), "rho_E": slice(N + d, N + d + 1),
+              "alpha": slice(N + d + 1, 2 * N + d + 1)}
+        for k in kinds:
+            diff = np.abs(ua[sl[k]] - ub[sl[k]])
+            num[k] += diff.sum() * vol
+            den[k] += np.abs(ub[sl[k]]).sum() * vol
+            mx[k] = max(mx[k], float(diff.max()))
+            mref[k] = max(mref[k], float(np.abs(ub[sl[k]]).max()))
+    return {"L1_rel": {k: num[k] / den[k] for k in kinds},
+            "Linf_rel": {k: mx[k] / mref[k] for k in kinds}}
+
+
+def precision_pair(name, args, stream):
+    """FP64 and mixed runs of one workload from the same initial state, and
+    the difference of the mixed states from the FP64 states after the same
+    K timed steps (each run with its own CFL steps).  Returns the summary and
+    the two runs."""
+    import numpy as np
+    out = {}
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        ws = workload(name, prec)
+        r = measure(ws, args, stream, keep_state=True)
+        runs[prec] = (ws, r)
+        out[prec] = {"value": r["value"], "unit": "cell-updates/s",
+                     "ms_per_step": r["ms_per_step"], "stage_ms": r["stage_ms"]}
+    ws, rf = runs["fp64"]
+    _, rm = runs["mixed"]
+    out["mixed_vs_fp64"] = dict(
+        steps=args.steps, **state_difference(ws, rm["state"], rf["state"]),
+        time_rel=float(np.abs(rm["t"] - rf["t"]).max() / np.abs(rf["t"]).max()))
+    out["speedup_mixed"] = out["mixed"]["value"] / out["fp64"]["value"]
+    for _, r in runs.values():
+        r["state"] = None
+    return out, runs
 
 
 def pf_rate(name, precision, stream, steps):
@@ -174,9 +279,8 @@ def pf_rate(name, precision, stream, steps):
     ms = e0.elapsed_time(e1)
     its = float(s.diag()[:, 29].max())
     s.close()
-    return {"value": cells * steps / (ms / 1e3), "unit": "cell-updates/s",
-            "ms_per_step": ms / steps, "steps": steps,
-            "cg_iterations_last_step": its}
+    return {"workload": name, "value": cells * steps / (ms / 1e3), "unit": "cell-updates/s",
+            "ms_per_step": ms / steps, "steps": steps, "cg_iterations_last_step": its}
 
 
 def main():
@@ -184,13 +288,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="advection_2d_512",
-                    choices=["advection_2d_512", "shock_bubble_2048x1024",
-                             "shock_interface_n3_1024", "advection_1d_200", "batched_256",
-                             "shock_vessel_bubble_400x200x200"])
+    ap.add_argument("--workload", default="batched_256", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP64 / mixed comparison runs (profiling runs)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shapes (no mp_weno_autotune at set-up)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -199,20 +302,16 @@ def main():
     ap.add_argument("--tiles", default=None,
                     help="fixed tile shapes instead of the autotuner, as "
                          "x<lanes>/y<X>x<Y>/<plain|xcd> (the form the bench line reports)")
-    ap.add_argument("--phase-field", action="store_true",
-                    help="end every step with the Phase-Field step (reported separately)")
     ap.add_argument("--pf-steps", type=int, default=10,
-                    help="after the main line's measurement, time this many steps of the "
-                         "same workload with the Phase-Field step on (0: skip)")
+                    help="time this many steps of the 2048 x 1024 shock-bubble with the "
+                         "Phase-Field step on (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see the design notes on sharding)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2608_00746_amd.binding import Solver
 
     if args.tiles is not None:
         # shapes by index into the library's candidate lists
@@ -221,19 +320,12 @@ def main():
         os.environ["MPWENO_XSHAPE"] = str([256, 128, 64].index(int(xs[1:])))
         os.environ["MPWENO_YSHAPE"] = str([(16, 16), (32, 8), (16, 24), (0, 0)].index((yx, yy)) % 3)
         os.environ["MPWENO_XCD_SWIZZLE"] = {"plain": "0", "xcd": "1"}[sw]
-    ws = workload(args.workload, args.precision)
     from paper_2608_00746_amd import inputs as I
-    if args.phase_field:
-        for w in ws:
-            w.opts.phase_field = 1
+    ws = workload(args.workload, args.precision)
     precision = "mixed" if ws[0].opts.precision == I.PREC_MIXED else "fp64"
     stream = torch.cuda.Stream()
-    s = Solver(ws, stream=stream, use_graph=not args.no_graph)
     cells = sum(w.ncells for w in ws)
-    tiles = None if (args.no_autotune or args.tiles) else s.autotune()
 
-    s.advance(args.warmup)
-    torch.cuda.synchronize()
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -242,82 +334,46 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # timed region: K whole steps (mp_weno_advance: runs of 16 steps replay one
-    # captured graph) bracketed by synchronisation and by events on the
-    # solver's stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    s.advance(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-
-    # the stage kernels (x sweep + y (+ z) sweep of one RK stage) timed by HIP event
-    # pairs the library records on its stream around each stage; a graph
-    # cannot carry readable event timestamps, so these steps are launched
-    # eagerly right after the timed region, from the state it left
-    prof_steps = max(1, min(args.steps, 20))
-    s.profile(3)
-    for _ in range(prof_steps):
-        s.step()
-    k_ms, k_n = s.timing(reset=True)
-    s.profile(0)
-
-    # sanity: the state stayed finite and admissible
-    d = s.diag()
-    cg_its = float(d[:, 29].max())
-    if (d[:, 25] > 0).any():
-        raise SystemExit("non-finite state after the timed steps")
-
-    ms_step = ms / args.steps
-    value = cells * args.steps / (ms / 1e3)
-    bytes_launch = sum(8 * w.nU * w.ncells for w in ws) * (2 + 3 + 3) / 3.0
-    avg_launch_s = (k_ms / 1e3) / max(k_n, 1)
-    achieved = bytes_launch / avg_launch_s / 1e9
-    tiles_key = args.tiles if args.tiles else "default" if tiles is None else ",".join(
-        sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
-                for t in tiles.tolist()}))
-    ctr = stage_counters(args.workload, precision, tiles_key)
-    hbm = {
-        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": ctr["traffic"],
-        "bytes_per_launch": bytes_launch,
-    }
-    roof = hbm
-    if ctr["flops64"] is not None:
-        # FP64-equivalent flops: an FP32 flop takes half an FP64 slot
-        flops = (ctr["flops64"] + 0.5 * ctr["flops32"]) * cells
-        tf = flops / avg_launch_s / 1e12
-        alu = {
-            "bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS, "traffic": ctr["traffic"],
-            "flops_per_launch": flops,
-            "valu_issue_frac": ctr["valu"] * cells / avg_launch_s / VALU_LANE_OPS_PEAK,
-        }
-        # the roof the stage is closer to binds it
-        if alu["frac"] > hbm["frac"]:
-            roof = dict(alu, hbm=hbm)
-        else:
-            roof = dict(hbm, alu=alu)
-    roof.update({
-        "kernel": "RK stage (x sweep + transverse sweeps)",
-        "avg_launch_ms": avg_launch_s * 1e3, "launches": k_n,
+    comparison = {}
+    if args.no_compare:
+        r = measure(ws, args, stream)
+    else:
+        # the headline run is the pair's run of its precision
+        summary, runs = precision_pair(args.workload, args, stream)
+        comparison[args.workload] = summary
+        ws, r = runs[precision]
+    tk = tiles_key(args, r["tiles"])
+    bytes_stage = sum(8 * w.nU * w.ncells for w in ws) * (2 + 3 + 3) / 3.0
+    stage_s = r["stage_ms"] / 1e3
+    achieved = bytes_stage / stage_s / 1e9
+    ctr = stage_counters(args.workload, precision, tk)
+    roof = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": ctr["traffic"],
+        "kernel": "RK stage: the sweep kernels of one stage over every instance",
+        "bytes_per_launch": bytes_stage, "avg_launch_ms": r["stage_ms"],
+        "launches": r["stages"],
         "timing": "HIP events around each RK stage on the solver stream, "
-                  "%d eager steps after the timed region" % prof_steps,
-    })
+                  "%d eager steps after the timed region" % r["prof_steps"],
+    }
+    if ctr["flops64"] is not None:
+        flops = (ctr["flops64"] + 0.5 * ctr["flops32"]) * cells
+        tf = flops / stage_s / 1e12
+        roof["alu"] = {
+            "bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP64_PEAK_TFLOPS, "flops_per_launch": flops,
+            "valu_issue_frac": ctr["valu"] * cells / stage_s / VALU_LANE_OPS_PEAK,
+        }
     w0 = ws[0]
     out = {
         "metric": "cell-updates/s",
-        "value": value,
+        "value": r["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -329,24 +385,24 @@ def main():
             "nphase": w0.N if len(ws) == 1 else sorted({w.N for w in ws}),
             "instances": len(ws), "cells": cells,
             "precision": precision,
-            "recon": ["WENO-C", "WENO-CL"][w0.opts.recon],
+            "recon": ["WENO-C", "WENO-CL", "WENO-JS", "WENO-W"][w0.opts.recon],
             "flux": ["HLLC", "HLL"][w0.opts.flux],
-            "cfl": w0.opts.cfl, "graph": not args.no_graph and not args.phase_field,
-            "phase_field": bool(args.phase_field),
-            "tiles": [args.tiles] if args.tiles else "default" if tiles is None else
-                     sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
-                             for t in tiles.tolist()}),
+            "cfl": w0.opts.cfl, "graph": not args.no_graph,
+            "tiles": tk,
         },
         "roofline": roof,
-        "wall_s": wall,
+        "wall_s": r["wall_s"],
     }
     if len(ws) > 1:
-        out["instances_per_s"] = len(ws) * args.steps / (ms / 1e3)
-    if args.phase_field:
-        out["pf_cg_iterations_last_step"] = cg_its
-    s.close()
-    if args.pf_steps > 0 and not args.phase_field:
-        out["with_phase_field"] = pf_rate(args.workload, args.precision, stream, args.pf_steps)
+        out["instances_per_s"] = len(ws) * args.steps / (r["ms_per_step"] * args.steps / 1e3)
+    if not args.no_compare:
+        if args.workload != "shock_bubble_2048x1024":
+            comparison["shock_bubble_2048x1024"] = precision_pair(
+                "shock_bubble_2048x1024", args, stream)[0]
+        out["precision_comparison"] = comparison
+    if args.pf_steps > 0:
+        out["with_phase_field"] = pf_rate("shock_bubble_2048x1024", "fp64", stream,
+                                          args.pf_steps)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(ws, args.cpu_seconds)
     print(json.dumps(out), flush=True)

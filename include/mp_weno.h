@@ -267,7 +267,9 @@ mp_status mp_weno_step(mp_weno_ctx *ctx, const double *dt_dev);
  * which need the host between steps) runs of 16 steps are captured once as
  * one graph and replayed, so consecutive steps follow each other without a
  * graph launch between them.  Asynchronous; results identical to nsteps
- * single steps. */
+ * single steps.  nsteps = 0 only captures that graph (if use_graph applies
+ * and it is not captured yet) and advances nothing, so a timed run that
+ * follows does not include the capture. */
 mp_status mp_weno_advance(mp_weno_ctx *ctx, int32_t nsteps);
 
 /* Diagnostics per instance, MP_DIAG_LEN doubles each (out[i*MP_DIAG_LEN+k]):

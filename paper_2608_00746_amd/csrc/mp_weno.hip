@@ -3038,7 +3038,7 @@ mp_status mp_weno_advance(mp_weno_ctx* c, int32_t nsteps) {
     return MP_OK;
   }
   int32_t left = nsteps;
-  if (left >= mp_weno_ctx::kChain) {
+  if (left >= mp_weno_ctx::kChain || nsteps == 0) {
     if (!c->chain) {
       hipGraph_t gph;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));

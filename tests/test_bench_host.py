@@ -1,5 +1,6 @@
 """Host logic of bench.py (no GPU): the counter-table lookup behind
-roofline.traffic and the ALU roofline, and the one-GPU guard."""
+roofline.traffic and the ALU roofline, the state-difference metric of the
+precision comparison, and the one-GPU guard."""
 import os
 import subprocess
 import sys
@@ -29,12 +30,12 @@ def test_stage_counters_lookup(tmp_path, monkeypatch):
     c = bench.stage_counters("wl", "fp64", "x64/y16x16/plain")
     assert c["traffic"] == (100 + 28) * 1024.0
     assert (c["flops64"], c["flops32"], c["valu"]) == (1900.0, 10.0, 2000.0)
-    # a row of other sources: its flops may serve, its traffic never
+    # a row of other sources: nothing from it (the counters describe that code)
     c = bench.stage_counters("wl", "fp64", "x128/y16x16/xcd")
-    assert c["traffic"] is None and c["flops64"] == 1800.0
-    # no row for the tiles: the workload's flops, no traffic
+    assert c == {"traffic": None, "flops64": None, "flops32": None, "valu": None}
+    # no row for the tiles: nothing
     c = bench.stage_counters("wl", "fp64", "x256/y16x24/plain")
-    assert c["traffic"] is None and c["flops64"] is not None
+    assert c["traffic"] is None and c["flops64"] is None
     # unknown workload or precision: nothing
     c = bench.stage_counters("other", "fp64", "x64/y16x16/plain")
     assert c == {"traffic": None, "flops64": None, "flops32": None, "valu": None}
@@ -59,3 +60,25 @@ def test_more_than_one_gpu_refused(n):
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_state_difference_metric():
+    """L1 and Linf per kind of component over uneven instances."""
+    import numpy as np
+    from paper_2608_00746_amd import inputs as I
+    ws = [I.random_state((12, 10), nphase=2, seed=1), I.random_state((9, 7), nphase=3, seed=2)]
+    a = [w.U.copy() for w in ws]
+    b = [w.U.copy() for w in ws]
+    d = bench.state_difference(ws, a, b)
+    assert all(v == 0.0 for v in d["L1_rel"].values())
+    # perturb the energy of one cell of the second instance by 1e-9 of it
+    w = ws[1]
+    a[1].reshape(w.nU, -1)[w.N + w.ndim, 5] *= 1 + 1e-9
+    d = bench.state_difference(ws, a, b)
+    assert d["L1_rel"]["m"] == 0.0 and d["L1_rel"]["alpha"] == 0.0
+    E = [x.reshape(v.nU, -1)[v.N + v.ndim] for x, v in zip(b, ws)]
+    vol = [float(np.prod(v.dx)) for v in ws]
+    ref = 1e-9 * abs(E[1][5]) * vol[1] / sum(np.abs(e).sum() * v for e, v in zip(E, vol))
+    assert abs(d["L1_rel"]["rho_E"] - ref) <= 1e-6 * ref
+    assert abs(d["Linf_rel"]["rho_E"] - 1e-9 * abs(E[1][5]) / max(np.abs(e).max() for e in E)) \
+        <= 1e-6 * d["Linf_rel"]["rho_E"]
