@@ -130,10 +130,11 @@ typedef struct {
                               + 64 eps || |[div J]| + |K| |Q| || (the second
                               term: the rounding floor of res itself), or
                               once a restart no longer halves it while it is
-                              <= 1000 cg_rtol ||[div J]|| (stagnation at the
-                              attainable accuracy; a run whose recurrence sits
-                              within 1000 cg_rtol without halving for 50
-                              iterations ends for that check); <= 0: 1e-12   */
+                              <= 1e4 cg_rtol ||[div J]|| (stagnation at the
+                              attainable accuracy of the FP32-preconditioned
+                              flexible CG; a run whose recurrence sits within
+                              1e4 cg_rtol without halving for 50 iterations
+                              ends for that check); <= 0: 1e-12             */
   int32_t cg_maxit;        /* iteration limit of that solve (<= 0: 10000)    */
   int32_t check_bounds;    /* 1: mp_weno_step checks the result of each step
                               (not the intermediate RK stages; see below)  */

@@ -86,8 +86,12 @@ constexpr int kPfsM = 0, kPfsMe2 = 1, kPfsB = 2, kPfsIts = 10, kPfsRes = 11,
               kPfsBest = 80, kPfsBestIt = 88;
 // a run whose recurrence residual is within kPfsStallTol cg_rtol and has not
 // halved for kPfsStallIts iterations has stagnated at the attainable accuracy:
-// it ends, and the next start pass judges the true residual
-constexpr double kPfsStallTol = 1000.0;
+// it ends, and the next start pass judges the true residual.  With the FP32
+// preconditioner the attainable relative residual sits near 1e-9 on
+// high-contrast states (the Sec. 4.2.1 cavity with the Kapila model stalls at
+// 1.0e-9 .. 1.5e-9 over 16 restarts); the Phase-Field flux it sets moves by
+// that fraction of itself
+constexpr double kPfsStallTol = 1e4;
 constexpr double kPfsStallIts = 50.0;
 
 // The state pointers come from a table in device memory, so the compiler
@@ -1152,11 +1156,16 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_start(const Desc* __restric
 //   alpha:  alpha = r.z / p.q
 //   axpy:   Q += alpha p, r -= alpha q
 //   (V-cycle: z = M^-1 r)
-//   dots:   partials [p] r.z, [N + p] r.r, [2N + p] sum z, [3N + p] sum r
+//   dots:   partials [p] r.z, [N + p] r.r, [2N + p] sum z, [3N + p] sum r,
+//           [4N + p] z.q, [5N + p] sum q (q = K p of this iteration)
 //   beta:   done once the recurrence's ||r|| <= rtol ||b|| (then checked
-//           against the true residual by the start pass); else
-//           beta = r.z' / (r.z')_prev with z' = z - mean z, i.e.
-//           r.z' = r.z - mean z sum r
+//           against the true residual by the start pass); else the flexible
+//           (Polak-Ribiere) beta = z'.(r - r_prev) / (r.z')_prev
+//           = -alpha z'.q / (r.z')_prev with z' = z - mean z (so
+//           r.z' = r.z - mean z sum r, z'.q = z.q - mean z sum q): equal to
+//           r.z' / (r.z')_prev for a fixed symmetric preconditioner, and it
+//           keeps the directions conjugate when the FP32 V-cycle is not
+//           exactly one (plain PCG then stalls near 1e-9)
 // The directions alternate between two buffers (p at neighbours is read
 // while the new one is written).  K is singular (its null space: the
 // constants; faces at outflow ends carry no flux) and the V-cycle's output
@@ -1298,26 +1307,28 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dots(const Desc* __restrict
   if (!any) return;
   const int64_t c0 = (int64_t)it.y * d.chunk;
   const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
-  double acc[4 * N];
+  double acc[6 * N];
 #pragma unroll
-  for (int k = 0; k < 4 * N; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 6 * N; ++k) acc[k] = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       if (!live[p]) continue;
       const int64_t ip = (int64_t)p * nc + i;
-      const double r = gptr(d.pf_r)[ip], z = gptr(d.pf_u)[ip];
+      const double r = gptr(d.pf_r)[ip], z = gptr(d.pf_u)[ip], q = gptr(d.pf_ap)[ip];
       acc[p] += r * z;
       acc[N + p] += r * r;
       acc[2 * N + p] += z;
       acc[3 * N + p] += r;
+      acc[4 * N + p] += z * q;
+      acc[5 * N + p] += q;
     }
   }
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     if (!live[p]) continue;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 6; ++k) {
       const double r = block_reduce(acc[k * N + p], sh, 0);
       if (threadIdx.x == 0) part[(int64_t)(k * N + p) * d.ps + blockIdx.x] = r;
     }
@@ -1332,14 +1343,15 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict
   __shared__ double sh[kRedBlock];
   const Desc& d = descs[blockIdx.x];
   gdouble* s = gptr(d.pfs);
-  double v[4 * N];
-  reduce_chunks_n<4 * N>(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], v, sh);
+  double v[6 * N];
+  reduce_chunks_n<6 * N>(part, d.ps, start[blockIdx.x], start[blockIdx.x + 1], v, sh);
   if (threadIdx.x != 0) return;
   double rmax = 0.0;
   bool stepped = false, adv = false;
   for (int p = 0; p < N; ++p) {
     if (s[kPfsDone + p] != 0.0) continue;
     const double rz0 = v[p], rr = v[N + p], zs = v[2 * N + p], rs = v[3 * N + p];
+    const double zq = v[4 * N + p], qs = v[5 * N + p];
     const double zb = zs / (double)d.g.nc;
     const double rz = rz0 - zb * rs;
     stepped = true;
@@ -1360,7 +1372,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict
         s[kPfsDone + p] = 1.0;                 // breakdown: restart
         s[kPfsCorr] = 1.0;
       } else {
-        s[kPfsBeta + p] = k > 0.0 ? rz / s[kPfsRZ + p] : 0.0;
+        s[kPfsBeta + p] = k > 0.0 ? -s[kPfsAlpha + p] * (zq - zb * qs) / s[kPfsRZ + p] : 0.0;
         s[kPfsRZ + p] = rz;
         s[kPfsUbar + p] = zb;
         s[kPfsPits + p] = k + 1.0;

@@ -534,6 +534,38 @@ def paper_four_phase_miscible(n=100, opts=None):
                     opts=opts or Options(recon=RECON_WENO_CL), dt_fixed=1e-3)
 
 
+CAVITY_AIR = (1.4, 0.0, 0.0)              # Sec. 4.2.1, nondimensional
+CAVITY_WATER = (4.4, 6000.0, 0.0)
+
+
+def cavity_collapse(nx=1600, ny=800, opts=None, t_end=0.02):
+    """Sec. 4.2.1 (Eq. (32)): shock-induced collapse of an air cavity in
+    water on [0, 10] x [-2.5, 2.5], outflow: air (phase 1, gamma 1.4,
+    rho 1e-3) inside the circle of radius 1 about (4.375, 0), water (phase 2,
+    gamma 4.4, Pinf 6000, rho 1, P = 1) elsewhere, and the post-shock water
+    state (rho 1.325, u 68.52, P = 1.915e4) left of x_S = 1.  The sharp
+    regions of Eq. (32) enter as cell averages (4 x 4 Gauss points per cell,
+    so interface cells hold the area fraction).  HLL, CFL 0.2 (Sec. 4.2)."""
+    g, pi, D = _eos([CAVITY_AIR, CAVITY_WATER])
+    box = ((0.0, 10.0), (-2.5, 2.5))
+    dx, dy = 10.0 / nx, 5.0 / ny
+    a1 = cell_average_2d(lambda X, Y: (np.hypot(X - 4.375, Y) <= 1.0).astype(np.float64),
+                         nx, ny, box)
+    post = cell_average_2d(lambda X, Y: (X < 1.0).astype(np.float64), nx, ny, box)
+    a1 = np.clip(a1, 0.0, 1.0)
+    alpha = np.stack([a1, 1.0 - a1])
+    rho2 = 1.0 + post * (1.325 - 1.0)
+    m = np.stack([1.0e-3 * alpha[0], rho2 * alpha[1]])
+    u = np.zeros((2, ny, nx))
+    u[0] = post * 68.52
+    P = 1.0 + post * (1.915e4 - 1.0)
+    U = conserved(alpha, m, u, P, g, pi, D)
+    return Workload("cavity_%dx%d" % (nx, ny), 2, (nx, ny), (dx, dy),
+                    ((BC_OUTFLOW,) * 2,) * 2, g, pi, D, default_pmin(pi, 1.0),
+                    np.zeros(2), _to4d(U, 2), t_end=t_end,
+                    opts=opts or Options(flux=FLUX_HLL, cfl=0.2))
+
+
 def air_helium_shock_tube(dx=0.01, opts=None):
     """Sec. 4.1.5 (Eq. (31)): [0,2], helium (phase 1, gamma 1.6) and air
     (phase 2, gamma 1.4); left (0,1]: pure air, P = 1; right: pure helium,

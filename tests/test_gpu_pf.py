@@ -228,7 +228,7 @@ def test_pf_long_run_converges():
     Phase-Field step.  Around step 250 a solve sits at its attainable
     accuracy (true residual ~1e-11) and its restarts break down at their
     first iteration; such a restart must count as stagnation (the residual
-    did not halve and is within 1000 cg_rtol), not run the solve out of
+    did not halve and is within 1e4 cg_rtol), not run the solve out of
     restarts (MP_ERR_SOLVER, as it once did)."""
     import torch
     w = I.shock_bubble_2d(2048, 1024)
@@ -238,7 +238,7 @@ def test_pf_long_run_converges():
     for _ in range(6):
         s.advance(50)
         d = s.diag()[0]
-        assert d[25] == 0 and d[30] <= 1000 * 1e-12, d[30]
+        assert d[25] == 0 and d[30] <= 1e4 * 1e-12, d[30]
     assert d[27] == 300
     assert d[20] <= 16 * 2 * EPS * np.sqrt(300)
     assert d[21] >= -8 * EPS and d[22] >= -8 * EPS and d[23] <= 1 + 8 * EPS
@@ -248,7 +248,7 @@ def test_pf_long_run_converges():
 def test_pf_batched_long_run_converges():
     """Regression: 60 steps of the 256-instance batch with the Phase-Field
     step.  Around step 50 one instance's CG recurrence stagnates at ~2e-11
-    (within 1000 cg_rtol, not below cg_rtol); such a run must end and let the
+    (within 1e4 cg_rtol, not below cg_rtol); such a run must end and let the
     start pass judge the true residual, not iterate to cg_maxit
     (MP_ERR_SOLVER after 10000 iterations, as it once did)."""
     import torch
@@ -260,7 +260,7 @@ def test_pf_batched_long_run_converges():
     for _ in range(4):
         s.advance(15)
         d = s.diag()
-        assert (d[:, 25] == 0).all() and (d[:, 30] <= 1000 * 1e-12).all(), d[:, 30].max()
+        assert (d[:, 25] == 0).all() and (d[:, 30] <= 1e4 * 1e-12).all(), d[:, 30].max()
     assert (d[:, 27] == 60).all()
     tau = 8 * EPS
     assert (d[:, 21] >= -tau).all() and (d[:, 22] >= -tau).all() and (d[:, 23] <= 1 + tau).all()
