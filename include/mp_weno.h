@@ -178,6 +178,41 @@ mp_status mp_weno_init(mp_weno_ctx **ctx, int32_t n_inst,
 mp_status mp_weno_rhs(mp_weno_ctx *ctx, const double *const *U_in,
                       double *const *dUdt);
 
+/* Two-level coupling of a context's instances (block-structured refinement,
+ * Sec. 3.4.2: the scheme runs unchanged on each uniform level).  Link k
+ * makes instance `fine` the refinement by 2 of the W x H coarse cells
+ * [lo[0], lo[0] + W) x [lo[1], lo[1] + H) of instance `coarse` (1D: W cells
+ * from lo[0]).  The fine instance's grid is that block refined, 2W x 2H
+ * cells, surrounded by a ring of 3 ghost cells: n = (2W + 6, 2H + 6), dx
+ * half the coarse dx; its ring is overwritten by the coupling (its boundary
+ * codes do not matter) and is not part of the solution.  From then on each
+ * mp_weno_step / mp_weno_advance of the context, per RK stage, fills the
+ * ring from the coarse stage state (each ghost cell takes its coarse
+ * parent's average) and evaluates the interface fluxes of both levels;
+ * after the step the coarse cells under the block take the mean of their
+ * four children, the ring takes the new coarse values, and the coarse
+ * cells beside the block are corrected by the difference of the fine and
+ * coarse interface fluxes (RK3-weighted), with
+ * the alpha source on the same face velocities: m_p, rho u and rho E are
+ * conserved over the composite grid (coarse cells outside the blocks plus
+ * fine cells inside) to rounding.  Linked instances share the smallest of
+ * their CFL steps (an external dt must be equal for them).  Requirements:
+ * same N and d (1 or 2) for every link, the block at least 3 coarse cells
+ * from every coarse boundary, blocks of one coarse instance at least 6
+ * coarse cells apart, an instance refining at most one block; no
+ * Phase-Field step.  n_links = 0 removes the coupling.  mp_weno_rhs stays
+ * per instance.  Synchronises the stream; drops captured step graphs.
+ * Errors: MP_ERR_ARG (geometry), MP_ERR_UNSUPPORTED (3D, phase_field,
+ * links of several (N, d)), MP_ERR_OOM. */
+typedef struct {
+  int32_t fine;            /* index of the refined instance                  */
+  int32_t coarse;          /* index of the coarse instance                   */
+  int32_t lo[3];           /* first coarse cell of the block per direction   */
+} mp_weno_link;
+
+mp_status mp_weno_amr_link(mp_weno_ctx *ctx, int32_t n_links,
+                           const mp_weno_link *links);
+
 /* Allocation-free L(U): for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  The operator of mp_weno_rhs for ONE instance, without a
@@ -240,7 +275,8 @@ mp_status mp_weno_autotune(mp_weno_ctx *ctx, int32_t reps, int32_t *choice);
 
 /* CFL time step per instance: dt = cfl / max_cells sum_d (|u_d| + c)/dx_d,
  * clipped so that t + dt <= t_end (t is the instance's time, advanced by
- * mp_weno_step).  where = MP_WHERE_DEVICE: dt is a device array of n_inst
+ * mp_weno_step); instances coupled by mp_weno_amr_link get the smallest of
+ * their steps.  where = MP_WHERE_DEVICE: dt is a device array of n_inst
  * doubles (asynchronous); MP_WHERE_HOST: a host array (synchronises the
  * stream). */
 mp_status mp_weno_dt(mp_weno_ctx *ctx, double *dt, int32_t where);

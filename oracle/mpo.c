@@ -694,6 +694,10 @@ static double one_plus_K(const mpo_problem *pb, const double *U, int p) {
   return rho * c * c / k;
 }
 
+double mpo_one_plus_K(const mpo_problem *pb, const double *U, int p) {
+  return one_plus_K(pb, U, p);
+}
+
 /* L(U) of Eq. (3): for each direction (dimension by dimension, all from the
  * same Ubar), reconstruct cells -1..n of every line, take the flux at faces
  * -1/2..n-1/2 from (U^L of cell i, U^R of cell i+1) and add

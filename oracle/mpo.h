@@ -86,6 +86,9 @@ void mpo_weno5_ideal(double dL[3], double dR[3]);
 /* Interior value f^C of a cell from its average and face values, Eq. (6)
  * inverted with the four-point Gauss-Lobatto weights (end weights 1/12). */
 double mpo_gl_interior(double fbar, double fL, double fR);
+/* (1 + K_p) of the alpha source of Eq. (1) at the conserved cell state U:
+ * 1 for the Allaire model, rho c^2 / (rho_p c_p^2) for the Kapila model. */
+double mpo_one_plus_K(const mpo_problem *pb, const double *U, int p);
 /* WENO-W weights, Sec. 3.3, Eq. (15). */
 void mpo_wenow_weights(const double beta[3], const double d[3], double w[3]);
 /* WENO-JS weights (Eq. (12) generalised to three stencils); comparator only. */

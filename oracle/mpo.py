@@ -99,6 +99,8 @@ def lib():
         L.mpo_pf_flux.argtypes = [pp, C.c_int, dp, dp, dp, dp, dp]
         L.mpo_pf_rhs.argtypes = [pp, dp, dp, dp, dp]
         L.mpo_pf_rk3.argtypes = [pp, dp, dp, dp, C.c_double]
+        L.mpo_one_plus_K.argtypes = [pp, dp, C.c_int]
+        L.mpo_one_plus_K.restype = C.c_double
         L.mpo_num_threads.restype = C.c_int
         L.mpo_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -356,6 +358,9 @@ class Problem:
         a = _arr(alpha, self.N)
         mm = _arr(m, self.N)
         return lib().mpo_sound_speed(self.ref(), _ptr(a), _ptr(mm), float(P))
+
+    def one_plus_K(self, Ucell, p):
+        return lib().mpo_one_plus_K(self.ref(), _ptr(_arr(Ucell, self.nU)), int(p))
 
     def psi(self, Ucell):
         U = _arr(Ucell, self.nU)

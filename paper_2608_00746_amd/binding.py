@@ -38,6 +38,10 @@ class Instance(C.Structure):
     ]
 
 
+class Link(C.Structure):
+    _fields_ = [("fine", C.c_int32), ("coarse", C.c_int32), ("lo", C.c_int32 * 3)]
+
+
 class Opts(C.Structure):
     _fields_ = [
         ("recon", C.c_int32), ("flux", C.c_int32), ("model", C.c_int32),
@@ -93,6 +97,8 @@ def lib():
         L.mp_weno_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]
         L.mp_weno_timing.restype = C.c_int
+        L.mp_weno_amr_link.argtypes = [vp, C.c_int32, C.POINTER(Link)]
+        L.mp_weno_amr_link.restype = C.c_int
         L.mp_weno_rhs_noalloc.argtypes = [C.POINTER(Instance), C.POINTER(Opts), vp, vp, vp]
         L.mp_weno_rhs_noalloc.restype = C.c_int
         L.mp_weno_rhs_noalloc_scratch_bytes.restype = C.c_size_t
@@ -105,7 +111,7 @@ EXPORTED = ["mp_weno_abi_version", "mp_weno_max_phases", "mp_weno_init",
             "mp_weno_step", "mp_weno_advance", "mp_weno_diag",
             "mp_weno_set_time", "mp_weno_destroy", "mp_weno_strerror",
             "mp_weno_last_error", "mp_weno_profile", "mp_weno_timing",
-            "mp_weno_rhs_noalloc", "mp_weno_rhs_noalloc_scratch_bytes"]
+            "mp_weno_rhs_noalloc", "mp_weno_rhs_noalloc_scratch_bytes", "mp_weno_amr_link"]
 
 
 def make_instance(w, U_ptr):
@@ -250,6 +256,16 @@ class Solver:
         self._check(lib().mp_weno_autotune(self.ctx, int(reps), out))
         self._leave()
         return np.array(list(out), dtype=np.int64).reshape(len(self.U), 4)
+
+    def amr_link(self, links):
+        """Couple instances: links = [(fine, coarse, (lo_x[, lo_y])), ...]
+        (mp_weno_amr_link); [] removes the coupling."""
+        arr = (Link * max(len(links), 1))()
+        for k, (f, c, lo) in enumerate(links):
+            arr[k].fine, arr[k].coarse = int(f), int(c)
+            for d, v in enumerate(lo):
+                arr[k].lo[d] = int(v)
+        self._check(lib().mp_weno_amr_link(self.ctx, len(links), arr))
 
     def dt(self):
         out = np.zeros(len(self.U))

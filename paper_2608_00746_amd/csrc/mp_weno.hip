@@ -613,6 +613,240 @@ void k_sweep_t(const Desc* __restrict__ descs,
 }
 
 // ---------------------------------------------------------------------------
+// two-level coupling of batched instances (block-structured refinement)
+// ---------------------------------------------------------------------------
+// A fine instance covers a W x H block of cells of a coarse instance at
+// refinement ratio 2 (Sec. 3.4.2: each level is a uniform grid the scheme
+// runs on unchanged).  Its grid is the 2W x 2H refined block plus a ring of
+// three ghost cells (the stencil reach), (2W + 6) x (2H + 6) cells.  Both
+// levels take the same time step.  Per RK stage the ring is filled from the
+// coarse stage state (each fine ghost cell takes its coarse parent's
+// average: bounds, consistency m_p = rho_p alpha_p and uniform u, P carry
+// over exactly), and the interface fluxes of both levels are evaluated from
+// the stage states; after the step the coarse cells under the block take the
+// average of their four children, the ring takes the new coarse values, and
+// the coarse cells beside the block get
+// the difference between the fine and coarse interface fluxes (the RK3
+// weights 1/6, 1/6, 2/3 of the three stages) so that the composite grid
+// conserves m_p, rho u and rho E exactly; the alpha source of those cells is
+// corrected with the same face velocities so that sum_p alpha_p stays 1.
+constexpr int kAmrHalo = 3;
+
+struct AmrLink {
+  double* fst[3];            // fine stage states U, U1, U2 (input of stage s)
+  double* cst[3];            // coarse stage states
+  Grid fg, cg;               // the two grids (scheme switches included)
+  Eos e;
+  int lox, loy, W, H;        // the block: coarse cells [lox, lox + W) x [loy, loy + H)
+  int nface;                 // coarse faces on its boundary: 2H (+ 2W in 2D)
+  double* flx;               // [nface][3][NU + 1]: coarse flux, two fine fluxes (+ u-hat)
+  double* reg;               // [nface][NU]: correction of the outside coarse cell's L
+  const double* dt;          // the (shared) time step
+};
+
+// coarse face f of the block's boundary: normal direction, the coarse cells
+// on its minus and plus sides, which of them lies outside, and the fine
+// cells on both sides of its k-th fine sub-face (k = 0, 1)
+struct AmrFace {
+  int dir;
+  int cm[2], cp[2];          // coarse (x, y) of the minus / plus cell
+  bool out_minus;            // the outside coarse cell is the minus cell
+  int fm[2][2], fp[2][2];    // fine (x, y) of the minus / plus cell of sub-face k
+};
+
+__device__ __forceinline__ AmrFace amr_face(const AmrLink& L, int f) {
+  AmrFace a;
+  const int H = L.H, W = L.W, h = kAmrHalo;
+  if (f < 2 * H) {                        // x faces: left (f < H) and right edges
+    const bool left = f < H;
+    const int J = L.loy + (left ? f : f - H);
+    a.dir = 0;
+    const int xm = left ? L.lox - 1 : L.lox + W - 1;
+    a.cm[0] = xm; a.cm[1] = J; a.cp[0] = xm + 1; a.cp[1] = J;
+    a.out_minus = left;
+    const int fxm = left ? h - 1 : h + 2 * W - 1;
+    for (int k = 0; k < 2; ++k) {
+      const int fy = (L.fg.ny == 1) ? 0 : h + 2 * (J - L.loy) + k;
+      a.fm[k][0] = fxm; a.fm[k][1] = fy; a.fp[k][0] = fxm + 1; a.fp[k][1] = fy;
+    }
+  } else {                                // y faces: bottom and top edges
+    const bool bot = f < 2 * H + W;
+    const int I = L.lox + (bot ? f - 2 * H : f - 2 * H - W);
+    a.dir = 1;
+    const int ym = bot ? L.loy - 1 : L.loy + H - 1;
+    a.cm[0] = I; a.cm[1] = ym; a.cp[0] = I; a.cp[1] = ym + 1;
+    a.out_minus = bot;
+    const int fym = bot ? h - 1 : h + 2 * H - 1;
+    for (int k = 0; k < 2; ++k) {
+      const int fx = h + 2 * (I - L.lox) + k;
+      a.fm[k][0] = fx; a.fm[k][1] = fym; a.fp[k][0] = fx; a.fp[k][1] = fym + 1;
+    }
+  }
+  return a;
+}
+
+// halo cells: fine stage state <- the coarse parent's stage state
+__global__ void k_amr_prolong(const AmrLink* __restrict__ links, int stage, int nU) {
+  const AmrLink& L = links[blockIdx.y];
+  const int fnx = L.fg.nx, fny = L.fg.ny, h = kAmrHalo;
+  const int64_t fnc = L.fg.nc, cnc = L.cg.nc;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < fnc;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int fy = (int)(i / fnx), fx = (int)(i - (int64_t)fy * fnx);
+    const bool inx = fx >= h && fx < fnx - h, iny = fny == 1 || (fy >= h && fy < fny - h);
+    if (inx && iny) continue;
+    // parent: floor((f - h) / 2) cells from the block's origin
+    const int cx = L.lox + ((fx - h) >= 0 ? (fx - h) / 2 : -((h - fx + 1) / 2));
+    const int cy = fny == 1 ? 0 : L.loy + ((fy - h) >= 0 ? (fy - h) / 2 : -((h - fy + 1) / 2));
+    const int64_t ci = (int64_t)cy * L.cg.nx + cx;
+    for (int c = 0; c < nU; ++c) L.fst[stage][c * fnc + i] = L.cst[stage][c * cnc + ci];
+  }
+}
+
+// interface fluxes of stage s: item (link, face, k) with k = 0 the coarse
+// face and k = 1, 2 the fine sub-faces; every flux from the two cells'
+// WENO-C/CL reconstructions (5-cell stencils along the normal) and the
+// Riemann solver, the functions the sweeps use
+template <int N, int D, typename W>
+__global__ __launch_bounds__(64) void k_amr_flux(const AmrLink* __restrict__ links,
+                                                 const int2* __restrict__ items, int nitems,
+                                                 int stage) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nitems) return;
+  constexpr int NU = 2 * N + D + 1;
+  const int2 it = items[t];
+  const AmrLink& L = links[it.x];
+  const int f = it.y / 3, k = it.y - 3 * (it.y / 3);
+  if (D == 1 && k == 2) return;
+  const AmrFace a = amr_face(L, f);
+  const bool fine = k > 0;
+  const Grid& g = fine ? L.fg : L.cg;
+  const gdouble* U = gptr(fine ? L.fst[stage] : L.cst[stage]);
+  const int mx = fine ? a.fm[k - 1][0] : a.cm[0], my = fine ? a.fm[k - 1][1] : a.cm[1];
+  // the six cells along the normal: minus cell - 2 .. minus cell + 3
+  Cons<N, D> cu[6];
+  double V[6][2 * N + D + 1];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int x = a.dir == 0 ? mx - 2 + j : mx, y = a.dir == 1 ? my - 2 + j : my;
+    load_cons<N, D>(U, g.nc, (int64_t)y * g.nx + x, cu[j]);
+    Prim<N, D> v;
+    cons_to_prim<N, D>(cu[j], L.e, v);
+#pragma unroll
+    for (int p = 0; p < N; ++p) { V[j][p] = v.m[p]; V[j][N + p] = v.a[p]; }
+#pragma unroll
+    for (int q = 0; q < D; ++q) V[j][2 * N + q] = v.u[q];
+    V[j][2 * N + D] = v.P;
+  }
+  const double hd = a.dir == 0 ? g.hdx : g.hdy;
+  Face<N, D> fm0, fpm, fmp, fp0;
+  reconstruct<N, D, W>([&](int c, int j) { return V[j][c]; }, cu[2], L.e, g, hd, fm0, fpm);
+  reconstruct<N, D, W>([&](int c, int j) { return V[j + 1][c]; }, cu[3], L.e, g, hd, fmp, fp0);
+  Flux<N, D> F;
+  riemann<N, D, W>(fpm, fmp, a.dir, g.flux, F);
+  double* out = L.flx + ((int64_t)f * 3 + k) * (NU + 1);
+#pragma unroll
+  for (int c = 0; c < NU; ++c) gptr(out)[c] = F.f[c];
+  gptr(out)[NU] = F.uh;
+}
+
+// the stage's correction of the outside coarse cells' L: the fine minus
+// the coarse flux over the coarse width, with the alpha source on the same
+// face-velocity difference; accumulated with the RK3 weight of the stage
+template <int N, int D>
+__global__ void k_amr_combine(const AmrLink* __restrict__ links, const int2* __restrict__ faces,
+                              int nfaces, int stage) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nfaces) return;
+  constexpr int NU = 2 * N + D + 1;
+  const int2 it = faces[t];
+  const AmrLink& L = links[it.x];
+  const int f = it.y;
+  const AmrFace a = amr_face(L, f);
+  const gdouble* fl = gptr(L.flx) + (int64_t)f * 3 * (NU + 1);
+  const double rd = a.dir == 0 ? L.cg.rdx : L.cg.rdy;
+  // the outside coarse cell at the stage state
+  const int ox = a.out_minus ? a.cm[0] : a.cp[0], oy = a.out_minus ? a.cm[1] : a.cp[1];
+  Cons<N, D> ub;
+  load_cons<N, D>(gptr(L.cst[stage]), L.cg.nc, (int64_t)oy * L.cg.nx + ox, ub);
+  double opk[N];
+  one_plus_k<N, D>(ub, L.e, L.cg.model, opk);
+  double isa = 1.0;
+  if (L.cg.asrc) {
+    double sa = 0.0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) sa += ub.a[p];
+    isa = sa > 0.0 ? 1.0 / sa : 0.0;
+  }
+  // the face is the outside cell's upper face (block above it) or its lower one
+  const double sg = a.out_minus ? -1.0 : 1.0;
+  double dL[NU + 1];
+#pragma unroll
+  for (int c = 0; c <= NU; ++c) {
+    const double ff = D == 1 ? fl[(NU + 1) + c] : 0.5 * (fl[(NU + 1) + c] + fl[2 * (NU + 1) + c]);
+    dL[c] = sg * (ff - fl[c]) * rd;
+  }
+#pragma unroll
+  for (int p = 0; p < N; ++p) dL[N + D + 1 + p] -= ub.a[p] * isa * opk[p] * dL[NU];
+  const double w = stage == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
+  gdouble* r = gptr(L.reg) + (int64_t)f * NU;
+#pragma unroll
+  for (int c = 0; c < NU; ++c) r[c] = (stage == 0 ? 0.0 : r[c]) + w * dL[c];
+}
+
+// after the step: coarse cells under the block <- mean of their children;
+// coarse cells beside it += dt x the accumulated correction
+__global__ void k_amr_restrict(const AmrLink* __restrict__ links, int nU) {
+  const AmrLink& L = links[blockIdx.y];
+  const int h = kAmrHalo;
+  const bool one = L.fg.ny == 1;
+  const int64_t ncell = (int64_t)L.W * L.H;
+  double* cU = L.cst[0];
+  const double* fU = L.fst[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ncell;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int J = (int)(i / L.W), I = (int)(i - (int64_t)J * L.W);
+    const int64_t ci = (int64_t)(L.loy + J) * L.cg.nx + (L.lox + I);
+    const int fx = h + 2 * I;
+    for (int c = 0; c < nU; ++c) {
+      const double* F = fU + (int64_t)c * L.fg.nc;
+      double v;
+      if (one) {
+        v = 0.5 * (F[fx] + F[fx + 1]);
+      } else {
+        const int64_t f0 = (int64_t)(h + 2 * J) * L.fg.nx + fx, f1 = f0 + L.fg.nx;
+        v = 0.25 * ((F[f0] + F[f0 + 1]) + (F[f1] + F[f1 + 1]));
+      }
+      gptr(cU)[(int64_t)c * L.cg.nc + ci] = v;
+    }
+  }
+}
+
+__global__ void k_amr_reflux(const AmrLink* __restrict__ links, const int2* __restrict__ faces,
+                             int nfaces, int nU) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nfaces) return;
+  const int2 it = faces[t];
+  const AmrLink& L = links[it.x];
+  const AmrFace a = amr_face(L, it.y);
+  const int ox = a.out_minus ? a.cm[0] : a.cp[0], oy = a.out_minus ? a.cm[1] : a.cp[1];
+  const double dt = *gptr(L.dt);
+  const double* r = L.reg + (int64_t)it.y * nU;
+  for (int c = 0; c < nU; ++c) {
+    gdouble* u = gptr(L.cst[0]) + (int64_t)c * L.cg.nc + (int64_t)oy * L.cg.nx + ox;
+    *u = *u + dt * r[c];
+  }
+}
+
+// linked instances take the smallest of their time steps
+__global__ void k_amr_dt(const int* __restrict__ ids, int n, double* dt) {
+  if (threadIdx.x != 0) return;
+  double m = INFINITY;
+  for (int k = 0; k < n; ++k) m = fmin(m, dt[ids[k]]);
+  for (int k = 0; k < n; ++k) dt[ids[k]] = m;
+}
+
+// ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_max(double v) {
@@ -2000,9 +2234,25 @@ void launch_rhs_single(const Desc* desc, const Grid& g, hipStream_t s) {
 
 using RhsSingleFn = void (*)(const Desc*, const Grid&, hipStream_t);
 
+// the per-(N, d) kernels of the two-level coupling: (links, items, count,
+// stage, stream)
+using AmrFn = void (*)(const AmrLink*, const int2*, int, int, hipStream_t);
+template <int N, int D, typename W>
+void launch_amr_flux(const AmrLink* l, const int2* items, int n, int stage, hipStream_t s) {
+  hipLaunchKernelGGL((k_amr_flux<N, D, W>), dim3((n + 63) / 64), dim3(64), 0, s, l, items, n,
+                     stage);
+}
+template <int N, int D>
+void launch_amr_comb(const AmrLink* l, const int2* faces, int n, int stage, hipStream_t s) {
+  hipLaunchKernelGGL((k_amr_combine<N, D>), dim3((n + 63) / 64), dim3(64), 0, s, l, faces, n,
+                     stage);
+}
+
 struct Table {
   StageFn sx[2][kMaxN + 1][4][2][kXVar] = {};   // [PF flux][N][d][precision][shape]
   RhsSingleFn rhs1[kMaxN + 1][4][2] = {};       // allocation-free L(U): [N][d][precision]
+  AmrFn amrflux[kMaxN + 1][3][2] = {};          // interface fluxes of linked levels
+  AmrFn amrcomb[kMaxN + 1][3] = {};             // their stage corrections
   StageFn sy[2][kMaxN + 1][2][kYVar] = {};      // 2D y sweep
   StageFn sy3[kMaxN3 + 1][2][kYVar] = {};       // 3D y sweep (adds to the accumulator)
   StageFn sz3[kMaxN3 + 1][2][kYVar] = {};       // 3D z sweep (finishes the stage)
@@ -2046,6 +2296,12 @@ void fill_shapes(Table& t) {
 
 template <int N>
 void fill(Table& t) {
+  t.amrflux[N][1][0] = launch_amr_flux<N, 1, double>;
+  t.amrflux[N][1][1] = launch_amr_flux<N, 1, float>;
+  t.amrflux[N][2][0] = launch_amr_flux<N, 2, double>;
+  t.amrflux[N][2][1] = launch_amr_flux<N, 2, float>;
+  t.amrcomb[N][1] = launch_amr_comb<N, 1>;
+  t.amrcomb[N][2] = launch_amr_comb<N, 2>;
   t.rhs1[N][1][0] = launch_rhs_single<N, 1, double>;
   t.rhs1[N][1][1] = launch_rhs_single<N, 1, float>;
   t.rhs1[N][2][0] = launch_rhs_single<N, 2, double>;
@@ -2154,6 +2410,16 @@ struct mp_weno_ctx {
   hipGraphExec_t pf_graph = nullptr;
   hipStream_t cap_stream = nullptr;
   double* pf_flags = nullptr;
+  // two-level coupling (mp_weno_amr_link): device link table, flux items
+  // (link, 3 face + k), faces (link, face), the linked instances, one buffer
+  // of interface fluxes and registers; all linked instances share (N, d)
+  AmrLink* amr = nullptr;
+  int2* amr_items = nullptr;
+  int2* amr_faces = nullptr;
+  int* amr_ids = nullptr;
+  double* amr_buf = nullptr;
+  int amr_nlinks = 0, amr_nitems = 0, amr_nfaces = 0, amr_nids = 0, amr_N = 0, amr_D = 0;
+  int amr_maxcells = 0;       // largest fine grid (ghost-fill launch size)
   std::string err;
   int profile = 0;            // Bracket::which
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -2378,10 +2644,36 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
 
 // the RK stages (and the Phase-Field step); advance: move time and step
 // count on at the end (when the CFL kernel did not)
+// two-level coupling around stage s: ghost fill of the fine blocks from the
+// coarse stage state, interface fluxes of both levels and their correction
+static void enqueue_amr_stage(mp_weno_ctx* c, int s) {
+  const Table& T = table();
+  const int nU = 2 * c->amr_N + c->amr_D + 1;
+  const int blocks = std::max(1, std::min(1024, (c->amr_maxcells + 255) / 256));
+  hipLaunchKernelGGL(k_amr_prolong, dim3(blocks, c->amr_nlinks), dim3(256), 0, c->stream,
+                     c->amr, s, nU);
+  T.amrflux[c->amr_N][c->amr_D][c->opt.precision](c->amr, c->amr_items, c->amr_nitems, s,
+                                                  c->stream);
+  T.amrcomb[c->amr_N][c->amr_D](c->amr, c->amr_faces, c->amr_nfaces, s, c->stream);
+}
+
 static mp_status enqueue_rk(mp_weno_ctx* c, bool advance) {
   for (int s = 0; s < 3; ++s) {
+    if (c->amr_nlinks) enqueue_amr_stage(c, s);
     mp_status st = enqueue_stage(c, s);
     if (st != MP_OK) return st;
+  }
+  if (c->amr_nlinks) {
+    const int nU = 2 * c->amr_N + c->amr_D + 1;
+    hipLaunchKernelGGL(k_amr_restrict, dim3(64, c->amr_nlinks), dim3(256), 0, c->stream, c->amr,
+                       nU);
+    hipLaunchKernelGGL(k_amr_reflux, dim3((c->amr_nfaces + 63) / 64), dim3(64), 0, c->stream,
+                       c->amr, c->amr_faces, c->amr_nfaces, nU);
+    // the rings hold the new coarse values between steps (the CFL step and
+    // the diagnostics read them)
+    const int blocks = std::max(1, std::min(1024, (c->amr_maxcells + 255) / 256));
+    hipLaunchKernelGGL(k_amr_prolong, dim3(blocks, c->amr_nlinks), dim3(256), 0, c->stream,
+                       c->amr, 0, nU);
   }
   if (c->opt.phase_field) {
     // the Phase-Field step on the hyperbolic result, same dt
@@ -2460,6 +2752,8 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
   }
   (void)hipFree(c->dt); (void)hipFree(c->t); (void)hipFree(c->steps); (void)hipFree(c->part);
   (void)hipFree(c->diag); (void)hipFree(c->pfs);
+  (void)hipFree(c->amr); (void)hipFree(c->amr_items); (void)hipFree(c->amr_faces);
+  (void)hipFree(c->amr_ids); (void)hipFree(c->amr_buf);
   delete c;
   return MP_OK;
 }
@@ -2887,6 +3181,109 @@ mp_status mp_weno_rhs_noalloc(const mp_weno_instance* inst, const mp_weno_opts* 
   return hipGetLastError() == hipSuccess ? MP_OK : MP_ERR_HIP;
 }
 
+mp_status mp_weno_amr_link(mp_weno_ctx* c, int32_t n_links, const mp_weno_link* links) {
+  if (!c || n_links < 0 || (n_links > 0 && !links)) return MP_ERR_ARG;
+  if (c->opt.phase_field && n_links > 0)
+    return fail(c, MP_ERR_UNSUPPORTED, "coupled levels with the Phase-Field step");
+  const int n = (int)c->inst.size();
+  std::vector<AmrLink> L((size_t)n_links);
+  std::vector<int2> items, faces;
+  std::vector<int> ids;
+  std::vector<char> used((size_t)n, 0), is_fine((size_t)n, 0);
+  int N0 = 0, D0 = 0, maxcells = 0;
+  size_t buf = 0;
+  std::vector<size_t> off((size_t)n_links);
+  for (int k = 0; k < n_links; ++k) {
+    const mp_weno_link& a = links[k];
+    if (a.fine < 0 || a.fine >= n || a.coarse < 0 || a.coarse >= n || a.fine == a.coarse)
+      return fail(c, MP_ERR_ARG, "link instance index out of range");
+    const Inst& F = c->inst[a.fine];
+    const Inst& C = c->inst[a.coarse];
+    const int D = C.D, N = C.N;
+    if (F.D != D || F.N != N || D > 2)
+      return fail(c, D > 2 ? MP_ERR_UNSUPPORTED : MP_ERR_ARG,
+                  "linked instances need the same N and d (1 or 2)");
+    if (k == 0) { N0 = N; D0 = D; }
+    if (N != N0 || D != D0) return fail(c, MP_ERR_UNSUPPORTED, "links of several (N, d)");
+    const int W = (F.in.n[0] - 2 * kAmrHalo) / 2, H = D > 1 ? (F.in.n[1] - 2 * kAmrHalo) / 2 : 1;
+    const int lx = a.lo[0], ly = D > 1 ? a.lo[1] : 0;
+    bool ok = W >= 1 && 2 * W + 2 * kAmrHalo == F.in.n[0] &&
+              (D == 1 || (H >= 1 && 2 * H + 2 * kAmrHalo == F.in.n[1]));
+    // the block and the coarse stencils around it stay inside the coarse grid
+    ok = ok && lx >= kAmrHalo && lx + W + kAmrHalo <= C.in.n[0];
+    ok = ok && (D == 1 || (ly >= kAmrHalo && ly + H + kAmrHalo <= C.in.n[1]));
+    for (int d = 0; d < D && ok; ++d)
+      ok = std::fabs(F.in.dx[d] * 2.0 - C.in.dx[d]) <= 1e-12 * C.in.dx[d];
+    if (!ok) return fail(c, MP_ERR_ARG, "link geometry (halo 3, ratio 2, block inside the coarse grid)");
+    if (is_fine[a.fine]) return fail(c, MP_ERR_ARG, "an instance refines two blocks");
+    is_fine[a.fine] = 1;
+    // blocks of one coarse instance: their coarse stencil regions must not meet
+    for (int j = 0; j < k; ++j) {
+      if (links[j].coarse != a.coarse) continue;
+      const AmrLink& B = L[j];
+      const int g = 2 * kAmrHalo;
+      const bool apart = lx >= B.lox + B.W + g || B.lox >= lx + W + g ||
+                         (D > 1 && (ly >= B.loy + B.H + g || B.loy >= ly + H + g));
+      if (!apart) return fail(c, MP_ERR_ARG, "blocks of one coarse instance too close");
+    }
+    AmrLink& l = L[k];
+    std::memset(&l, 0, sizeof(l));
+    l.fst[0] = F.in.U; l.fst[1] = F.U1; l.fst[2] = F.U2;
+    l.cst[0] = C.in.U; l.cst[1] = C.U1; l.cst[2] = C.U2;
+    Desc df, dc;
+    desc_grid_eos(F.in, c->opt, df);
+    desc_grid_eos(C.in, c->opt, dc);
+    l.fg = df.g; l.cg = dc.g; l.e = dc.e;
+    l.lox = lx; l.loy = ly; l.W = W; l.H = H;
+    l.nface = D > 1 ? 2 * H + 2 * W : 2;
+    l.dt = c->dt + a.coarse;
+    const int nU = 2 * N + D + 1;
+    off[(size_t)k] = buf;
+    buf += (size_t)l.nface * (3 * (nU + 1) + nU);
+    for (int f = 0; f < l.nface; ++f) {
+      faces.push_back(make_int2(k, f));
+      for (int q = 0; q < 3; ++q) items.push_back(make_int2(k, 3 * f + q));
+    }
+    for (int id : {a.fine, a.coarse})
+      if (!used[id]) { used[id] = 1; ids.push_back(id); }
+    maxcells = std::max<int>(maxcells, (int)F.nc);
+  }
+  // drop the previous coupling and any captured step (it holds the old one)
+  (void)hipFree(c->amr); (void)hipFree(c->amr_items); (void)hipFree(c->amr_faces);
+  (void)hipFree(c->amr_ids); (void)hipFree(c->amr_buf);
+  c->amr = nullptr; c->amr_items = nullptr; c->amr_faces = nullptr; c->amr_ids = nullptr;
+  c->amr_buf = nullptr;
+  c->amr_nlinks = 0;
+  for (auto& g : c->graph)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  if (c->chain) { (void)hipGraphExecDestroy(c->chain); c->chain = nullptr; }
+  if (n_links == 0) return MP_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (hipMalloc(&c->amr, sizeof(AmrLink) * L.size()) != hipSuccess ||
+      hipMalloc(&c->amr_items, sizeof(int2) * items.size()) != hipSuccess ||
+      hipMalloc(&c->amr_faces, sizeof(int2) * faces.size()) != hipSuccess ||
+      hipMalloc(&c->amr_ids, sizeof(int) * ids.size()) != hipSuccess ||
+      hipMalloc(&c->amr_buf, sizeof(double) * buf) != hipSuccess)
+    return fail(c, MP_ERR_OOM, "coupling buffers");
+  for (int k = 0; k < n_links; ++k) {
+    const int nU = 2 * N0 + D0 + 1;
+    L[(size_t)k].flx = c->amr_buf + off[(size_t)k];
+    L[(size_t)k].reg = L[(size_t)k].flx + (size_t)L[(size_t)k].nface * 3 * (nU + 1);
+  }
+  HIPCHK(c, hipMemcpy(c->amr, L.data(), sizeof(AmrLink) * L.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->amr_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->amr_faces, faces.data(), sizeof(int2) * faces.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->amr_ids, ids.data(), sizeof(int) * ids.size(), hipMemcpyHostToDevice));
+  c->amr_nlinks = n_links;
+  c->amr_nitems = (int)items.size();
+  c->amr_nfaces = (int)faces.size();
+  c->amr_nids = (int)ids.size();
+  c->amr_N = N0;
+  c->amr_D = D0;
+  c->amr_maxcells = maxcells;
+  return MP_OK;
+}
+
 mp_status mp_weno_pf_fields(mp_weno_ctx* c, const double* const* U_in, double* const* divj,
                             double* const* grad, double* const* dUdt) {
   if (!c) return MP_ERR_ARG;
@@ -3017,6 +3414,8 @@ mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
   if (!c || !dt) return fail(c, MP_ERR_ARG, "null argument");
   mp_status s = enqueue_dt(c, 0);
   if (s != MP_OK) return s;
+  if (c->amr_nlinks)      // linked instances share the smallest step
+    hipLaunchKernelGGL(k_amr_dt, dim3(1), dim3(64), 0, c->stream, c->amr_ids, c->amr_nids, c->dt);
   const size_t bytes = sizeof(double) * c->inst.size();
   if (where == MP_WHERE_HOST) {
     HIPCHK(c, hipMemcpyAsync(dt, c->dt, bytes, hipMemcpyDeviceToHost, c->stream));
@@ -3031,10 +3430,13 @@ mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
 // moves the time on (nothing later in the step reads it); otherwise it moves
 // at the end, so a failed Phase-Field solve leaves it untouched.
 static mp_status enqueue_step(mp_weno_ctx* c, bool external_dt) {
-  const bool early = !external_dt && !c->opt.phase_field;
+  const bool early = !external_dt && !c->opt.phase_field && !c->amr_nlinks;
   if (!external_dt) {
     mp_status s = enqueue_dt(c, early ? 1 : 0);
     if (s != MP_OK) return s;
+    if (c->amr_nlinks)
+      hipLaunchKernelGGL(k_amr_dt, dim3(1), dim3(64), 0, c->stream, c->amr_ids, c->amr_nids,
+                         c->dt);
   }
   return enqueue_rk(c, !early);
 }
