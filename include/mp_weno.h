@@ -282,7 +282,10 @@ mp_status mp_weno_autotune(mp_weno_ctx *ctx, int32_t reps, int32_t *choice);
 mp_status mp_weno_dt(mp_weno_ctx *ctx, double *dt, int32_t where);
 
 /* Advance every instance by one third-order SSP Runge-Kutta step, in place in
- * the instances' U.  dt_dev: device array of n_inst time steps, or NULL to
+ * the instances' U.  An instance whose step is 0 (it reached its t_end, or
+ * an external dt of 0) is skipped by the sweeps: its state stays bitwise
+ * unchanged and its tiles cost nothing, so a batch retires its instances as
+ * they finish.  dt_dev: device array of n_inst time steps, or NULL to
  * use the CFL step computed on the device inside the same call.  Each
  * instance's time and step counter advance on the device.  Asynchronous,
  * except with check_bounds = 1: then the call synchronises, checks the new

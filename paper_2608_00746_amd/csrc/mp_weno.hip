@@ -306,6 +306,8 @@ void k_sweep_x(const Desc* __restrict__ descs,
   const Grid& g = d.g;
   const Eos& e = d.e;
   const StageArgs a = stage_args(d, stage);
+  // an instance whose step is 0 (retired at its end time) is left as it is
+  if (a.mode == 1 && *a.dt == 0.0) return;
   const int ns = (g.nx + BX - 3) / (BX - 2);
   const int local = it.y;
   const int y = local / ns;
@@ -468,6 +470,7 @@ void k_sweep_t(const Desc* __restrict__ descs,
   const Grid& g = d.g;
   const Eos& e = d.e;
   const StageArgs a = stage_args(d, stage);
+  if (a.mode == 1 && *a.dt == 0.0) return;     // retired instance (step 0)
   constexpr int kOY = kTY - 2;      // output lines per tile
   // the sweep line: its length, stride, end conditions and spacing
   const int nl = DIR == 1 ? g.ny : g.nz;
@@ -927,7 +930,8 @@ __global__ __launch_bounds__(kRedBlock) void k_dt_finish(
     *gptr(d.dt) = dt;
     if (advance) {
       *gptr(d.t) = t + dt;
-      *gptr(d.steps) = *gptr(d.steps) + 1.0;
+      // a step of 0 (the instance reached t_end) is not taken
+      if (dt > 0.0) *gptr(d.steps) = *gptr(d.steps) + 1.0;
     }
   }
 }
@@ -936,7 +940,7 @@ __global__ void k_advance_time(double* t, double* steps, const double* dt, int n
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     t[i] = t[i] + dt[i];
-    steps[i] = steps[i] + 1.0;
+    if (dt[i] > 0.0) steps[i] = steps[i] + 1.0;   // a step of 0 is not taken
   }
 }
 
