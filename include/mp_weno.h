@@ -262,8 +262,9 @@ mp_status mp_weno_pf_fields(mp_weno_ctx *ctx, const double *const *U_in,
 /* Autotuner: for every group of instances with the same (N, d), time the
  * tile shapes of the sweeps (x strips of 256, 128 or 64 lanes; y tiles, and
  * in 3D z tiles of the same shape, of 16 x 16, 32 x 8 or 16 x 24 lanes) and
- * the XCD-aware tile order (off / on) on the
- * current states, reps launches each (0: 8) in two interleaved rounds (the
+ * the XCD-aware tile order (off / on; with the comparison schemes
+ * MP_RECON_WENO_JS / WENO_W, built with the default shapes only, just the
+ * order) on the current states, reps launches each (0: 8) in two interleaved rounds (the
  * faster round counts), and keep the fastest for the
  * hyperbolic sweeps of later calls.  The timing evaluates L(U) into the
  * context's stage buffer: the states, the time and the step count are not

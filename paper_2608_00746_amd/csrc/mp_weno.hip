@@ -290,6 +290,16 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
 // FP64 latency better than 2 waves (measured +7..10 % on N = 2 in 2D); two
 // phases in 3D, three and four phases would spill heavily at 3 and keep 2;
 // five need the AGPRs too.
+// The flux and reconstruction variants of the sweeps (template PFM):
+// kRiemann: Riemann flux, WENO-C / WENO-CL; kPfFlux: the Phase-Field flux
+// (any reconstruction); kRiemannCmp: Riemann flux with the comparison
+// schemes (WENO-JS, WENO-W).
+constexpr int kRiemann = 0, kPfFlux = 1, kRiemannCmp = 2;
+template <int PFM>
+constexpr int kRecon() {
+  return PFM == kRiemann ? kReconC : (PFM == kRiemannCmp ? kReconCmp : kReconAny);
+}
+
 template <int N, int D>
 constexpr int sweep_waves() {
   return N == 1 ? (D == 1 ? 4 : 3) : (N == 2 ? (D == 3 ? 2 : 3) : (N <= 4 ? 2 : 1));
@@ -361,7 +371,8 @@ void k_sweep_x(const Desc* __restrict__ descs,
   __syncthreads();
 
   Face<N, D> fm, fp;
-  reconstruct<N, D, W>([&](int c, int j) { return sprim[c][l + j]; }, ub, e, g, g.hdx, fm, fp);
+  reconstruct<N, D, W, kRecon<PFM>()>([&](int c, int j) { return sprim[c][l + j]; }, ub, e, g,
+                                      g.hdx, fm, fp);
 
   // publish the minus-side face state for the left neighbour
 #pragma unroll
@@ -386,7 +397,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
     R.P = sface[2 * N + 2 * D + 1][r];
     R.rho = sface[2 * N + 2 * D + 2][r];
     R.c = sface[2 * N + 2 * D + 3][r];
-    if constexpr (PFM) {
+    if constexpr (PFM == kPfFlux) {
       // gradient at face x_{xi+1/2}: face -1/2 is face n-1/2 when periodic
       // and carries none at an outflow end
       const int xo = xi < 0 ? (g.bcx0 == MP_BC_PERIODIC ? g.nx - 1 : -1) : (xi < g.nx ? xi : -1);
@@ -411,7 +422,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
 
   if (l >= 1 && l < BX - 1 && xi < g.nx) {
     double L[NU];
-    if constexpr (PFM) {
+    if constexpr (PFM == kPfFlux) {
 #pragma unroll
       for (int c = 0; c < NU; ++c) L[c] = (F.f[c] - sflux[c][l - 1]) * g.rdx;
     } else {
@@ -463,7 +474,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, kTX * kTY),
 void k_sweep_t(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map,
                                                        int ninst, int stage, int swz) {
-  static_assert(D >= 2 && DIR >= 1 && DIR < D && (PFM == 0 || D == 2), "sweep shape");
+  static_assert(D >= 2 && DIR >= 1 && DIR < D && (PFM != kPfFlux || D == 2), "sweep shape");
   constexpr bool kLast = DIR == D - 1;
   const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));
   const Desc d = descs[it.x];
@@ -534,7 +545,8 @@ void k_sweep_t(const Desc* __restrict__ descs,
   __syncthreads();
 
   Face<N, D> fm, fp;
-  reconstruct<N, D, W>([&](int c, int j) { return sprim[c][ty + j][tx]; }, ub, e, g, hd, fm, fp);
+  reconstruct<N, D, W, kRecon<PFM>()>([&](int c, int j) { return sprim[c][ty + j][tx]; }, ub, e,
+                                      g, hd, fm, fp);
 
 #pragma unroll
   for (int p = 0; p < N; ++p) { sface[p][ty][tx] = fm.m[p]; sface[N + p][ty][tx] = fm.a[p]; }
@@ -558,7 +570,7 @@ void k_sweep_t(const Desc* __restrict__ descs,
     R.P = sface[2 * N + 2 * D + 1][r][tx];
     R.rho = sface[2 * N + 2 * D + 2][r][tx];
     R.c = sface[2 * N + 2 * D + 3][r][tx];
-    if constexpr (PFM) {
+    if constexpr (PFM == kPfFlux) {
       const int yo = yi < 0 ? (g.bcy0 == MP_BC_PERIODIC ? g.ny - 1 : -1) : (yi < g.ny ? yi : -1);
       const int yq = yo < 0 ? -1 : (yo + 1 < g.ny ? yo + 1 : (g.bcy1 == MP_BC_PERIODIC ? 0 : -1));
       double G[N], kf[N];
@@ -582,7 +594,7 @@ void k_sweep_t(const Desc* __restrict__ descs,
   if (ty >= 1 && ty < kTY - 1 && colok && yi < nl) {
     const int64_t idx = pb + (int64_t)yi * ls + x;
     double L[NU];
-    if constexpr (PFM) {
+    if constexpr (PFM == kPfFlux) {
 #pragma unroll
       for (int c = 0; c < NU; ++c)
         L[c] = a.acc[(int64_t)c * nc + idx] + (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
@@ -743,8 +755,10 @@ __global__ __launch_bounds__(64) void k_amr_flux(const AmrLink* __restrict__ lin
   }
   const double hd = a.dir == 0 ? g.hdx : g.hdy;
   Face<N, D> fm0, fpm, fmp, fp0;
-  reconstruct<N, D, W>([&](int c, int j) { return V[j][c]; }, cu[2], L.e, g, hd, fm0, fpm);
-  reconstruct<N, D, W>([&](int c, int j) { return V[j + 1][c]; }, cu[3], L.e, g, hd, fmp, fp0);
+  reconstruct<N, D, W, kReconAny>([&](int c, int j) { return V[j][c]; }, cu[2], L.e, g, hd, fm0,
+                                  fpm);
+  reconstruct<N, D, W, kReconAny>([&](int c, int j) { return V[j + 1][c]; }, cu[3], L.e, g, hd,
+                                  fmp, fp0);
   Flux<N, D> F;
   riemann<N, D, W>(fpm, fmp, a.dir, g.flux, F);
   double* out = L.flx + ((int64_t)f * 3 + k) * (NU + 1);
@@ -2218,19 +2232,19 @@ __global__ void k_put_desc(Desc d, Desc* dst) {
 
 // L(U) of one instance (stage 3: rin -> rout) with the default tile shapes,
 // the descriptor at desc (a group of one: no tile map is read)
-template <int N, int D, typename W>
+template <int N, int D, typename W, int PFM>
 void launch_rhs_single(const Desc* desc, const Grid& g, hipStream_t s) {
   const int64_t nstrip = (g.nx + kXS[0] - 3) / (kXS[0] - 2);
-  hipLaunchKernelGGL((k_sweep_x<N, D, W, 0, kXS[0]>), dim3((unsigned)(nstrip * g.ny * g.nz)),
+  hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM, kXS[0]>), dim3((unsigned)(nstrip * g.ny * g.nz)),
                      dim3(kXS[0]), 0, s, desc, nullptr, 1, 3, 0);
   if constexpr (D >= 2) {
     constexpr int oy = kYY[0] - 2;
     const int64_t ntx = (g.nx + kYX[0] - 1) / kYX[0];
-    hipLaunchKernelGGL((k_sweep_t<N, W, 0, kYX[0], kYY[0], D, 1>),
+    hipLaunchKernelGGL((k_sweep_t<N, W, PFM, kYX[0], kYY[0], D, 1>),
                        dim3((unsigned)(ntx * ((g.ny + oy - 1) / oy) * g.nz)),
                        dim3(kYX[0] * kYY[0]), 0, s, desc, nullptr, 1, 3, 0);
     if constexpr (D == 3)
-      hipLaunchKernelGGL((k_sweep_t<N, W, 0, kYX[0], kYY[0], D, 2>),
+      hipLaunchKernelGGL((k_sweep_t<N, W, PFM, kYX[0], kYY[0], D, 2>),
                          dim3((unsigned)(ntx * ((g.nz + oy - 1) / oy) * g.ny)),
                          dim3(kYX[0] * kYY[0]), 0, s, desc, nullptr, 1, 3, 0);
   }
@@ -2252,14 +2266,16 @@ void launch_amr_comb(const AmrLink* l, const int2* faces, int n, int stage, hipS
                      stage);
 }
 
+// Sweep tables: [variant][N][d][precision][shape], variant kRiemann,
+// kPfFlux or kRiemannCmp (the last two with the default shapes only)
 struct Table {
-  StageFn sx[2][kMaxN + 1][4][2][kXVar] = {};   // [PF flux][N][d][precision][shape]
-  RhsSingleFn rhs1[kMaxN + 1][4][2] = {};       // allocation-free L(U): [N][d][precision]
+  StageFn sx[3][kMaxN + 1][4][2][kXVar] = {};
+  RhsSingleFn rhs1[2][kMaxN + 1][4][2] = {};    // allocation-free L(U): [comparison][N][d][prec]
   AmrFn amrflux[kMaxN + 1][3][2] = {};          // interface fluxes of linked levels
   AmrFn amrcomb[kMaxN + 1][3] = {};             // their stage corrections
-  StageFn sy[2][kMaxN + 1][2][kYVar] = {};      // 2D y sweep
-  StageFn sy3[kMaxN3 + 1][2][kYVar] = {};       // 3D y sweep (adds to the accumulator)
-  StageFn sz3[kMaxN3 + 1][2][kYVar] = {};       // 3D z sweep (finishes the stage)
+  StageFn sy[3][kMaxN + 1][2][kYVar] = {};      // 2D y sweep
+  StageFn sy3[2][kMaxN3 + 1][2][kYVar] = {};    // 3D y sweep (adds to the accumulator): [comparison]
+  StageFn sz3[2][kMaxN3 + 1][2][kYVar] = {};    // 3D z sweep (finishes the stage): [comparison]
   DtFn dt[kMaxN + 1][4] = {};
   RedFn diag[kMaxN + 1][4] = {};
   PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
@@ -2280,21 +2296,33 @@ void fill_pf(Table& t) {
   t.mg_lds[N][D] = mg_fused_lds<N, D>;
 }
 
-template <int N, int V>
+// the Riemann-flux sweeps of shape V; F: kRiemann or kRiemannCmp
+template <int N, int V, int F>
 void fill_shapes(Table& t) {
-  t.sx[0][N][1][0][V] = launch_x<N, 1, double, 0, V>;
-  t.sx[0][N][1][1][V] = launch_x<N, 1, float, 0, V>;
-  t.sx[0][N][2][0][V] = launch_x<N, 2, double, 0, V>;
-  t.sx[0][N][2][1][V] = launch_x<N, 2, float, 0, V>;
-  t.sy[0][N][0][V] = launch_t<N, double, 0, V, 2, 1>;
-  t.sy[0][N][1][V] = launch_t<N, float, 0, V, 2, 1>;
+  constexpr int C = F == kRiemannCmp;
+  t.sx[F][N][1][0][V] = launch_x<N, 1, double, F, V>;
+  t.sx[F][N][1][1][V] = launch_x<N, 1, float, F, V>;
+  t.sx[F][N][2][0][V] = launch_x<N, 2, double, F, V>;
+  t.sx[F][N][2][1][V] = launch_x<N, 2, float, F, V>;
+  t.sy[F][N][0][V] = launch_t<N, double, F, V, 2, 1>;
+  t.sy[F][N][1][V] = launch_t<N, float, F, V, 2, 1>;
   if constexpr (N <= kMaxN3) {
-    t.sx[0][N][3][0][V] = launch_x<N, 3, double, 0, V>;
-    t.sx[0][N][3][1][V] = launch_x<N, 3, float, 0, V>;
-    t.sy3[N][0][V] = launch_t<N, double, 0, V, 3, 1>;
-    t.sy3[N][1][V] = launch_t<N, float, 0, V, 3, 1>;
-    t.sz3[N][0][V] = launch_t<N, double, 0, V, 3, 2>;
-    t.sz3[N][1][V] = launch_t<N, float, 0, V, 3, 2>;
+    t.sx[F][N][3][0][V] = launch_x<N, 3, double, F, V>;
+    t.sx[F][N][3][1][V] = launch_x<N, 3, float, F, V>;
+    t.sy3[C][N][0][V] = launch_t<N, double, F, V, 3, 1>;
+    t.sy3[C][N][1][V] = launch_t<N, float, F, V, 3, 1>;
+    t.sz3[C][N][0][V] = launch_t<N, double, F, V, 3, 2>;
+    t.sz3[C][N][1][V] = launch_t<N, float, F, V, 3, 2>;
+  }
+  if constexpr (V == 0) {
+    t.rhs1[C][N][1][0] = launch_rhs_single<N, 1, double, F>;
+    t.rhs1[C][N][1][1] = launch_rhs_single<N, 1, float, F>;
+    t.rhs1[C][N][2][0] = launch_rhs_single<N, 2, double, F>;
+    t.rhs1[C][N][2][1] = launch_rhs_single<N, 2, float, F>;
+    if constexpr (N <= kMaxN3) {
+      t.rhs1[C][N][3][0] = launch_rhs_single<N, 3, double, F>;
+      t.rhs1[C][N][3][1] = launch_rhs_single<N, 3, float, F>;
+    }
   }
 }
 
@@ -2306,24 +2334,17 @@ void fill(Table& t) {
   t.amrflux[N][2][1] = launch_amr_flux<N, 2, float>;
   t.amrcomb[N][1] = launch_amr_comb<N, 1>;
   t.amrcomb[N][2] = launch_amr_comb<N, 2>;
-  t.rhs1[N][1][0] = launch_rhs_single<N, 1, double>;
-  t.rhs1[N][1][1] = launch_rhs_single<N, 1, float>;
-  t.rhs1[N][2][0] = launch_rhs_single<N, 2, double>;
-  t.rhs1[N][2][1] = launch_rhs_single<N, 2, float>;
-  if constexpr (N <= kMaxN3) {
-    t.rhs1[N][3][0] = launch_rhs_single<N, 3, double>;
-    t.rhs1[N][3][1] = launch_rhs_single<N, 3, float>;
-  }
-  fill_shapes<N, 0>(t);
-  fill_shapes<N, 1>(t);
-  fill_shapes<N, 2>(t);
+  fill_shapes<N, 0, kRiemann>(t);
+  fill_shapes<N, 1, kRiemann>(t);
+  fill_shapes<N, 2, kRiemann>(t);
+  fill_shapes<N, 0, kRiemannCmp>(t);
   // the Phase-Field sweeps: default shapes only
-  t.sx[1][N][1][0][0] = launch_x<N, 1, double, 1, 0>;
-  t.sx[1][N][1][1][0] = launch_x<N, 1, float, 1, 0>;
-  t.sx[1][N][2][0][0] = launch_x<N, 2, double, 1, 0>;
-  t.sx[1][N][2][1][0] = launch_x<N, 2, float, 1, 0>;
-  t.sy[1][N][0][0] = launch_t<N, double, 1, 0, 2, 1>;
-  t.sy[1][N][1][0] = launch_t<N, float, 1, 0, 2, 1>;
+  t.sx[kPfFlux][N][1][0][0] = launch_x<N, 1, double, kPfFlux, 0>;
+  t.sx[kPfFlux][N][1][1][0] = launch_x<N, 1, float, kPfFlux, 0>;
+  t.sx[kPfFlux][N][2][0][0] = launch_x<N, 2, double, kPfFlux, 0>;
+  t.sx[kPfFlux][N][2][1][0] = launch_x<N, 2, float, kPfFlux, 0>;
+  t.sy[kPfFlux][N][0][0] = launch_t<N, double, kPfFlux, 0, 2, 1>;
+  t.sy[kPfFlux][N][1][0] = launch_t<N, float, kPfFlux, 0, 2, 1>;
   fill_pf<N, 1>(t);
   fill_pf<N, 2>(t);
   t.pfi[0][N] = launch_pf_inst<N, 0>;
@@ -2471,16 +2492,19 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
     if (G.swz >= 0) return G.swz;
     return G.ids.size() > 1 ? 1 : 0;
   };
+  // the comparison schemes and the Phase-Field flux run the default shapes
+  const int cmp = c->opt.recon >= MP_RECON_WENO_JS;
+  const int v = pf ? kPfFlux : (cmp ? kRiemannCmp : kRiemann);
   for (const Group& G : c->groups)
-    T.sx[pf][G.N][G.D][prec][pf ? 0 : G.xv](G, s, swz(G), c->stream);
+    T.sx[v][G.N][G.D][prec][v ? 0 : G.xv](G, s, swz(G), c->stream);
   if (w == 1) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   if (w == 2) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
   for (const Group& G : c->groups) {
-    if (G.D == 2) T.sy[pf][G.N][prec][pf ? 0 : G.yv](G, s, swz(G), c->stream);
-    if (G.D == 3) T.sy3[G.N][prec][G.yv](G, s, swz(G), c->stream);
+    if (G.D == 2) T.sy[v][G.N][prec][v ? 0 : G.yv](G, s, swz(G), c->stream);
+    if (G.D == 3) T.sy3[cmp][G.N][prec][cmp ? 0 : G.yv](G, s, swz(G), c->stream);
   }
   for (const Group& G : c->groups)
-    if (G.D == 3) T.sz3[G.N][prec][G.yv](G, s, swz(G), c->stream);
+    if (G.D == 3) T.sz3[cmp][G.N][prec][cmp ? 0 : G.yv](G, s, swz(G), c->stream);
   if (w == 2 || w == 3) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -2813,8 +2837,10 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
   // mp_weno_autotune)
   const char* xsh = std::getenv("MPWENO_XSHAPE");
   const char* ysh = std::getenv("MPWENO_YSHAPE");
-  const int xv0 = xsh ? std::min(std::max(std::atoi(xsh), 0), kXVar - 1) : 0;
-  const int yv0 = ysh ? std::min(std::max(std::atoi(ysh), 0), kYVar - 1) : 0;
+  // (the comparison schemes are built with the default shapes only)
+  const bool cmp = opt->recon >= MP_RECON_WENO_JS;
+  const int xv0 = xsh && !cmp ? std::min(std::max(std::atoi(xsh), 0), kXVar - 1) : 0;
+  const int yv0 = ysh && !cmp ? std::min(std::max(std::atoi(ysh), 0), kYVar - 1) : 0;
   const size_t n = (size_t)n_inst;
   if (hipMalloc(&c->dt, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&c->t, sizeof(double) * n) != hipSuccess ||
@@ -3181,7 +3207,7 @@ mp_status mp_weno_rhs_noalloc(const mp_weno_instance* inst, const mp_weno_opts* 
   d.vol = 1.0;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, st, d, ddesc);
-  table().rhs1[N][D][o.precision](ddesc, d.g, st);
+  table().rhs1[o.recon >= MP_RECON_WENO_JS][N][D][o.precision](ddesc, d.g, st);
   return hipGetLastError() == hipSuccess ? MP_OK : MP_ERR_HIP;
 }
 
@@ -3355,23 +3381,28 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
     return fail(c, MP_ERR_HIP, "hipEventCreate failed");
   }
   mp_status st = MP_OK;
+  // the comparison schemes are built with the default shapes only: for them
+  // only the tile order is chosen
+  const int cmp = c->opt.recon >= MP_RECON_WENO_JS;
+  const int v = cmp ? kRiemannCmp : kRiemann;
+  const int nxv = cmp ? 1 : kXVar;
   for (Group& G : c->groups) {
     // every candidate timed in two interleaved rounds, the faster one kept:
     // a single round is at the mercy of clock and neighbour noise
-    const int nyv = G.D >= 2 ? kYVar : 1;
+    const int nyv = G.D >= 2 && !cmp ? kYVar : 1;
     float tmin[kXVar][kYVar][2];
     for (auto& a : tmin)
       for (auto& b : a) b[0] = b[1] = INFINITY;
     for (int round = 0; round < 2 && st == MP_OK; ++round)
-      for (int xv = 0; xv < kXVar && st == MP_OK; ++xv)
+      for (int xv = 0; xv < nxv && st == MP_OK; ++xv)
         for (int yv = 0; yv < nyv && st == MP_OK; ++yv)
           for (int sw = 0; sw < 2 && st == MP_OK; ++sw) {
             auto run = [&]() {
-              T.sx[0][G.N][G.D][prec][xv](G, 3, sw, c->stream);
-              if (G.D == 2) T.sy[0][G.N][prec][yv](G, 3, sw, c->stream);
+              T.sx[v][G.N][G.D][prec][xv](G, 3, sw, c->stream);
+              if (G.D == 2) T.sy[v][G.N][prec][yv](G, 3, sw, c->stream);
               if (G.D == 3) {
-                T.sy3[G.N][prec][yv](G, 3, sw, c->stream);
-                T.sz3[G.N][prec][yv](G, 3, sw, c->stream);
+                T.sy3[cmp][G.N][prec][yv](G, 3, sw, c->stream);
+                T.sz3[cmp][G.N][prec][yv](G, 3, sw, c->stream);
               }
             };
             run();   // warm-up
@@ -3388,7 +3419,7 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
           }
     float best = INFINITY;
     int bx = 0, by = 0, bs = 0;
-    for (int xv = 0; xv < kXVar; ++xv)
+    for (int xv = 0; xv < nxv; ++xv)
       for (int yv = 0; yv < nyv; ++yv)
         for (int sw = 0; sw < 2; ++sw)
           if (tmin[xv][yv][sw] < best) { best = tmin[xv][yv][sw]; bx = xv; by = yv; bs = sw; }

@@ -428,14 +428,22 @@ __device__ __forceinline__ void consistent_limiter(const double* S,
 // never sits in registers as a whole); ub: conserved average of cell i.  Outputs: fm = U^R_{i-1/2} (the cell's
 // face on the minus side), fp = U^L_{i+1/2} (plus side), each with its face
 // primitives, density and sound speed.  hdx = dx/2 of the direction.
-template <int N, int D, typename W, typename S>
+// RS: the reconstructions compiled in: kReconC (WENO-C and WENO-CL, chosen
+// by g.recon), kReconCmp (the comparison schemes WENO-JS and WENO-W) or
+// kReconAny (all four, chosen at run time).  Keeping the comparison schemes
+// out of the WENO-C kernels keeps their register use, and so their
+// occupancy, what the method alone needs.
+constexpr int kReconC = 0, kReconCmp = 1, kReconAny = 2;
+
+template <int N, int D, typename W, int RS, typename S>
 __device__ __forceinline__ void reconstruct(const S& st,
                                             const Cons<N, D>& ub,
                                             const Eos& e, const Grid& g,
                                             double hdx, Face<N, D>& fm,
                                             Face<N, D>& fp) {
   constexpr bool MIXED = sizeof(W) == 4;
-  if (g.recon >= 2) {
+  const bool cmp = RS == kReconCmp || (RS == kReconAny && g.recon >= 2);
+  if (cmp) {
     // comparison schemes: every primitive with its own weights, no limiter
     const bool js = g.recon == 2;
 #pragma unroll
@@ -582,7 +590,7 @@ __device__ __forceinline__ void reconstruct(const S& st,
     f.rho = rho;
   }
 
-  if (g.energy && g.recon < 2) {
+  if (g.energy && !cmp) {
     // Eq. (21): one theta^psi from psi at Ubar, U^L, U^R and U^C
     double cm[N], ca[N], cmom[D];
 #pragma unroll
