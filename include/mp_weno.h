@@ -315,6 +315,12 @@ mp_status mp_weno_advance(mp_weno_ctx *ctx, int32_t nsteps);
 
 /* Diagnostics per instance, MP_DIAG_LEN doubles each (out[i*MP_DIAG_LEN+k]):
  *   k = 0 .. n_U-1 : sum over cells of U_c times the cell volume
+ *   k = 18, 19     : the two integrals of the interface thickness N_I of
+ *                    Eq. (30) for alpha_1: the volume of the cells with
+ *                    0.05 <= alpha_1 <= 0.95, and the integral of
+ *                    |grad alpha_1| (central differences inside, one-sided
+ *                    ones at the two ends of each direction), so that
+ *                    N_I = out[18] / (min_d dx_d * out[19])
  *   k = 20         : max over cells |sum_p alpha_p - 1|
  *   k = 21, 22, 23 : min m_p, min alpha_p, max alpha_p over cells and phases
  *   k = 24         : min over cells of psi(U) (Eq. (9))

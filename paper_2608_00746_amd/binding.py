@@ -319,6 +319,49 @@ class Solver:
         self.torch.cuda.synchronize(self.device)
         return self.U[i].cpu().numpy()
 
+    def interface_thickness(self, diag=None):
+        """N_I of Eq. (30) for alpha_1 per instance, from the diagnostics'
+        two integrals (slots 18 and 19)."""
+        d = self.diag() if diag is None else diag
+        out = np.zeros(len(self.U))
+        for i, w in enumerate(self.w):
+            den = min(w.dx) * d[i, 19]
+            out[i] = d[i, 18] / den if den > 0.0 else 0.0
+        return out
+
+    def checkpoint(self, path=None):
+        """The state that decides every later step: the instances' U and
+        times (and, for the record, their step counts).  A context holds no
+        other state the hyperbolic step reads; with the Phase-Field step the
+        solve of Eq. (4) starts from the previous step's Q, which a
+        checkpoint does not hold (a resumed run then matches to the solver
+        tolerance, not bitwise).  path: also written there as .npz."""
+        d = self.diag()
+        ck = {"t": d[:, 26].copy(), "steps": d[:, 27].copy()}
+        for i in range(len(self.U)):
+            ck["U%d" % i] = self.host(i).copy()
+        if path is not None:
+            np.savez(path, **ck)
+        return ck
+
+    def restore(self, ck):
+        """Load a checkpoint (dict or .npz path) into this context: the
+        states are copied into the device buffers in place and the times
+        set.  The step count is the context's own."""
+        if not isinstance(ck, dict):
+            with np.load(ck, allow_pickle=False) as f:
+                ck = {k: f[k] for k in f.files}
+        if len(ck["t"]) != len(self.U):
+            raise ValueError("checkpoint of %d instances for %d" % (len(ck["t"]), len(self.U)))
+        self.torch.cuda.synchronize(self.device)
+        for i, u in enumerate(self.U):
+            src = np.ascontiguousarray(ck["U%d" % i], dtype=np.float64)
+            if src.size != u.numel():
+                raise ValueError("instance %d: %d values for %d" % (i, src.size, u.numel()))
+            u.copy_(self.torch.from_numpy(src.reshape(u.shape)))
+        self.torch.cuda.synchronize(self.device)
+        self.set_time(ck["t"])
+
     def close(self):
         if self.ctx:
             lib().mp_weno_destroy(self.ctx)

@@ -958,7 +958,10 @@ __global__ void k_advance_time(double* t, double* steps, const double* dt, int n
   }
 }
 
-// per-workgroup diagnostics: slots 0..nU-1 sums, then
+// per-workgroup diagnostics: slots 0..nU-1 sums, [18], [19] the two
+// integrals of the interface thickness of Eq. (30) for alpha_1 (cells with
+// 0.05 <= alpha_1 <= 0.95; |grad alpha_1| by central differences inside
+// and one-sided ones at the ends of each direction), then
 // [20] max|sum a - 1|, [21] min m, [22] min a, [23] max a, [24] min psi,
 // [25] non-finite count, [28] max |rho E|
 template <int N, int D>
@@ -966,6 +969,7 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
                                                     const int2* __restrict__ map,
                                                     int ninst, double* __restrict__ part) {
   constexpr int NU = 2 * N + D + 1;
+  static_assert(NU <= 18, "the totals share the slots below the interface integrals");
   __shared__ double sh[kRedBlock];
   const int2 it = locate(map, ninst, blockIdx.x);
   const Desc& d = descs[it.x];
@@ -1001,6 +1005,27 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
     acc[24] = fmin(acc[24], psi<N, D>(u, u + N + D + 1, u + N, u[N + D], e));
     acc[25] += nonfin;
     acc[28] = fmax(acc[28], fabs(u[N + D]));
+    // interface thickness integrals of alpha_1
+    const double a1 = u[N + D + 1];
+    if (a1 >= 0.05 && a1 <= 0.95) acc[18] += 1.0;
+    const gdouble* A = U + (int64_t)(N + D + 1) * g.nc;
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    const int z = (int)(i / plane);
+    const int64_t r = i - (int64_t)z * plane;
+    const int y = (int)(r / g.nx), x = (int)(r - (int64_t)y * g.nx);
+    double g2 = 0.0;
+    auto grad = [&](int k, int n, int64_t st, double rd) {
+      if (n < 2) return;
+      double v;
+      if (k == 0) v = (A[i + st] - A[i]) * rd;
+      else if (k == n - 1) v = (A[i] - A[i - st]) * rd;
+      else v = (A[i + st] - A[i - st]) * (0.5 * rd);
+      g2 += v * v;
+    };
+    grad(x, g.nx, 1, g.rdx);
+    if constexpr (D >= 2) grad(y, g.ny, g.nx, g.rdy);
+    if constexpr (D >= 3) grad(z, g.nz, plane, g.rdz);
+    acc[19] += sqrt(g2);
   }
   // fixed-order tree per slot
   for (int k = 0; k < kDiagSlots; ++k) {
