@@ -99,6 +99,7 @@ constexpr double kPfsStallIts = 50.0;
 // also count against the LDS wait counter).  They always point to global
 // memory; these types say so.
 using gdouble = __attribute__((address_space(1))) double;
+using lds_void = __attribute__((address_space(3))) void;   // LDS destination of global_load_lds
 using gfloat = __attribute__((address_space(1))) float;
 __device__ __forceinline__ const gdouble* gptr(const double* p) { return (const gdouble*)p; }
 __device__ __forceinline__ gdouble* gptr(double* p) { return (gdouble*)p; }
@@ -252,11 +253,12 @@ __device__ __forceinline__ void one_plus_k(const Cons<N, D>& ub, const Eos& e,
   }
 }
 
-// RK epilogue for one cell: L in component order; writes out.
-template <int N, int D>
+// RK epilogue for one cell: L in component order; writes out (U^n of the
+// cell read through un(c), in stages that need it).
+template <int N, int D, typename UnF>
 __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
                                             int64_t idx, const Cons<N, D>& uk,
-                                            const double* L) {
+                                            const double* L, UnF un) {
   constexpr int NU = 2 * N + D + 1;
   if (a.mode == 0) {
 #pragma unroll
@@ -275,11 +277,16 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
     for (int c = 0; c < NU; ++c) a.out[(int64_t)c * nc + idx] = a.b * (u[c] + dt * L[c]);
   } else {
 #pragma unroll
-    for (int c = 0; c < NU; ++c) {
-      const double un = a.Un[(int64_t)c * nc + idx];
-      a.out[(int64_t)c * nc + idx] = a.a * un + a.b * (u[c] + dt * L[c]);
-    }
+    for (int c = 0; c < NU; ++c) a.out[(int64_t)c * nc + idx] = a.a * un(c) + a.b * (u[c] + dt * L[c]);
   }
+}
+
+// the same with U^n read from the stage arguments
+template <int N, int D>
+__device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
+                                            int64_t idx, const Cons<N, D>& uk,
+                                            const double* L) {
+  finish_cell<N, D>(a, nc, idx, uk, L, [&](int c) { return a.Un[(int64_t)c * nc + idx]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -499,10 +506,17 @@ void k_sweep_t(const Desc* __restrict__ descs,
   constexpr int NU = NV;
   constexpr int NF = 2 * N + 2 * D + 4;
   constexpr int NFL = NU + 1;
-  constexpr int NPRIM = NV * (kTY + 4) * kTX, NFLX = NFL * kTY * kTX;
-  __shared__ double sraw[NPRIM > NFLX ? NPRIM : NFLX];
-  __shared__ double sface[NF][kTY][kTX];
+  // The primitive rows, then the minus-side face states, then the fluxes
+  // share one LDS area, each phase separated from the next by a barrier;
+  // the epilogue operands (the accumulator and, where the stage reads it,
+  // U^n) of the output rows have an area of their own, filled while the
+  // reconstruction runs.
+  constexpr int NPRIM = NV * (kTY + 4) * kTX, NFACE = NF * kTY * kTX, NFLX = NFL * kTY * kTX;
+  constexpr int NRAW = NPRIM > NFACE ? (NPRIM > NFLX ? NPRIM : NFLX) : (NFACE > NFLX ? NFACE : NFLX);
+  __shared__ double sraw[NRAW];
+  __shared__ double spre[2][NU][kOY][kTX];
   double (*sprim)[kTY + 4][kTX] = reinterpret_cast<double (*)[kTY + 4][kTX]>(sraw);
+  double (*sface)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(sraw);
   double (*sflux)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(sraw);
 
   const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
@@ -544,9 +558,40 @@ void k_sweep_t(const Desc* __restrict__ descs,
   if (ty >= kTY - 2) put_prim(yi + 2, ty + 4);
   __syncthreads();
 
+  // Epilogue operands of the tile's output rows straight into LDS
+  // (global_load_lds, 4 bytes a lane, 32 doubles a wave): nothing is held in
+  // registers while they are in flight, and the barrier after the
+  // reconstruction waits for them.  Rows and columns beyond the grid load
+  // its last row / column (in bounds; those cells are not written).
+  const bool need_un = kLast && a.mode == 1 && a.a != 0.0;
+  {
+    constexpr int kRPL = 32 / kTX;            // rows per wave-load
+    static_assert(32 % kTX == 0 && kOY % kRPL == 0, "prefetch shape");
+    constexpr int kLPC = kOY / kRPL;          // wave-loads per component
+    constexpr int kNW = kTX * kTY / 64;       // waves of the workgroup
+    const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int dbl = ln >> 1;                  // double of this lane in a wave-load
+    const int xq = min(txb * kTX + dbl % kTX, g.nx - 1);
+    int64_t off[kLPC];
+#pragma unroll
+    for (int k = 0; k < kLPC; ++k)
+      off[k] = pb + (int64_t)min(y0 + k * kRPL + dbl / kTX, nl - 1) * ls + xq;
+    const int ncomp = need_un ? 2 * NU : NU;
+    for (int q = wave; q < ncomp; q += kNW) {
+      const int arr = q >= NU, c = q - arr * NU;
+      const gdouble* arrp = arr ? a.Un : a.acc;
+      const char* src = (const char*)(const double*)(arrp + (int64_t)c * nc);
+#pragma unroll
+      for (int k = 0; k < kLPC; ++k)
+        __builtin_amdgcn_global_load_lds(src + off[k] * 8 + 4 * (ln & 1),
+                                         (lds_void*)&spre[arr][c][k * kRPL][0], 4, 0, 0);
+    }
+  }
+
   Face<N, D> fm, fp;
   reconstruct<N, D, W, kRecon<PFM>()>([&](int c, int j) { return sprim[c][ty + j][tx]; }, ub, e,
                                       g, hd, fm, fp);
+  __syncthreads();   // the primitive rows are read; the prefetch has landed
 
 #pragma unroll
   for (int p = 0; p < N; ++p) { sface[p][ty][tx] = fm.m[p]; sface[N + p][ty][tx] = fm.a[p]; }
@@ -585,6 +630,9 @@ void k_sweep_t(const Desc* __restrict__ descs,
     } else {
       riemann<N, D, W>(fp, R, DIR, g.flux, F);
     }
+  }
+  __syncthreads();   // the face states are read
+  if (ty < kTY - 1) {
 #pragma unroll
     for (int c = 0; c < NU; ++c) sflux[c][ty][tx] = F.f[c];
     sflux[NU][ty][tx] = F.uh;
@@ -597,13 +645,13 @@ void k_sweep_t(const Desc* __restrict__ descs,
     if constexpr (PFM == kPfFlux) {
 #pragma unroll
       for (int c = 0; c < NU; ++c)
-        L[c] = a.acc[(int64_t)c * nc + idx] + (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
+        L[c] = spre[0][c][ty - 1][tx] + (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
     } else {
       double opk[N];
       one_plus_k<N, D>(ub, e, g.model, opk);
 #pragma unroll
       for (int c = 0; c < NU; ++c)
-        L[c] = a.acc[(int64_t)c * nc + idx] - (F.f[c] - sflux[c][ty - 1][tx]) * rd;
+        L[c] = spre[0][c][ty - 1][tx] - (F.f[c] - sflux[c][ty - 1][tx]) * rd;
       const double du = (F.uh - sflux[NU][ty - 1][tx]) * rd;
       // alpha_p at the cell average, or alpha_p / sum_q alpha_q (then the
       // sources sum to du, as the fluxes' alpha parts do, and
@@ -619,7 +667,7 @@ void k_sweep_t(const Desc* __restrict__ descs,
       for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * isa * opk[p] * du;
     }
     if constexpr (kLast) {
-      finish_cell<N, D>(a, nc, idx, ub, L);
+      finish_cell<N, D>(a, nc, idx, ub, L, [&](int c) { return spre[1][c][ty - 1][tx]; });
     } else {
 #pragma unroll
       for (int c = 0; c < NU; ++c) a.acc[(int64_t)c * nc + idx] = L[c];
