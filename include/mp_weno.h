@@ -91,7 +91,7 @@ enum { MP_WHERE_DEVICE = 0, MP_WHERE_HOST = 1 };
 
 /* One uniform-grid problem instance (Sec. 2.1 and Eq. (26)). */
 typedef struct {
-  int32_t ndim;            /* 1, 2 or 3 (3: N <= 3, no Phase-Field step)    */
+  int32_t ndim;            /* 1, 2 or 3 (3: N <= 3)                         */
   int32_t n[3];            /* cells per direction, n[k] >= 1; unused = 1     */
   double dx[3];            /* uniform cell size per direction, > 0           */
   int32_t bc[3][2];        /* MP_BC_* at the low/high end of each direction  */
@@ -157,13 +157,12 @@ int32_t mp_weno_max_phases(void);
  * per instance (3 n_U doubles per cell) plus small reduction buffers; with
  * phase_field, (8 + d) N doubles per cell more (k_p, [div J_p], Q_p, the CG
  * vectors r, p, K p, w and u, and the face gradients) and the FP32
- * multigrid hierarchy (6 N floats per cell of every level: about 8 N floats
- * per cell in 2D, 12 N in 1D).
+ * multigrid hierarchy (6 N floats per cell of every level, 7 N in 3D:
+ * about 8 N floats per cell in 2D, 12 N in 1D and 8 N in 3D).
  * Errors: MP_ERR_ARG (ndim outside 1..3, bad sizes, gamma <= 1, dx <= 0, a
  * boundary code out of range, periodic at one end of a direction only,
  * phase_field with eta_over_dx <= 0, ...), MP_ERR_UNSUPPORTED (valid but
- * beyond the build: N > mp_weno_max_phases(), or in 3D N > 3 or
- * phase_field),
+ * beyond the build: N > mp_weno_max_phases(), or in 3D N > 3),
  * MP_ERR_OOM, MP_ERR_HIP.
  * On error *ctx is NULL. */
 mp_status mp_weno_init(mp_weno_ctx **ctx, int32_t n_inst,

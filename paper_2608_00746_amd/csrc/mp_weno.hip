@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
@@ -118,17 +119,18 @@ struct StageArgs {
 
 // One level of the multigrid preconditioner of Eq. (4) for one instance
 // (every array holds the N phases one after the other, [N][nc]).  Level 0 is
-// the grid itself; level l + 1 aggregates 2 x 2 cells of level l (a single
-// cell or row at an odd end) down to one cell.  The preconditioner works in
+// the grid itself; level l + 1 aggregates 2 x 2 (3D: 2 x 2 x 2) cells of
+// level l (a single cell or row at an odd end) down to one cell.  The preconditioner works in
 // FP32 (half the bytes of every pass; CG, its residual and the convergence
 // test stay FP64): level 0 reads the FP64 CG residual once, scaled by a power
 // of two near the rms of [div J_p] (exact, and far from the FP32 range
 // limits), and writes the FP64 preconditioned residual once, scaled back.
 struct MgLevel {
-  int nx, ny;
+  int nx, ny, nz;
   int64_t nc;
   float* wx;         // weight of the face to the +x neighbour (0: no face)
   float* wy;         // weight of the face to the +y neighbour
+  float* wz;         // weight of the face to the +z neighbour (3D)
   float* dg;         // diagonal: sum of the cell's face weights
   float* e;          // correction
   float* t;          // Jacobi ping-pong
@@ -294,9 +296,11 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
 // ---------------------------------------------------------------------------
 // Waves per SIMD the sweeps are compiled for: one or two phases fit 3 (or 4)
 // waves in the register file with at most a few spilled values, which hides
-// FP64 latency better than 2 waves (measured +7..10 % on N = 2 in 2D); two
-// phases in 3D, three and four phases would spill heavily at 3 and keep 2;
-// five need the AGPRs too.
+// FP64 latency better than 2 waves (measured +7..10 % on N = 2 in 2D); the x
+// sweep of three phases in 2D on the mixed path also runs at 3 (spilling
+// some values: +2 % on the batch; the transverse sweep's LDS allows only 2
+// there); two phases in 3D, three and four phases otherwise would spill
+// heavily at 3 and keep 2; five need the AGPRs too.
 // The flux and reconstruction variants of the sweeps (template PFM):
 // kRiemann: Riemann flux, WENO-C / WENO-CL; kPfFlux: the Phase-Field flux
 // (any reconstruction); kRiemannCmp: Riemann flux with the comparison
@@ -307,14 +311,15 @@ constexpr int kRecon() {
   return PFM == kRiemann ? kReconC : (PFM == kRiemannCmp ? kReconCmp : kReconAny);
 }
 
-template <int N, int D>
+template <int N, int D, typename W, int PFM, bool XSWEEP>
 constexpr int sweep_waves() {
+  if (N == 3 && D == 2 && sizeof(W) == 4 && PFM == 0 && XSWEEP) return 3;
   return N == 1 ? (D == 1 ? 4 : 3) : (N == 2 ? (D == 3 ? 2 : 3) : (N <= 4 ? 2 : 1));
 }
 
 template <int N, int D, typename W, int PFM, int BX>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, BX),
-                          amdgpu_waves_per_eu(sweep_waves<N, D>(), 8)))
+                          amdgpu_waves_per_eu(sweep_waves<N, D, W, PFM, true>(), 8)))
 void k_sweep_x(const Desc* __restrict__ descs,
                                                  const int2* __restrict__ map,
                                                  int ninst, int stage, int swz) {
@@ -477,11 +482,11 @@ void k_sweep_x(const Desc* __restrict__ descs,
 
 template <int N, typename W, int PFM, int kTX, int kTY, int D, int DIR>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kTX * kTY),
-                          amdgpu_waves_per_eu(sweep_waves<N, D>(), 8)))
+                          amdgpu_waves_per_eu(sweep_waves<N, D, W, PFM, false>(), 8)))
 void k_sweep_t(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map,
                                                        int ninst, int stage, int swz) {
-  static_assert(D >= 2 && DIR >= 1 && DIR < D && (PFM != kPfFlux || D == 2), "sweep shape");
+  static_assert(D >= 2 && DIR >= 1 && DIR < D, "sweep shape");
   constexpr bool kLast = DIR == D - 1;
   const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));
   const Desc d = descs[it.x];
@@ -616,15 +621,17 @@ void k_sweep_t(const Desc* __restrict__ descs,
     R.rho = sface[2 * N + 2 * D + 2][r][tx];
     R.c = sface[2 * N + 2 * D + 3][r][tx];
     if constexpr (PFM == kPfFlux) {
-      const int yo = yi < 0 ? (g.bcy0 == MP_BC_PERIODIC ? g.ny - 1 : -1) : (yi < g.ny ? yi : -1);
-      const int yq = yo < 0 ? -1 : (yo + 1 < g.ny ? yo + 1 : (g.bcy1 == MP_BC_PERIODIC ? 0 : -1));
+      // gradient at the upper face of line cell yi (as in the x sweep)
+      const int yo = yi < 0 ? (blo == MP_BC_PERIODIC ? nl - 1 : -1) : (yi < nl ? yi : -1);
+      const int yq = yo < 0 ? -1 : (yo + 1 < nl ? yo + 1 : (bhi == MP_BC_PERIODIC ? 0 : -1));
+      const int64_t co = pb + (int64_t)yo * ls + xc, cq = pb + (int64_t)yq * ls + xc;
       double G[N], kf[N];
 #pragma unroll
       for (int p = 0; p < N; ++p) {
         const bool in = yq >= 0;
-        G[p] = in ? gptr(d.pf_g)[(int64_t)(N + p) * nc + (int64_t)yo * g.nx + xc] : 0.0;
-        kf[p] = in ? 0.5 * (gptr(d.pf_k)[(int64_t)p * nc + (int64_t)yo * g.nx + xc] +
-                            gptr(d.pf_k)[(int64_t)p * nc + (int64_t)yq * g.nx + xc]) : 0.0;
+        G[p] = in ? gptr(d.pf_g)[(int64_t)(DIR * N + p) * nc + co] : 0.0;
+        kf[p] = in ? 0.5 * (gptr(d.pf_k)[(int64_t)p * nc + co] +
+                            gptr(d.pf_k)[(int64_t)p * nc + cq]) : 0.0;
       }
       pf_flux<N, D>(fp, R, G, kf, e, F);
     } else {
@@ -645,7 +652,7 @@ void k_sweep_t(const Desc* __restrict__ descs,
     if constexpr (PFM == kPfFlux) {
 #pragma unroll
       for (int c = 0; c < NU; ++c)
-        L[c] = spre[0][c][ty - 1][tx] + (F.f[c] - sflux[c][ty - 1][tx]) * g.rdy;
+        L[c] = spre[0][c][ty - 1][tx] + (F.f[c] - sflux[c][ty - 1][tx]) * rd;
     } else {
       double opk[N];
       one_plus_k<N, D>(ub, e, g.model, opk);
@@ -1198,34 +1205,54 @@ __device__ __forceinline__ double reduce_chunks(const double* __restrict__ part,
 }
 
 // neighbour of cell (x, y) one step along dir (+1 / -1); -1 if no face there
-__device__ __forceinline__ int64_t nbr(const Grid& g, int D, int x, int y, int dir, int s) {
+__device__ __forceinline__ int64_t nbr(const Grid& g, int x, int y, int z, int dir, int s) {
+  const int64_t plane = (int64_t)g.nx * g.ny;
   if (dir == 0) {
     int xn = x + s;
     if (xn < 0) { if (g.bcx0 != MP_BC_PERIODIC) return -1; xn += g.nx; }
     if (xn >= g.nx) { if (g.bcx1 != MP_BC_PERIODIC) return -1; xn -= g.nx; }
-    return (int64_t)y * g.nx + xn;
+    return z * plane + (int64_t)y * g.nx + xn;
   }
-  (void)D;
-  int yn = y + s;
-  if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += g.ny; }
-  if (yn >= g.ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= g.ny; }
-  return (int64_t)yn * g.nx + x;
+  if (dir == 1) {
+    int yn = y + s;
+    if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += g.ny; }
+    if (yn >= g.ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= g.ny; }
+    return z * plane + (int64_t)yn * g.nx + x;
+  }
+  int zn = z + s;
+  if (zn < 0) { if (g.bcz0 != MP_BC_PERIODIC) return -1; zn += g.nz; }
+  if (zn >= g.nz) { if (g.bcz1 != MP_BC_PERIODIC) return -1; zn -= g.nz; }
+  return zn * plane + (int64_t)y * g.nx + x;
+}
+
+// coordinates of cell i (x fastest, then y, then z)
+__device__ __forceinline__ void cell_xyz(const Grid& g, int64_t i, int& x, int& y, int& z) {
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  z = (int)(i / plane);
+  const int64_t r = i - z * plane;
+  y = (int)(r / g.nx);
+  x = (int)(r - (int64_t)y * g.nx);
+}
+
+// 1 / dx of direction dir
+__device__ __forceinline__ double grid_rd(const Grid& g, int dir) {
+  return dir == 0 ? g.rdx : (dir == 1 ? g.rdy : g.rdz);
 }
 
 // (K v)_i and (|K| |v|)_i for phase p at cell i
 template <int D>
 __device__ __forceinline__ void k_apply(const Grid& g, const gdouble* __restrict__ k,
                                         const gdouble* __restrict__ v, int64_t i, int x, int y,
-                                        double& Kv, double& aKv) {
+                                        int z, double& Kv, double& aKv) {
   Kv = 0.0;
   aKv = 0.0;
   const double ki = k[i], vi = v[i];
 #pragma unroll
   for (int dir = 0; dir < D; ++dir) {
-    const double r2 = dir == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
+    const double r2 = grid_rd(g, dir) * grid_rd(g, dir);
 #pragma unroll
     for (int s = -1; s <= 1; s += 2) {
-      const int64_t j = nbr(g, D, x, y, dir, s);
+      const int64_t j = nbr(g, x, y, z, dir, s);
       if (j >= 0) {
         const double kf = 0.5 * (ki + k[j]) * r2;
         Kv += kf * (vi - v[j]);
@@ -1383,7 +1410,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
 #pragma unroll
   for (int k = 0; k < 3 * N; ++k) acc[k] = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
-    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+    int x, y, z;
+    cell_xyz(g, i, x, y, z);
     double phi[N], sg = 0.0;
 #pragma unroll
     for (int p = 0; p < N; ++p) {
@@ -1396,10 +1424,10 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
       double lap = 0.0;
 #pragma unroll
       for (int dir = 0; dir < D; ++dir) {
-        const int64_t lo = nbr(g, D, x, y, dir, -1), hi = nbr(g, D, x, y, dir, 1);
+        const int64_t lo = nbr(g, x, y, z, dir, -1), hi = nbr(g, x, y, z, dir, 1);
         const double fl = lo >= 0 ? f[lo] : phi[p];    // outflow: zero gradient
         const double fh = hi >= 0 ? f[hi] : phi[p];
-        const double r2 = dir == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
+        const double r2 = grid_rd(g, dir) * grid_rd(g, dir);
         lap += (fh - 2.0 * phi[p] + fl) * r2;
       }
       double Lc = 0.0;
@@ -1414,7 +1442,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
       if (cold)
         gptr(d.pf_q)[ip] = 0.0;
       else
-        k_apply<D>(g, K + (int64_t)p * nc, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, Kq, aKq);
+        k_apply<D>(g, K + (int64_t)p * nc, gptr(d.pf_q) + (int64_t)p * nc, i, x, y, z, Kq, aKq);
       const double r = -b - Kq;
       gptr(d.pf_r)[ip] = r;
       acc[p] += b * b;
@@ -1527,7 +1555,8 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dir(const Desc* __restrict_
 #pragma unroll
   for (int k = 0; k < N; ++k) acc[k] = 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
-    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+    int x, y, z;
+    cell_xyz(g, i, x, y, z);
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       if (!live[p]) continue;
@@ -1543,10 +1572,10 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dir(const Desc* __restrict_
       const double ki = K[i];
 #pragma unroll
       for (int dd = 0; dd < D; ++dd) {
-        const double r2 = dd == 0 ? g.rdx * g.rdx : g.rdy * g.rdy;
+        const double r2 = grid_rd(g, dd) * grid_rd(g, dd);
 #pragma unroll
         for (int sg = -1; sg <= 1; sg += 2) {
-          const int64_t j = nbr(g, D, x, y, dd, sg);
+          const int64_t j = nbr(g, x, y, z, dd, sg);
           if (j >= 0) q += 0.5 * (ki + K[j]) * r2 * (pi - dir_at(j));
         }
       }
@@ -1723,26 +1752,16 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_beta(const Desc* __restrict
 constexpr int kMgMaxLev = 16;
 constexpr int kMgCoarseSweeps = 8;    // sweeps on the coarsest level (even)
 // damping of the Jacobi smoother: the value with the best smoothing factor
-// for the model operator, 2/3 for the 1D three-point and 4/5 for the 2D
-// five-point Laplacian
+// for the model operator, 2 d / (2 d + 1): 2/3 for the 1D three-point, 4/5
+// for the 2D five-point and 6/7 for the 3D seven-point Laplacian
 template <int D>
-constexpr double mg_omega() { return D == 1 ? 2.0 / 3.0 : 0.8; }
+constexpr double mg_omega() { return D == 1 ? 2.0 / 3.0 : (D == 2 ? 0.8 : 6.0 / 7.0); }
 
-// neighbour of cell (x, y) of a level one step along dir; -1 if no face
-__device__ __forceinline__ int64_t lnbr(const Grid& g, int nx, int ny, int x, int y, int dir, int s) {
-  if (dir == 0) {
-    if (nx == 1) return -1;                 // one aggregate: no face
-    int xn = x + s;
-    if (xn < 0) { if (g.bcx0 != MP_BC_PERIODIC) return -1; xn += nx; }
-    if (xn >= nx) { if (g.bcx1 != MP_BC_PERIODIC) return -1; xn -= nx; }
-    return (int64_t)y * nx + xn;
-  }
-  if (ny == 1) return -1;
-  int yn = y + s;
-  if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += ny; }
-  if (yn >= ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= ny; }
-  return (int64_t)yn * nx + x;
-}
+// arrays of a level in the LDS image of the fused cycle: the face weights of
+// each direction (at least x and y), the diagonal, e, t and f
+template <int D>
+constexpr int mg_lds_arrays() { return D > 2 ? 7 : 6; }
+
 
 // A level's arrays are read and written in global memory (AS = 1) by the
 // per-level kernels, or in the LDS copy of the fused coarse cycle (AS = 3).
@@ -1751,52 +1770,71 @@ using lfloat = __attribute__((address_space(AS))) float;
 template <int AS>
 __device__ __forceinline__ lfloat<AS>* lp(float* p) { return (lfloat<AS>*)p; }
 
-// lnbr that also gives the neighbour's coordinates
-__device__ __forceinline__ int lnbr_xy(const Grid& g, int nx, int ny, int x, int y, int dir,
-                                       int s, int& xn, int& yn) {
+// neighbour of cell (x, y, z) of a level one step along dir, with its
+// coordinates; -1 if there is no face (an outflow or symmetry end, or a
+// direction one aggregate wide)
+__device__ __forceinline__ int lnbr_xyz(const Grid& g, const MgLevel& L, int x, int y, int z,
+                                        int dir, int s, int& xn, int& yn, int& zn) {
   xn = x;
   yn = y;
+  zn = z;
   if (dir == 0) {
-    if (nx == 1) return -1;
+    if (L.nx == 1) return -1;
     xn = x + s;
-    if (xn < 0) { if (g.bcx0 != MP_BC_PERIODIC) return -1; xn += nx; }
-    if (xn >= nx) { if (g.bcx1 != MP_BC_PERIODIC) return -1; xn -= nx; }
-  } else {
-    if (ny == 1) return -1;
+    if (xn < 0) { if (g.bcx0 != MP_BC_PERIODIC) return -1; xn += L.nx; }
+    if (xn >= L.nx) { if (g.bcx1 != MP_BC_PERIODIC) return -1; xn -= L.nx; }
+  } else if (dir == 1) {
+    if (L.ny == 1) return -1;
     yn = y + s;
-    if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += ny; }
-    if (yn >= ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= ny; }
+    if (yn < 0) { if (g.bcy0 != MP_BC_PERIODIC) return -1; yn += L.ny; }
+    if (yn >= L.ny) { if (g.bcy1 != MP_BC_PERIODIC) return -1; yn -= L.ny; }
+  } else {
+    if (L.nz == 1) return -1;
+    zn = z + s;
+    if (zn < 0) { if (g.bcz0 != MP_BC_PERIODIC) return -1; zn += L.nz; }
+    if (zn >= L.nz) { if (g.bcz1 != MP_BC_PERIODIC) return -1; zn -= L.nz; }
   }
-  return yn * nx + xn;
+  return (zn * L.ny + yn) * L.nx + xn;
 }
 
-// (K v)_i of a level from its face weights; val(j, x_j, y_j) gives v at a
-// cell of the level
+__device__ __forceinline__ int lnbr(const Grid& g, const MgLevel& L, int x, int y, int z,
+                                    int dir, int s) {
+  int xn, yn, zn;
+  return lnbr_xyz(g, L, x, y, z, dir, s, xn, yn, zn);
+}
+
+// coordinates of cell i of a level (levels hold < 2^31 cells)
+__device__ __forceinline__ void lcell(const MgLevel& L, int i, int& x, int& y, int& z) {
+  const int plane = L.nx * L.ny;
+  z = i / plane;
+  const int r = i - z * plane;
+  y = r / L.nx;
+  x = r - y * L.nx;
+}
+
+// (K v)_i of a level from its face weights; val(j, x_j, y_j, z_j) gives v
+// at a cell of the level
 template <int D, int AS, typename V>
 __device__ __forceinline__ float lapply_v(const Grid& g, const MgLevel& L, int p, int i, int x,
-                                          int y, V val) {
-  const lfloat<AS>* wx = lp<AS>(L.wx) + (int64_t)p * L.nc;
-  const lfloat<AS>* wy = lp<AS>(L.wy) + (int64_t)p * L.nc;
-  const float vi = val(i, x, y);
+                                          int y, int z, V val) {
+  const float vi = val(i, x, y, z);
   float r = 0.0f;
-  int xn, yn;
-  int j = lnbr_xy(g, L.nx, L.ny, x, y, 0, 1, xn, yn);
-  if (j >= 0) r += wx[i] * (vi - val(j, xn, yn));
-  j = lnbr_xy(g, L.nx, L.ny, x, y, 0, -1, xn, yn);
-  if (j >= 0) r += wx[j] * (vi - val(j, xn, yn));
-  if constexpr (D > 1) {
-    j = lnbr_xy(g, L.nx, L.ny, x, y, 1, 1, xn, yn);
-    if (j >= 0) r += wy[i] * (vi - val(j, xn, yn));
-    j = lnbr_xy(g, L.nx, L.ny, x, y, 1, -1, xn, yn);
-    if (j >= 0) r += wy[j] * (vi - val(j, xn, yn));
+#pragma unroll
+  for (int dir = 0; dir < D; ++dir) {
+    const lfloat<AS>* w = lp<AS>(dir == 0 ? L.wx : (dir == 1 ? L.wy : L.wz)) + (int64_t)p * L.nc;
+    int xn, yn, zn;
+    int j = lnbr_xyz(g, L, x, y, z, dir, 1, xn, yn, zn);
+    if (j >= 0) r += w[i] * (vi - val(j, xn, yn, zn));
+    j = lnbr_xyz(g, L, x, y, z, dir, -1, xn, yn, zn);
+    if (j >= 0) r += w[j] * (vi - val(j, xn, yn, zn));
   }
   return r;
 }
 
 template <int D, int AS>
 __device__ __forceinline__ float lapply(const Grid& g, const MgLevel& L, int p, const lfloat<AS>* v,
-                                        int i, int x, int y) {
-  return lapply_v<D, AS>(g, L, p, i, x, y, [v](int j, int, int) { return (float)v[j]; });
+                                        int i, int x, int y, int z) {
+  return lapply_v<D, AS>(g, L, p, i, x, y, z, [v](int j, int, int, int) { return (float)v[j]; });
 }
 
 // per-level work items: (instance, chunk of 256 cells of that level)
@@ -1821,15 +1859,17 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_weights0(const Desc* __restric
   MG_PROLOGUE
   const MgLevel L = d.mg[0];
   if (i >= L.nc) return;
-  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
+  int x, y, z;
+  lcell(L, (int)i, x, y, z);
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     const gdouble* K = gptr(d.pf_k) + (int64_t)p * L.nc;
-    int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
-    gptr(L.wx)[(int64_t)p * L.nc + i] = j >= 0 ? (float)(0.5 * (K[i] + K[j]) * g.rdx * g.rdx) : 0.0f;
-    if constexpr (D > 1) {
-      j = lnbr(g, L.nx, L.ny, x, y, 1, 1);
-      gptr(L.wy)[(int64_t)p * L.nc + i] = j >= 0 ? (float)(0.5 * (K[i] + K[j]) * g.rdy * g.rdy) : 0.0f;
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir) {
+      const int j = lnbr(g, L, x, y, z, dir, 1);
+      const double rd = grid_rd(g, dir);
+      float* w = dir == 0 ? L.wx : (dir == 1 ? L.wy : L.wz);
+      gptr(w)[(int64_t)p * L.nc + i] = j >= 0 ? (float)(0.5 * (K[i] + K[j]) * rd * rd) : 0.0f;
     }
   }
 }
@@ -1842,21 +1882,35 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_coarsen(const Desc* __restrict
   MG_PROLOGUE
   const MgLevel F = d.mg[l], C = d.mg[l + 1];
   if (i >= C.nc) return;
-  const int Y = (int)(i / C.nx), X = (int)(i - (int64_t)Y * C.nx);
-  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
+  int X, Y, Z;
+  lcell(C, (int)i, X, Y, Z);
+  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1),
+            zt = min(2 * Z + 1, F.nz - 1);
+  const int z0 = 2 * Z, z1 = D > 2 ? zt : 0;
+  auto fi = [&](int x, int y, int z) { return ((int64_t)z * F.ny + y) * F.nx + x; };
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     const gfloat* wx = gptr(F.wx) + (int64_t)p * F.nc;
     const gfloat* wy = gptr(F.wy) + (int64_t)p * F.nc;
-    float cx = 0.0f, cy = 0.0f;
+    const gfloat* wz = gptr(F.wz) + (int64_t)p * F.nc;
+    float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+    // the fine faces between this aggregate and its +x (+y, +z) neighbour
     if (C.nx > 1)
-      for (int y = 2 * Y; y <= yt; ++y) cx += wx[(int64_t)y * F.nx + xr];
+      for (int z = z0; z <= z1; ++z)
+        for (int y = 2 * Y; y <= yt; ++y) cx += wx[fi(xr, y, z)];
     if constexpr (D > 1) {
       if (C.ny > 1)
-        for (int x = 2 * X; x <= xr; ++x) cy += wy[(int64_t)yt * F.nx + x];
+        for (int z = z0; z <= z1; ++z)
+          for (int x = 2 * X; x <= xr; ++x) cy += wy[fi(x, yt, z)];
+    }
+    if constexpr (D > 2) {
+      if (C.nz > 1)
+        for (int y = 2 * Y; y <= yt; ++y)
+          for (int x = 2 * X; x <= xr; ++x) cz += wz[fi(x, y, zt)];
     }
     gptr(C.wx)[(int64_t)p * C.nc + i] = cx;
     if constexpr (D > 1) gptr(C.wy)[(int64_t)p * C.nc + i] = cy;
+    if constexpr (D > 2) gptr(C.wz)[(int64_t)p * C.nc + i] = cz;
   }
 }
 
@@ -1868,21 +1922,18 @@ __global__ __launch_bounds__(kRedBlock) void k_mg_diag(const Desc* __restrict__ 
   MG_PROLOGUE
   const MgLevel L = d.mg[l];
   if (i >= L.nc) return;
-  const int y = (int)(i / L.nx), x = (int)(i - (int64_t)y * L.nx);
+  int x, y, z;
+  lcell(L, (int)i, x, y, z);
 #pragma unroll
   for (int p = 0; p < N; ++p) {
-    const gfloat* wx = gptr(L.wx) + (int64_t)p * L.nc;
-    const gfloat* wy = gptr(L.wy) + (int64_t)p * L.nc;
     float dgv = 0.0f;
-    int64_t j = lnbr(g, L.nx, L.ny, x, y, 0, 1);
-    if (j >= 0) dgv += wx[i];
-    j = lnbr(g, L.nx, L.ny, x, y, 0, -1);
-    if (j >= 0) dgv += wx[j];
-    if constexpr (D > 1) {
-      j = lnbr(g, L.nx, L.ny, x, y, 1, 1);
-      if (j >= 0) dgv += wy[i];
-      j = lnbr(g, L.nx, L.ny, x, y, 1, -1);
-      if (j >= 0) dgv += wy[j];
+#pragma unroll
+    for (int dir = 0; dir < D; ++dir) {
+      const gfloat* w = gptr(dir == 0 ? L.wx : (dir == 1 ? L.wy : L.wz)) + (int64_t)p * L.nc;
+      int j = lnbr(g, L, x, y, z, dir, 1);
+      if (j >= 0) dgv += w[i];
+      j = lnbr(g, L, x, y, z, dir, -1);
+      if (j >= 0) dgv += w[j];
     }
     gptr(L.dg)[(int64_t)p * L.nc + i] = dgv;
   }
@@ -1909,7 +1960,8 @@ __device__ __forceinline__ void mg_smooth_cell(const Desc& d, const MgLevel& L, 
                                                int i, int mode, const MgLevel* C = nullptr,
                                                float corr = 0.0f) {
   const Grid& g = d.g;
-  const int y = i / L.nx, x = i - y * L.nx;          // levels hold < 2^31 cells
+  int x, y, z;
+  lcell(L, i, x, y, z);
   const int64_t ip = (int64_t)p * L.nc + i;
   const float dgv = lp<AS>(L.dg)[ip];
   const float w = (float)mg_omega<D>();
@@ -1928,15 +1980,17 @@ __device__ __forceinline__ void mg_smooth_cell(const Desc& d, const MgLevel& L, 
   if (mode == 5) {
     const lfloat<AS>* e = lp<AS>(L.e) + (int64_t)p * L.nc;
     const lfloat<AS>* ec = lp<AS>(C->e) + (int64_t)p * C->nc;
-    const int cnx = C->nx;
-    auto ep = [=](int j, int xj, int yj) { return e[j] + corr * ec[(yj >> 1) * cnx + (xj >> 1)]; };
-    const float ei = ep(i, x, y);
-    const float kv = lapply_v<D, AS>(g, L, p, i, x, y, ep);
+    const int cnx = C->nx, cny = C->ny;
+    auto ep = [=](int j, int xj, int yj, int zj) {
+      return e[j] + corr * ec[((zj >> 1) * cny + (yj >> 1)) * cnx + (xj >> 1)];
+    };
+    const float ei = ep(i, x, y, z);
+    const float kv = lapply_v<D, AS>(g, L, p, i, x, y, z, ep);
     (lp<AS>(L.t) + (int64_t)p * L.nc)[i] = dgv > 0.0f ? ei + w * (fv - kv) / dgv : ei;
     return;
   }
   const lfloat<AS>* src = lp<AS>(mode == 1 ? L.e : L.t) + (int64_t)p * L.nc;
-  const float kv = lapply<D, AS>(g, L, p, src, i, x, y);
+  const float kv = lapply<D, AS>(g, L, p, src, i, x, y, z);
   const float v = dgv > 0.0f ? src[i] + w * (fv - kv) / dgv : src[i];
   if (mode == 4)
     gptr(d.pf_u)[ip] = ldexp((double)v, mg_scale_exp(gptr(d.pfs), p, L.nc));
@@ -1950,16 +2004,19 @@ template <int D, int AS>
 __device__ __forceinline__ void mg_restrict_cell(const Grid& g, const MgLevel& F,
                                                  const MgLevel& C, int p, int i,
                                                  bool smooth0) {
-  const int Y = i / C.nx, X = i - Y * C.nx;
-  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1);
+  int X, Y, Z;
+  lcell(C, i, X, Y, Z);
+  const int xr = min(2 * X + 1, F.nx - 1), yt = min(2 * Y + 1, F.ny - 1),
+            zt = D > 2 ? min(2 * Z + 1, F.nz - 1) : 0;
   const lfloat<AS>* e = lp<AS>(F.e) + (int64_t)p * F.nc;
   const lfloat<AS>* f = lp<AS>(F.f) + (int64_t)p * F.nc;
   float r = 0.0f;
-  for (int y = 2 * Y; y <= yt; ++y)
-    for (int x = 2 * X; x <= xr; ++x) {
-      const int j = y * F.nx + x;
-      r += f[j] - lapply<D, AS>(g, F, p, e, j, x, y);
-    }
+  for (int z = 2 * Z; z <= zt; ++z)
+    for (int y = 2 * Y; y <= yt; ++y)
+      for (int x = 2 * X; x <= xr; ++x) {
+        const int j = (z * F.ny + y) * F.nx + x;
+        r += f[j] - lapply<D, AS>(g, F, p, e, j, x, y, z);
+      }
   const int64_t ci = (int64_t)p * C.nc + i;
   lp<AS>(C.f)[ci] = r;
   if (smooth0) {
@@ -2014,9 +2071,11 @@ constexpr int kMgFuseBlock = 1024;
 constexpr int kMgFusedStatic = 4096;     // bytes kept for its static LDS
 
 // level l's arrays in the LDS image, which holds levels lf .. l - 1 before it
+template <int D>
 __device__ __forceinline__ MgLevel mg_lds_level(const Desc& d, float* lds, int N, int lf, int l) {
+  constexpr int A = mg_lds_arrays<D>();
   int64_t off = 0;
-  for (int k = lf; k < l; ++k) off += 6 * (int64_t)N * d.mg[k].nc;
+  for (int k = lf; k < l; ++k) off += A * (int64_t)N * d.mg[k].nc;
   MgLevel L = d.mg[l];
   const int64_t f = (int64_t)N * L.nc;
   float* b = lds + off;
@@ -2026,6 +2085,7 @@ __device__ __forceinline__ MgLevel mg_lds_level(const Desc& d, float* lds, int N
   L.e = b + 3 * f;
   L.t = b + 4 * f;
   L.f = b + 5 * f;
+  if constexpr (D > 2) L.wz = b + 6 * f;
   return L;
 }
 
@@ -2050,14 +2110,15 @@ __global__ __launch_bounds__(kMgFuseBlock) void k_mg_fused(const Desc* __restric
   __shared__ MgLevel lv[kMgMaxLev];
   static_assert(sizeof(lv) <= kMgFusedStatic, "static LDS of the fused cycle");
   if (threadIdx.x >= lf && threadIdx.x < nlev)
-    lv[threadIdx.x] = mg_lds_level(d, mg_lds, N, lf, threadIdx.x);
+    lv[threadIdx.x] = mg_lds_level<D>(d, mg_lds, N, lf, threadIdx.x);
   for (int l = lf; l < nlev; ++l) {
     const MgLevel G = d.mg[l];
-    const MgLevel L = mg_lds_level(d, mg_lds, N, lf, l);
+    const MgLevel L = mg_lds_level<D>(d, mg_lds, N, lf, l);
     const int f = N * (int)G.nc;
     for (int i = threadIdx.x; i < f; i += kMgFuseBlock) {
       lp<3>(L.wx)[i] = gptr(G.wx)[i];
       lp<3>(L.wy)[i] = gptr(G.wy)[i];
+      if constexpr (D > 2) lp<3>(L.wz)[i] = gptr(G.wz)[i];
       lp<3>(L.dg)[i] = gptr(G.dg)[i];
       if (l == lf && lf > 0) lp<3>(L.f)[i] = gptr(G.f)[i];
     }
@@ -2129,17 +2190,18 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_grad(const Desc* __restrict__ 
   const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
   const double dt = clip ? *gptr(d.dt) : 0.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
-    const int y = (int)(i / g.nx), x = (int)(i - (int64_t)y * g.nx);
+    int x, y, z;
+    cell_xyz(g, i, x, y, z);
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       const gdouble* Q = gptr(d.pf_q) + (int64_t)p * nc;
       const bool on = s[kPfsBB + p] > 0.0;
 #pragma unroll
       for (int dir = 0; dir < D; ++dir) {
-        const int64_t j = nbr(g, D, x, y, dir, 1);
+        const int64_t j = nbr(g, x, y, z, dir, 1);
         double G = 0.0;
         if (on && j >= 0) {
-          const double rd = dir == 0 ? g.rdx : g.rdy;
+          const double rd = grid_rd(g, dir);
           G = (Q[j] - Q[i]) * rd;
           if (clip) {
             const double gm = kPfCfl / (dt * rd);
@@ -2347,14 +2409,14 @@ struct Table {
   AmrFn amrflux[kMaxN + 1][3][2] = {};          // interface fluxes of linked levels
   AmrFn amrcomb[kMaxN + 1][3] = {};             // their stage corrections
   StageFn sy[3][kMaxN + 1][2][kYVar] = {};      // 2D y sweep
-  StageFn sy3[2][kMaxN3 + 1][2][kYVar] = {};    // 3D y sweep (adds to the accumulator): [comparison]
-  StageFn sz3[2][kMaxN3 + 1][2][kYVar] = {};    // 3D z sweep (finishes the stage): [comparison]
+  StageFn sy3[3][kMaxN3 + 1][2][kYVar] = {};    // 3D y sweep (adds to the accumulator)
+  StageFn sz3[3][kMaxN3 + 1][2][kYVar] = {};    // 3D z sweep (finishes the stage)
   DtFn dt[kMaxN + 1][4] = {};
   RedFn diag[kMaxN + 1][4] = {};
-  PfFn pfc[6][kMaxN + 1][3] = {};          // per-cell PF passes
+  PfFn pfc[6][kMaxN + 1][4] = {};          // per-cell PF passes: [kind][N][d]
   PfFn pfi[4][kMaxN + 1] = {};             // per-instance PF finishers
-  MgFn mg[kMaxN + 1][3] = {};
-  hipError_t (*mg_lds[kMaxN + 1][3])(int) = {};
+  MgFn mg[kMaxN + 1][4] = {};
+  hipError_t (*mg_lds[kMaxN + 1][4])(int) = {};
 };
 
 template <int N, int D>
@@ -2382,10 +2444,10 @@ void fill_shapes(Table& t) {
   if constexpr (N <= kMaxN3) {
     t.sx[F][N][3][0][V] = launch_x<N, 3, double, F, V>;
     t.sx[F][N][3][1][V] = launch_x<N, 3, float, F, V>;
-    t.sy3[C][N][0][V] = launch_t<N, double, F, V, 3, 1>;
-    t.sy3[C][N][1][V] = launch_t<N, float, F, V, 3, 1>;
-    t.sz3[C][N][0][V] = launch_t<N, double, F, V, 3, 2>;
-    t.sz3[C][N][1][V] = launch_t<N, float, F, V, 3, 2>;
+    t.sy3[F][N][0][V] = launch_t<N, double, F, V, 3, 1>;
+    t.sy3[F][N][1][V] = launch_t<N, float, F, V, 3, 1>;
+    t.sz3[F][N][0][V] = launch_t<N, double, F, V, 3, 2>;
+    t.sz3[F][N][1][V] = launch_t<N, float, F, V, 3, 2>;
   }
   if constexpr (V == 0) {
     t.rhs1[C][N][1][0] = launch_rhs_single<N, 1, double, F>;
@@ -2418,6 +2480,15 @@ void fill(Table& t) {
   t.sx[kPfFlux][N][2][1][0] = launch_x<N, 2, float, kPfFlux, 0>;
   t.sy[kPfFlux][N][0][0] = launch_t<N, double, kPfFlux, 0, 2, 1>;
   t.sy[kPfFlux][N][1][0] = launch_t<N, float, kPfFlux, 0, 2, 1>;
+  if constexpr (N <= kMaxN3) {
+    t.sx[kPfFlux][N][3][0][0] = launch_x<N, 3, double, kPfFlux, 0>;
+    t.sx[kPfFlux][N][3][1][0] = launch_x<N, 3, float, kPfFlux, 0>;
+    t.sy3[kPfFlux][N][0][0] = launch_t<N, double, kPfFlux, 0, 3, 1>;
+    t.sy3[kPfFlux][N][1][0] = launch_t<N, float, kPfFlux, 0, 3, 1>;
+    t.sz3[kPfFlux][N][0][0] = launch_t<N, double, kPfFlux, 0, 3, 2>;
+    t.sz3[kPfFlux][N][1][0] = launch_t<N, float, kPfFlux, 0, 3, 2>;
+    fill_pf<N, 3>(t);
+  }
   fill_pf<N, 1>(t);
   fill_pf<N, 2>(t);
   t.pfi[0][N] = launch_pf_inst<N, 0>;
@@ -2574,10 +2645,10 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
   if (w == 2) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
   for (const Group& G : c->groups) {
     if (G.D == 2) T.sy[v][G.N][prec][v ? 0 : G.yv](G, s, swz(G), c->stream);
-    if (G.D == 3) T.sy3[cmp][G.N][prec][cmp ? 0 : G.yv](G, s, swz(G), c->stream);
+    if (G.D == 3) T.sy3[v][G.N][prec][v ? 0 : G.yv](G, s, swz(G), c->stream);
   }
   for (const Group& G : c->groups)
-    if (G.D == 3) T.sz3[cmp][G.N][prec][cmp ? 0 : G.yv](G, s, swz(G), c->stream);
+    if (G.D == 3) T.sz3[v][G.N][prec][v ? 0 : G.yv](G, s, swz(G), c->stream);
   if (w == 2 || w == 3) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   HIPCHK(c, hipGetLastError());
   return MP_OK;
@@ -2873,7 +2944,6 @@ static mp_status validate(int32_t n_inst, const mp_weno_instance* inst,
   for (int i = 0; i < n_inst; ++i) {
     const mp_weno_instance& s = inst[i];
     if (s.ndim < 1 || s.ndim > 3 || !s.U) return MP_ERR_ARG;
-    if (s.ndim > 2 && opt->phase_field) return MP_ERR_UNSUPPORTED;   // Eq. (4) in 3D
     if (s.nphase < 1 || s.nphase > MP_MAXP) return MP_ERR_ARG;
     if (s.nphase > kMaxN || (s.ndim == 3 && s.nphase > kMaxN3)) return MP_ERR_UNSUPPORTED;
     for (int d = 0; d < s.ndim; ++d) {
@@ -2970,20 +3040,23 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         // one-cell levels do nothing)
         for (int id : G.ids) {
           const Inst& I = c->inst[id];
-          int nx = I.in.n[0], ny = I.D > 1 ? I.in.n[1] : 1, L = 1;
-          while ((nx > 1 || ny > 1) && L < kMgMaxLev) { nx = (nx + 1) / 2; ny = (ny + 1) / 2; ++L; }
+          int nx = I.in.n[0], ny = I.D > 1 ? I.in.n[1] : 1, nz = I.D > 2 ? I.in.n[2] : 1, L = 1;
+          while ((nx > 1 || ny > 1 || nz > 1) && L < kMgMaxLev) {
+            nx = (nx + 1) / 2; ny = (ny + 1) / 2; nz = (nz + 1) / 2; ++L;
+          }
           G.nlev = std::max(G.nlev, L);
         }
         for (int id : G.ids) {
           Inst& I = c->inst[id];
-          int nx = I.in.n[0], ny = I.D > 1 ? I.in.n[1] : 1;
+          int nx = I.in.n[0], ny = I.D > 1 ? I.in.n[1] : 1, nz = I.D > 2 ? I.in.n[2] : 1;
           size_t tot = 0;
-          std::vector<std::pair<int, int>> dims;
+          std::vector<std::array<int, 3>> dims;
           for (int l = 0; l < G.nlev; ++l) {
-            dims.emplace_back(nx, ny);
-            tot += (size_t)nx * ny * 6;
+            dims.push_back({nx, ny, nz});
+            tot += (size_t)nx * ny * nz * (I.D > 2 ? 7 : 6);
             nx = (nx + 1) / 2;
             ny = (ny + 1) / 2;
+            nz = (nz + 1) / 2;
           }
           tot *= (size_t)I.N;
           if (hipMalloc(&I.mgbuf, sizeof(float) * tot) != hipSuccess ||
@@ -2995,12 +3068,15 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           float* q = I.mgbuf;
           for (int l = 0; l < G.nlev; ++l) {
             MgLevel L;
-            L.nx = dims[l].first;
-            L.ny = dims[l].second;
-            L.nc = (int64_t)L.nx * L.ny;
+            L.nx = dims[l][0];
+            L.ny = dims[l][1];
+            L.nz = dims[l][2];
+            L.nc = (int64_t)L.nx * L.ny * L.nz;
             const size_t f = (size_t)I.N * (size_t)L.nc;
             L.wx = q; q += f;
             L.wy = q; q += f;
+            L.wz = nullptr;
+            if (I.D > 2) { L.wz = q; q += f; }
             L.t = q; q += f;
             L.e = q; q += f;
             L.f = q; q += f;
@@ -3090,7 +3166,8 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         G.lcount[l] = (int)lm[l].size();
       }
       // the fused cycle takes the coarsest levels whose LDS image (6 N floats
-      // per cell) fits the workgroup's LDS in every instance of the group:
+      // per cell, 7 N in 3D) fits the workgroup's LDS in every instance of
+      // the group:
       // the device's limit when the kernel accepts it, else 64 KiB
       if (G.nlev > 0) {
         // (less kMgFusedStatic for the kernel's own LDS)
@@ -3109,7 +3186,8 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           for (size_t k = 0; k < m; ++k) {
             size_t b = 0;
             for (int j = l; j < G.nlev; ++j)
-              b += 6 * sizeof(float) * (size_t)G.N * (size_t)c->inst[G.ids[k]].lv[j].nc;
+              b += (G.D > 2 ? 7 : 6) * sizeof(float) * (size_t)G.N *
+                   (size_t)c->inst[G.ids[k]].lv[j].nc;
             mx = std::max(mx, b);
           }
           return mx;
@@ -3474,8 +3552,8 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
               T.sx[v][G.N][G.D][prec][xv](G, 3, sw, c->stream);
               if (G.D == 2) T.sy[v][G.N][prec][yv](G, 3, sw, c->stream);
               if (G.D == 3) {
-                T.sy3[cmp][G.N][prec][yv](G, 3, sw, c->stream);
-                T.sz3[cmp][G.N][prec][yv](G, 3, sw, c->stream);
+                T.sy3[v][G.N][prec][yv](G, 3, sw, c->stream);
+                T.sz3[v][G.N][prec][yv](G, 3, sw, c->stream);
               }
             };
             run();   // warm-up

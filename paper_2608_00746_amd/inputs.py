@@ -162,6 +162,22 @@ def cell_average_2d(f, nx, ny, box, ng=4):
     return out
 
 
+def cell_average_3d(f, nx, ny, nz, box, ng=3):
+    (x0, x1), (y0, y1), (z0, z1) = box
+    dx, dy, dz = (x1 - x0) / nx, (y1 - y0) / ny, (z1 - z0) / nz
+    xc = x0 + (np.arange(nx) + 0.5) * dx
+    yc = y0 + (np.arange(ny) + 0.5) * dy
+    zc = z0 + (np.arange(nz) + 0.5) * dz
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")     # (nz, ny, nx)
+    g, w = _gauss(ng)
+    out = np.zeros((nz, ny, nx))
+    for gi, wi in zip(g, w):
+        for gj, wj in zip(g, w):
+            for gk, wk in zip(g, w):
+                out += wi * wj * wk * f(X + gi * dx, Y + gj * dy, Z + gk * dz)
+    return out
+
+
 def _to4d(U, ndim):
     """(nU, *shape) -> (nU, nz, ny, nx)."""
     if ndim == 1:
@@ -192,6 +208,11 @@ def _tanh_slab(x, lo, hi, w):
 
 def _tanh_disc(X, Y, xc, yc, r, w):
     return 0.5 * (1.0 - np.tanh((np.hypot(X - xc, Y - yc) - r) / w))
+
+
+def _tanh_ball(X, Y, Z, c, r, w):
+    d = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+    return 0.5 * (1.0 - np.tanh((d - r) / w))
 
 
 # ---------------------------------------------------------------------------
@@ -591,12 +612,13 @@ def air_helium_shock_tube(dx=0.01, opts=None):
 # random admissible states for parity tests
 # ---------------------------------------------------------------------------
 
-def pf_bubble(shape, nphase=2, width=1.0, bc=BC_PERIODIC, u=(1.0, 0.5),
+def pf_bubble(shape, nphase=2, width=1.0, bc=BC_PERIODIC, u=(1.0, 0.5, 0.25),
               r=0.25, opts=None):
     """A Phase-Field test state: gas bubble (radius r of the unit box, tanh
     profile `width` cells wide) in water (SI); for N = 3 a shell of the third
     liquid (thickness r/2) around it; uniform velocity and P = 1e5.  1D: a
-    slab [0.5 - r, 0.5 + r].  Cell averages by Gauss quadrature."""
+    slab [0.5 - r, 0.5 + r]; 3D: a ball about the box centre.  Cell averages
+    by Gauss quadrature."""
     shape = tuple(shape)
     ndim = len(shape)
     N = nphase
@@ -614,6 +636,19 @@ def pf_bubble(shape, nphase=2, width=1.0, bc=BC_PERIODIC, u=(1.0, 0.5),
                 lambda x: _tanh_slab(x, 0.5 - 1.5 * r, 0.5 + 1.5 * r, w), n, 0.0, 1.0), 0.0, 1.0)
         dxs = (dx,)
         vel = np.full((1, n), float(u[0]))
+    elif ndim == 3:
+        nx, ny, nz = shape
+        dx = 1.0 / nx
+        w = width * dx
+        box = ((0, 1), (0, ny / nx), (0, nz / nx))
+        c = (0.5, 0.5 * ny / nx, 0.5 * nz / nx)
+        a1 = np.clip(cell_average_3d(lambda X, Y, Z: _tanh_ball(X, Y, Z, c, r, w),
+                                     nx, ny, nz, box), 0.0, 1.0)
+        if N == 3:
+            a13 = np.clip(cell_average_3d(
+                lambda X, Y, Z: _tanh_ball(X, Y, Z, c, 1.5 * r, w), nx, ny, nz, box), 0.0, 1.0)
+        dxs = (dx, dx, dx)
+        vel = np.stack([np.full((nz, ny, nx), float(u[k])) for k in range(3)])
     else:
         nx, ny = shape
         dx = 1.0 / nx

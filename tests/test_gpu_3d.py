@@ -162,10 +162,12 @@ def test_3d_full_size_invariants():
     assert d[21] >= -8 * EPS and d[22] >= -8 * EPS and d[23] <= 1 + 8 * EPS
 
 
-def test_3d_phase_field_unsupported():
+def test_3d_more_than_three_phases_unsupported():
+    """3D is built for N <= 3 (with and without the Phase-Field step)."""
     from paper_2608_00746_amd.binding import MpWenoError, ERR_UNSUPPORTED
-    w = I.shock_vessel_bubble_3d(16, 8, 8)
-    w.opts.phase_field = 1
-    with pytest.raises(MpWenoError) as ei:
-        _solver(w)
-    assert ei.value.status == ERR_UNSUPPORTED
+    for pf in (0, 1):
+        w = I.random_state((8, 6, 5), nphase=4, seed=1, ndim=3)
+        w.opts.phase_field = pf
+        with pytest.raises(MpWenoError) as ei:
+            _solver(w)
+        assert ei.value.status == ERR_UNSUPPORTED

@@ -50,7 +50,19 @@ CASES = [
     # five phases with one absent (its solve is done at once), four miscible
     lambda: _pf(I.paper_five_phase(40)),
     lambda: _pf(I.paper_four_phase_miscible(36)),
+    # 3D (the shock-vessel-bubble problem runs the step, Sec. 4.2.2): several
+    # tiles and levels, ragged edges, and the symmetry planes of that problem
+    lambda: I.pf_bubble((24, 20, 17), 2, width=1.5, bc=I.BC_PERIODIC),
+    lambda: _sym3(I.pf_bubble((21, 18, 14), 3, width=1.5, bc=I.BC_OUTFLOW)),
 ]
+
+
+def _sym3(w):
+    """Symmetry planes at the low y and z ends, as in the shock-vessel-bubble
+    problem."""
+    w.bc = ((I.BC_OUTFLOW, I.BC_OUTFLOW), (I.BC_SYMMETRY, I.BC_OUTFLOW),
+            (I.BC_SYMMETRY, I.BC_OUTFLOW))
+    return w
 
 
 def _faces_k(w, pb, U):
@@ -113,7 +125,8 @@ def test_pf_fields_vs_oracle(oracle, make):
     assert np.isfinite(L_g).all() and (inc <= TOL_J).all(), inc
 
 
-@pytest.mark.parametrize("make,K", [(CASES[0], 5), (CASES[3], 3), (CASES[4], 3), (CASES[6], 3)])
+@pytest.mark.parametrize("make,K", [(CASES[0], 5), (CASES[3], 3), (CASES[4], 3), (CASES[6], 3),
+                                    (CASES[7], 3), (CASES[8], 3)])
 def test_pf_steps_vs_oracle(oracle, make, K):
     w = make()
     w.t_end = 0.0
@@ -304,3 +317,29 @@ def test_pf_full_size_invariants(which):
     assert (d[:, 22] >= -tau).all(), d[:, 22].min()
     assert (d[:, 23] <= 1 + tau).all(), d[:, 23].max()
 
+
+
+@pytest.mark.parametrize("model", [0, 1], ids=["allaire", "kapila"])
+def test_pf_3d_full_size_shock_vessel_bubble(model):
+    """The shock-vessel-bubble problem at 400 x 200 x 200 with the
+    Phase-Field step after each step, both models (Sec. 4.2.2 runs it so):
+    converged solves, finite states, sum alpha = 1 and the bounds to
+    round-off (the hyperbolic step alone keeps sum alpha - 1 below 5e-13
+    there before the collapse)."""
+    w = I.shock_vessel_bubble_3d()
+    w.opts.phase_field = 1
+    w.opts.model = model
+    K = 2
+    s = _solver([w])
+    for _ in range(K):
+        s.step()
+    d = s.diag()[0]
+    s.close()
+    print("3D PF: CG iterations of the last solve", d[29], "residual", d[30],
+          "max |sum alpha - 1|", d[20])
+    assert d[25] == 0 and d[27] == K
+    assert d[30] <= 1e-10, d[30]
+    assert d[29] <= 400, d[29]
+    assert d[20] <= 1e-12, d[20]
+    tau = 8 * EPS
+    assert d[21] >= -tau and d[22] >= -tau and d[23] <= 1 + tau
