@@ -45,9 +45,9 @@
 extern "C" {
 #endif
 
-#define MP_WENO_ABI_VERSION 2
+#define MP_WENO_ABI_VERSION 3
 #define MP_MAXP 8        /* largest N this header describes                 */
-#define MP_DIAG_LEN 32   /* doubles per instance written by mp_weno_diag    */
+#define MP_DIAG_LEN 40   /* doubles per instance written by mp_weno_diag    */
 
 typedef enum {
   MP_OK = 0,
@@ -314,12 +314,6 @@ mp_status mp_weno_advance(mp_weno_ctx *ctx, int32_t nsteps);
 
 /* Diagnostics per instance, MP_DIAG_LEN doubles each (out[i*MP_DIAG_LEN+k]):
  *   k = 0 .. n_U-1 : sum over cells of U_c times the cell volume
- *   k = 18, 19     : the two integrals of the interface thickness N_I of
- *                    Eq. (30) for alpha_1: the volume of the cells with
- *                    0.05 <= alpha_1 <= 0.95, and the integral of
- *                    |grad alpha_1| (central differences inside, one-sided
- *                    ones at the two ends of each direction), so that
- *                    N_I = out[18] / (min_d dx_d * out[19])
  *   k = 20         : max over cells |sum_p alpha_p - 1|
  *   k = 21, 22, 23 : min m_p, min alpha_p, max alpha_p over cells and phases
  *   k = 24         : min over cells of psi(U) (Eq. (9))
@@ -329,6 +323,12 @@ mp_status mp_weno_advance(mp_weno_ctx *ctx, int32_t nsteps);
  *                    the true relative residual ||-[div J] - K Q|| /
  *                    ||[div J]|| (largest over phases) of the last solve of
  *                    Eq. (4) (0 when it is off)
+ *   k = 32, 33     : the two integrals of the interface thickness N_I of
+ *                    Eq. (30) for alpha_1: the volume of the cells with
+ *                    0.05 <= alpha_1 <= 0.95, and the integral of
+ *                    |grad alpha_1| (central differences inside, one-sided
+ *                    ones at the two ends of each direction), so that
+ *                    N_I = out[32] / (min_d dx_d * out[33])
  * where = MP_WHERE_HOST (synchronises) or MP_WHERE_DEVICE. */
 mp_status mp_weno_diag(mp_weno_ctx *ctx, double *out, int32_t where);
 

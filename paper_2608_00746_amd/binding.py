@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpweno.so")
 MAXP = 8
-DIAG_LEN = 32
+DIAG_LEN = 40
 
 OK, ERR_ARG, ERR_HIP, ERR_OOM, ERR_INADMISSIBLE, ERR_NONFINITE, ERR_SOLVER, \
     ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -321,12 +321,12 @@ class Solver:
 
     def interface_thickness(self, diag=None):
         """N_I of Eq. (30) for alpha_1 per instance, from the diagnostics'
-        two integrals (slots 18 and 19)."""
+        two integrals (slots 32 and 33)."""
         d = self.diag() if diag is None else diag
         out = np.zeros(len(self.U))
         for i, w in enumerate(self.w):
-            den = min(w.dx) * d[i, 19]
-            out[i] = d[i, 18] / den if den > 0.0 else 0.0
+            den = min(w.dx) * d[i, 33]
+            out[i] = d[i, 32] / den if den > 0.0 else 0.0
         return out
 
     def checkpoint(self, path=None):

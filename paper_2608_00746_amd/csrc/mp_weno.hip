@@ -43,7 +43,8 @@
 
 namespace mpw {
 
-constexpr int kMaxN = 5;          // phases built
+constexpr int kMaxN = 8;          // phases built
+constexpr int kMaxNT = 5;         // phases built with every tile shape (above: the defaults)
 constexpr int kMaxN3 = 3;         // phases built in 3D
 // Tile shapes (chosen per group by mp_weno_autotune; index 0 is the default):
 // x sweep strips of kXS[v] lanes (kXS[v] - 2 output cells), y and z sweep
@@ -55,9 +56,13 @@ constexpr int kXS[kXVar] = {256, 128, 64};
 constexpr int kYX[kYVar] = {16, 32, 16};
 constexpr int kYY[kYVar] = {16, 8, 24};
 constexpr int kRedBlock = 256;    // reduction workgroup
-constexpr int kDiagSlots = 32;    // per-block partials of the diagnostics
-constexpr int kPartSlots = 40;    // partial slots per reduction chunk (stored slot-major:
+constexpr int kDiagSlots = 34;    // per-block partials of the diagnostics
+constexpr int kPartSlots = 88;    // partial slots per reduction chunk (stored slot-major:
                                   // slot k of chunk b at k * Desc::ps + b)
+static_assert(kDiagSlots <= MP_DIAG_LEN && MP_DIAG_LEN <= 64, "diagnostic slots (finisher of 64 lanes)");
+static_assert(kPartSlots >= kDiagSlots && kPartSlots >= 1 + kMaxN * kMaxN + 2 * kMaxN &&
+                  kPartSlots >= 6 * kMaxN,
+              "partial slots of the widest reduction (the Phase-Field integrands)");
 // per-instance Phase-Field scalars (offsets into Desc::pfs): mobility,
 // M / eta^2, multipliers B_q, CG iterations and relative residual at exit,
 // the multigrid correction scale, and per phase ||b||^2, res.z, alpha, beta,
@@ -1013,18 +1018,18 @@ __global__ void k_advance_time(double* t, double* steps, const double* dt, int n
   }
 }
 
-// per-workgroup diagnostics: slots 0..nU-1 sums, [18], [19] the two
-// integrals of the interface thickness of Eq. (30) for alpha_1 (cells with
-// 0.05 <= alpha_1 <= 0.95; |grad alpha_1| by central differences inside
-// and one-sided ones at the ends of each direction), then
+// per-workgroup diagnostics: slots 0..nU-1 sums, then
 // [20] max|sum a - 1|, [21] min m, [22] min a, [23] max a, [24] min psi,
-// [25] non-finite count, [28] max |rho E|
+// [25] non-finite count, [28] max |rho E|, [32], [33] the two integrals of
+// the interface thickness of Eq. (30) for alpha_1 (cells with
+// 0.05 <= alpha_1 <= 0.95; |grad alpha_1| by central differences inside
+// and one-sided ones at the ends of each direction)
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ descs,
                                                     const int2* __restrict__ map,
                                                     int ninst, double* __restrict__ part) {
   constexpr int NU = 2 * N + D + 1;
-  static_assert(NU <= 18, "the totals share the slots below the interface integrals");
+  static_assert(NU <= 20, "the totals take the slots below 20");
   __shared__ double sh[kRedBlock];
   const int2 it = locate(map, ninst, blockIdx.x);
   const Desc& d = descs[it.x];
@@ -1062,7 +1067,7 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
     acc[28] = fmax(acc[28], fabs(u[N + D]));
     // interface thickness integrals of alpha_1
     const double a1 = u[N + D + 1];
-    if (a1 >= 0.05 && a1 <= 0.95) acc[18] += 1.0;
+    if (a1 >= 0.05 && a1 <= 0.95) acc[32] += 1.0;
     const gdouble* A = U + (int64_t)(N + D + 1) * g.nc;
     const int64_t plane = (int64_t)g.nx * g.ny;
     const int z = (int)(i / plane);
@@ -1080,7 +1085,7 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
     grad(x, g.nx, 1, g.rdx);
     if constexpr (D >= 2) grad(y, g.ny, g.nx, g.rdy);
     if constexpr (D >= 3) grad(z, g.nz, plane, g.rdz);
-    acc[19] += sqrt(g2);
+    acc[33] += sqrt(g2);
   }
   // fixed-order tree per slot
   for (int k = 0; k < kDiagSlots; ++k) {
@@ -1102,13 +1107,17 @@ __global__ __launch_bounds__(kRedBlock) void k_diag(const Desc* __restrict__ des
   }
 }
 
-// one workgroup of kDiagSlots lanes per instance, lane k reduces slot k in
-// block order
+// one workgroup per instance (at least MP_DIAG_LEN lanes), lane k reduces
+// slot k in block order
 __global__ void k_diag_finish(const Desc* __restrict__ descs, const int* __restrict__ start,
                               const double* __restrict__ part) {
   const int k = threadIdx.x;
   const Desc& d = descs[blockIdx.x];
-  if (k >= kDiagSlots) return;
+  if (k >= MP_DIAG_LEN) return;
+  if (k >= kDiagSlots) {            // slots no reduction fills: 0
+    gptr(d.diag)[k] = 0.0;
+    return;
+  }
   double r;
   if (k == 21 || k == 22 || k == 24) r = INFINITY;
   else if (k == 23) r = -INFINITY;
@@ -1119,7 +1128,7 @@ __global__ void k_diag_finish(const Desc* __restrict__ descs, const int* __restr
     else if (k == 20 || k == 23 || k == 28) r = fmax(r, x);
     else r = r + x;
   }
-  if (k < 20) r *= d.vol;
+  if (k < 20 || k >= 32) r *= d.vol;      // the integrals
   if (k == 26) r = *gptr(d.t);
   if (k == 27) r = *gptr(d.steps);
   if (k == 29) r = d.pfs ? gptr(d.pfs)[kPfsIts] : 0.0;
@@ -2470,8 +2479,10 @@ void fill(Table& t) {
   t.amrcomb[N][1] = launch_amr_comb<N, 1>;
   t.amrcomb[N][2] = launch_amr_comb<N, 2>;
   fill_shapes<N, 0, kRiemann>(t);
-  fill_shapes<N, 1, kRiemann>(t);
-  fill_shapes<N, 2, kRiemann>(t);
+  if constexpr (N <= kMaxNT) {
+    fill_shapes<N, 1, kRiemann>(t);
+    fill_shapes<N, 2, kRiemann>(t);
+  }
   fill_shapes<N, 0, kRiemannCmp>(t);
   // the Phase-Field sweeps: default shapes only
   t.sx[kPfFlux][N][1][0][0] = launch_x<N, 1, double, kPfFlux, 0>;
@@ -2508,7 +2519,8 @@ void fill(Table& t) {
 static const Table& table() {
   static Table t = [] {
     Table x;
-    fill<1>(x); fill<2>(x); fill<3>(x); fill<4>(x); fill<5>(x);
+    fill<1>(x); fill<2>(x); fill<3>(x); fill<4>(x); fill<5>(x); fill<6>(x); fill<7>(x);
+    fill<8>(x);
     return x;
   }();
   return t;
@@ -3217,8 +3229,8 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         zm[v] = tile_map(G.zs[v]);
         ok = ok && hipMalloc(&G.zmap[v], sizeof(int2) * std::max<size_t>(zm[v].size(), 1)) == hipSuccess;
       }
-      G.xv = xv0;
-      G.yv = yv0;
+      G.xv = N > kMaxNT ? 0 : xv0;
+      G.yv = N > kMaxNT ? 0 : yv0;
       c->groups.push_back(G);
       if (!ok) {
         mp_weno_destroy(c);
@@ -3536,11 +3548,13 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
   // only the tile order is chosen
   const int cmp = c->opt.recon >= MP_RECON_WENO_JS;
   const int v = cmp ? kRiemannCmp : kRiemann;
-  const int nxv = cmp ? 1 : kXVar;
   for (Group& G : c->groups) {
     // every candidate timed in two interleaved rounds, the faster one kept:
-    // a single round is at the mercy of clock and neighbour noise
-    const int nyv = G.D >= 2 && !cmp ? kYVar : 1;
+    // a single round is at the mercy of clock and neighbour noise (groups of
+    // more than kMaxNT phases are built with the default shapes only)
+    const bool fixed = cmp || G.N > kMaxNT;
+    const int nxv = fixed ? 1 : kXVar;
+    const int nyv = G.D >= 2 && !fixed ? kYVar : 1;
     float tmin[kXVar][kYVar][2];
     for (auto& a : tmin)
       for (auto& b : a) b[0] = b[1] = INFINITY;

@@ -46,14 +46,14 @@ def instance_record(w, d, tot0):
     for c in range(N + D + 1):          # m_p, rho u_k, rho E
         ref = abs(tot0[c]) if tot0[c] != 0.0 else 1.0
         cons.append(float(abs(tot[c] - tot0[c]) / ref))
-    den = min(w.dx) * d[19]
+    den = min(w.dx) * d[33]
     return {
         "name": w.name, "t": float(d[26]), "steps": int(d[27]),
         "sum_alpha_err": float(d[20]), "min_m": float(d[21]),
         "min_alpha": float(d[22]), "max_alpha": float(d[23]),
         "min_psi": float(d[24]), "nonfinite": int(d[25]),
         "conservation_rel": cons,
-        "interface_thickness": float(d[18] / den) if den > 0.0 else 0.0,
+        "interface_thickness": float(d[32] / den) if den > 0.0 else 0.0,
         "cg_iterations": float(d[29]), "cg_residual": float(d[30]),
     }
 

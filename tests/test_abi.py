@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
     assert set(_declared()) == set(binding.EXPORTED)
     lib.mp_weno_abi_version.restype = ctypes.c_int32
-    assert lib.mp_weno_abi_version() == 2
+    assert lib.mp_weno_abi_version() == 3
     lib.mp_weno_max_phases.restype = ctypes.c_int32
     assert lib.mp_weno_max_phases() >= 5
 

@@ -108,6 +108,8 @@ CASES_1D = [
     # N, flux, recon, energy, bc, seed
     (1, 0, 0, 1, 0, 1), (2, 0, 0, 1, 0, 2), (2, 1, 1, 1, 1, 3), (3, 1, 0, 1, 0, 4),
     (3, 0, 1, 0, 1, 5), (4, 1, 0, 1, 1, 6), (5, 0, 0, 1, 0, 7), (5, 1, 1, 1, 1, 8),
+    # up to the eight phases of the boundary's range (default tile shapes)
+    (6, 1, 0, 1, 0, 9), (7, 0, 1, 1, 1, 10), (8, 1, 0, 0, 0, 19), (8, 0, 1, 1, 1, 20),
 ]
 
 
@@ -123,6 +125,8 @@ CASES_2D = [
     ((37, 300), 2, 0, 0, 0, 11), ((70, 259), 2, 1, 0, 1, 12), ((33, 129), 3, 1, 1, 0, 13),
     ((65, 64), 3, 0, 0, 1, 14), ((5, 600), 4, 1, 0, 0, 15), ((41, 41), 5, 0, 1, 1, 16),
     ((1, 7), 2, 1, 0, 0, 17), ((9, 3), 2, 0, 0, 1, 18),
+    ((35, 270), 6, 1, 0, 0, 21), ((20, 300), 7, 0, 1, 1, 22), ((33, 257), 8, 1, 1, 0, 23),
+    ((18, 40), 8, 0, 0, 1, 24),
 ]
 
 
@@ -230,6 +234,31 @@ def test_absent_phase_and_reduction_bitwise(oracle):
     assert (a[2] == 0).all() and (a[-1] == 0).all()
     assert np.array_equal(a[keep], b)
     s3.close(); s2.close()
+
+
+def test_eight_phases_with_one_absent_reduce_to_seven_bitwise(oracle):
+    """The widest build: N = 8 with phase 8 absent reproduces N = 7 bitwise
+    over a few steps (the default tile shapes of N > 5, both precisions),
+    and the autotuner keeps those shapes."""
+    for prec in (I.PREC_FP64, I.PREC_MIXED):
+        w8 = I.random_state((24, 150), nphase=8, seed=43, absent=(7,), lowp=0.0,
+                            opts=I.Options(flux=1, cfl=0.2, precision=prec))
+        N = 8
+        keep = [c for c in range(w8.nU) if c not in (N - 1, w8.nU - 1)]
+        w7 = w8.copy()
+        w7.gamma, w7.pinf, w7.D, w7.pmin, w7.cT = (x[:N - 1] for x in
+                                                   (w8.gamma, w8.pinf, w8.D, w8.pmin, w8.cT))
+        w7.U = w8.U[keep].copy()
+        s8, s7 = _solver(w8), _solver(w7)
+        ch = s8.autotune(reps=1)
+        assert ch[0, 0] == 256 and ch[0, 1] == 16 and ch[0, 2] == 16
+        for _ in range(3):
+            s8.step()
+            s7.step()
+        a, b = s8.host(0), s7.host(0)
+        assert (a[N - 1] == 0).all() and (a[-1] == 0).all()
+        assert np.array_equal(a[keep], b)
+        s8.close(); s7.close()
 
 
 def test_determinism_and_graph_replay():

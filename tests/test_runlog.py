@@ -20,14 +20,14 @@ class _FakeSolver:
         self.steps += n
 
     def diag(self):
-        d = np.zeros((len(self.w), 32))
+        d = np.zeros((len(self.w), 40))
         for i, w in enumerate(self.w):
             U = w.U.reshape(w.nU, -1)
             vol = float(np.prod(w.dx))
             d[i, :w.nU] = U.sum(axis=1) * vol
             d[i, w.N + w.ndim] *= 1.0 + 1e-9 * self.steps
-            d[i, 18] = 0.25
-            d[i, 19] = 0.5 / min(w.dx)
+            d[i, 32] = 0.25
+            d[i, 33] = 0.5 / min(w.dx)
             d[i, 26] = 1e-3 * self.steps
             d[i, 27] = self.steps
         return d
@@ -57,7 +57,7 @@ def test_run_writes_a_line_per_block(tmp_path):
         assert len(cons) == w.N + w.ndim + 1
         assert abs(cons[w.N + w.ndim] - 25e-9) < 1e-15
         assert all(c == 0.0 for c in cons[:w.N + w.ndim])
-        # N_I = out[18] / (min dx * out[19]) = 0.25 / 0.5
+        # N_I = out[32] / (min dx * out[33]) = 0.25 / 0.5
         assert abs(r["interface_thickness"] - 0.5) < 1e-15
 
 
