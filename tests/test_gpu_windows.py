@@ -6,7 +6,9 @@ Always run:
   the problem with an absent third phase equals its N = 2 version bitwise
   (FP64 and mixed);
 * C5, the 256-instance batch: 8 seeded instances after 20 steps of the
-  batched FP64 run against the oracle run of each alone, at the window bar.
+  batched FP64 run against the oracle run of each alone, at the window bar;
+  and the benchmark's own configuration (mixed, autotuned, graphs): L(U)
+  and 10 steps of sampled instances against the oracle at the mixed bars.
 With MPWENO_LONG=1 (minutes; measured figures in the design notes):
 * C1 for the full period (t = 1, 580 024 steps): invariants and the L1
   error of alpha_1 against the translated initial state, plus the first
@@ -142,6 +144,53 @@ def test_c5_sampled_instances_vs_oracle(oracle):
         err = np.abs(G[int(k)] - U).max(axis=1) / _scales(w, U)
         print(w.name, np.array2string(err, precision=2))
         assert (err <= 1e-12).all(), (w.name, err)
+
+
+def test_c5_headline_configuration_sampled_vs_oracle(oracle):
+    """The benchmark's own launch configuration (the 256-instance batch,
+    mixed precision, autotuned tile shapes, captured 16-step graphs):
+    L(U) of 10 sampled instances (seeded, plus the smallest and the largest)
+    against the oracle at the mixed bar (1e-4 of max |L| per significant
+    component), then 10 steps of the whole batch against each sampled
+    instance's oracle run alone at the mixed window bar (1e-6 of the
+    component scale)."""
+    from test_gpu_mixed import TOL_RHS, TOL_STATE
+    ws = I.batched(opts=I.Options(flux=I.FLUX_HLL, cfl=0.2, precision=I.PREC_MIXED))
+    s = _solver(ws)
+    s.autotune()
+    L = s.rhs()
+    n = np.array([w.ncells for w in ws])
+    pick = sorted(set(np.random.default_rng(7).choice(len(ws), 8, replace=False).tolist()
+                      + [int(np.argmin(n)), int(np.argmax(n))]))
+    Lg = {k: L[k].cpu().numpy().reshape(ws[k].nU, -1) for k in pick}
+    del L
+    steps = 10
+    s.advance(steps)
+    G = {k: s.host(k).reshape(ws[k].nU, -1).copy() for k in pick}
+    d = s.diag()
+    s.close()
+    assert (d[:, 27] == steps).all() and (d[:, 25] == 0).all()
+    for k in pick:
+        w = ws[k]
+        pb = oracle_problem(oracle, w)
+        U = w.U.reshape(-1).copy()
+        Lo = pb.rhs(U).reshape(w.nU, -1)
+        dt = pb.dt(U, 0.0)
+        sc = _scales(w)
+        Lmax = np.abs(Lo).max(axis=1)
+        raw = np.abs(Lg[k] - Lo).max(axis=1) / np.where(Lmax > 0, Lmax, 1.0)
+        significant = dt * Lmax > 1e-10 * sc
+        t = 0.0
+        for _ in range(steps):
+            dtk = pb.dt(U, t)
+            U = pb.step(U, dtk)
+            t += dtk
+        U = U.reshape(w.nU, -1)
+        err = np.abs(G[k] - U).max(axis=1) / _scales(w, U)
+        print(w.name, "rhs", np.array2string(raw, precision=2), "| 10 steps",
+              np.array2string(err, precision=2))
+        assert (raw[significant] <= TOL_RHS).all(), (w.name, raw)
+        assert (err <= TOL_STATE).all(), (w.name, err)
 
 
 @LONG
