@@ -81,6 +81,28 @@ def test_reduction_n3_equals_n2_over_steps(oracle):
     assert np.array_equal(a[keep], b)
 
 
+def test_reduction_n8_equals_n7_over_steps(oracle):
+    """The widest phase count of the boundary: N = 8 with phase 8 absent
+    reproduces the N = 7 run bitwise over steps, and the absent phase stays
+    exactly zero (every per-phase loop of the scheme runs over eight
+    phases)."""
+    N = 8
+    w8 = I.random_state((14, 18), nphase=N, seed=17, absent=(N - 1,), lowp=0.0,
+                        opts=I.Options(flux=1, cfl=0.2))
+    pb8 = oracle_problem(oracle, w8)
+    keep = [c for c in range(w8.nU) if c not in (N - 1, w8.nU - 1)]
+    U8 = w8.U.reshape(w8.nU, -1)
+    U7 = U8[keep].copy()
+    pb7 = oracle.Problem(2, w8.n, w8.dx, w8.bc, list(w8.gamma[:N - 1]), list(w8.pinf[:N - 1]),
+                         list(w8.D[:N - 1]), list(w8.pmin[:N - 1]), flux=1, cfl=0.2)
+    dt = pb8.dt(U8.reshape(-1))
+    assert dt == pb7.dt(U7.reshape(-1))
+    a = _run(pb8, U8, dt, 3).reshape(w8.nU, -1)
+    b = _run(pb7, U7, dt, 3).reshape(w8.nU - 2, -1)
+    assert (a[N - 1] == 0).all() and (a[-1] == 0).all()
+    assert np.array_equal(a[keep], b)
+
+
 def test_thermal_and_consistency_errors_roundoff(oracle):
     """Sec. 4.1.1 with WENO-C: temperature and the consistency error
     (alpha_1 rho_1)/rho_1 - alpha_1 stay at round-off."""
