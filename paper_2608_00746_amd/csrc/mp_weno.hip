@@ -322,6 +322,31 @@ constexpr int sweep_waves() {
   return N == 1 ? (D == 1 ? 4 : 3) : (N == 2 ? (D == 3 ? 2 : 3) : (N <= 4 ? 2 : 1));
 }
 
+// v of lane l + 1 (SHL) or lane l - 1 (SHR) of the wave (DPP wave shift by
+// one lane); the lane at the wave's end keeps its own value
+template <bool SHL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  constexpr int ctrl = SHL ? 0x130 : 0x138;      // wave_shl:1 / wave_shr:1
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, ctrl, 0xf, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, ctrl, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)rhi << 32) |
+                                          (unsigned long long)(unsigned)rlo));
+}
+
+template <int N, int D>
+__device__ __forceinline__ void shift_face_left(Face<N, D>& f) {
+#pragma unroll
+  for (int p = 0; p < N; ++p) { f.m[p] = lane_shift<true>(f.m[p]); f.a[p] = lane_shift<true>(f.a[p]); }
+#pragma unroll
+  for (int k = 0; k < D; ++k) { f.mom[k] = lane_shift<true>(f.mom[k]); f.u[k] = lane_shift<true>(f.u[k]); }
+  f.E = lane_shift<true>(f.E);
+  f.P = lane_shift<true>(f.P);
+  f.rho = lane_shift<true>(f.rho);
+  f.c = lane_shift<true>(f.c);
+}
+
 template <int N, int D, typename W, int PFM, int BX>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, BX),
                           amdgpu_waves_per_eu(sweep_waves<N, D, W, PFM, true>(), 8)))
@@ -344,9 +369,12 @@ void k_sweep_x(const Desc* __restrict__ descs,
   constexpr int NFL = NU + 1;
   // the flux rows reuse the primitive rows: the stencil is in registers and
   // a barrier (after the face exchange) separates the two uses
-  constexpr int NPRIM = NV * (BX + 4), NFLX = NFL * BX;
+  // a strip of one wave trades face states and fluxes by DPP lane shifts
+  // (no LDS, no barrier); wider strips through LDS
+  constexpr bool kOneWave = BX == 64 && PFM != kPfFlux;
+  constexpr int NPRIM = NV * (BX + 4), NFLX = kOneWave ? 0 : NFL * BX;
   __shared__ double sraw[NPRIM > NFLX ? NPRIM : NFLX];
-  __shared__ double sface[NF][BX];
+  __shared__ double sface[kOneWave ? 1 : NF][BX];
   double (*sprim)[BX + 4] = reinterpret_cast<double (*)[BX + 4]>(sraw);
   double (*sflux)[BX] = reinterpret_cast<double (*)[BX]>(sraw);
 
@@ -391,6 +419,16 @@ void k_sweep_x(const Desc* __restrict__ descs,
   reconstruct<N, D, W, kRecon<PFM>()>([&](int c, int j) { return sprim[c][l + j]; }, ub, e, g,
                                       g.hdx, fm, fp);
 
+  Flux<N, D> F;
+  double Fl[NFL];            // the flux of face xi - 1/2 (one-wave strips)
+  if constexpr (kOneWave) {
+    Face<N, D> R = fm;
+    shift_face_left<N, D>(R);            // the minus-side face of lane l + 1
+    riemann<N, D, W>(fp, R, 0, g.flux, F);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) Fl[c] = lane_shift<false>(F.f[c]);
+    Fl[NU] = lane_shift<false>(F.uh);
+  } else {
   // publish the minus-side face state for the left neighbour
 #pragma unroll
   for (int p = 0; p < N; ++p) { sface[p][l] = fm.m[p]; sface[N + p][l] = fm.a[p]; }
@@ -402,7 +440,6 @@ void k_sweep_x(const Desc* __restrict__ descs,
   sface[2 * N + 2 * D + 3][l] = fm.c;
   __syncthreads();
 
-  Flux<N, D> F;
   if (l < BX - 1) {
     Face<N, D> R;
     const int r = l + 1;
@@ -436,18 +473,24 @@ void k_sweep_x(const Desc* __restrict__ descs,
     sflux[NU][l] = F.uh;
   }
   __syncthreads();
+  }
+  // the flux of face xi - 1/2, component c (NU: u-hat)
+  auto fleft = [&](int c) -> double {
+    if constexpr (kOneWave) return Fl[c];
+    else return sflux[c][l - 1];
+  };
 
   if (l >= 1 && l < BX - 1 && xi < g.nx) {
     double L[NU];
     if constexpr (PFM == kPfFlux) {
 #pragma unroll
-      for (int c = 0; c < NU; ++c) L[c] = (F.f[c] - sflux[c][l - 1]) * g.rdx;
+      for (int c = 0; c < NU; ++c) L[c] = (F.f[c] - fleft(c)) * g.rdx;
     } else {
       double opk[N];
       one_plus_k<N, D>(ub, e, g.model, opk);
 #pragma unroll
-      for (int c = 0; c < NU; ++c) L[c] = -(F.f[c] - sflux[c][l - 1]) * g.rdx;
-      const double du = (F.uh - sflux[NU][l - 1]) * g.rdx;
+      for (int c = 0; c < NU; ++c) L[c] = -(F.f[c] - fleft(c)) * g.rdx;
+      const double du = (F.uh - fleft(NU)) * g.rdx;
       // alpha_p at the cell average, or alpha_p / sum_q alpha_q (then the
       // sources sum to du, as the fluxes' alpha parts do, and
       // sum_q alpha_q - 1 gets no source of its own)
