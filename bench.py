@@ -150,13 +150,39 @@ def cpu_baseline(ws, seconds):
                       f"OpenMP over grid lines"}
 
 
-def tiles_key(args, tiles):
+def group_order(ws):
+    """(d, N) of the library's instance groups, in its group order."""
+    return sorted({(w.ndim, w.N) for w in ws})
+
+
+def tiles_key(args, ws, tiles):
+    """The tile choice as x<lanes>/y<X>x<Y>/<plain|xcd>: one entry when every
+    group has the same shapes, else one per group (comma-separated, in group
+    order), the form --tiles takes."""
     if args.tiles:
         return args.tiles
     if tiles is None:
         return "default"
-    return ",".join(sorted({"x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain")
-                            for t in tiles.tolist()}))
+    per = []
+    for g in group_order(ws):
+        i = next(k for k, w in enumerate(ws) if (w.ndim, w.N) == g)
+        t = tiles[i].tolist()
+        per.append("x%d/y%dx%d/%s" % (t[0], t[1], t[2], "xcd" if t[3] else "plain"))
+    return per[0] if len(set(per)) == 1 else ",".join(per)
+
+
+def tiles_env(spec):
+    """Environment of the library's tile overrides for a --tiles spec."""
+    xl, yl, sl = [], [], []
+    for ent in spec.split(","):
+        xs, ys, sw = ent.split("/")
+        yx, yy = (int(v) for v in ys[1:].split("x"))
+        xl.append(str([256, 128, 64].index(int(xs[1:]))))
+        # 1D groups report a y tile of 0 x 0: any index serves
+        yl.append(str([(16, 16), (32, 8), (16, 24), (0, 0)].index((yx, yy)) % 3))
+        sl.append({"plain": "0", "xcd": "1"}[sw])
+    return {"MPWENO_XSHAPE": ",".join(xl), "MPWENO_YSHAPE": ",".join(yl),
+            "MPWENO_XCD_SWIZZLE": ",".join(sl)}
 
 
 def measure(ws, args, stream, keep_state=False):
@@ -301,7 +327,9 @@ def main():
                          "timed region (a reference kernel of known traffic for counters)")
     ap.add_argument("--tiles", default=None,
                     help="fixed tile shapes instead of the autotuner, as "
-                         "x<lanes>/y<X>x<Y>/<plain|xcd> (the form the bench line reports)")
+                         "x<lanes>/y<X>x<Y>/<plain|xcd> for every group, or a comma-separated "
+                         "list of such, one per group of (d, N) in ascending order (the form "
+                         "the bench line reports)")
     ap.add_argument("--pf-steps", type=int, default=10,
                     help="time this many steps of the 2048 x 1024 shock-bubble with the "
                          "Phase-Field step on (0: skip)")
@@ -315,11 +343,7 @@ def main():
 
     if args.tiles is not None:
         # shapes by index into the library's candidate lists
-        xs, ys, sw = args.tiles.split("/")
-        yx, yy = (int(v) for v in ys[1:].split("x"))
-        os.environ["MPWENO_XSHAPE"] = str([256, 128, 64].index(int(xs[1:])))
-        os.environ["MPWENO_YSHAPE"] = str([(16, 16), (32, 8), (16, 24), (0, 0)].index((yx, yy)) % 3)
-        os.environ["MPWENO_XCD_SWIZZLE"] = {"plain": "0", "xcd": "1"}[sw]
+        os.environ.update(tiles_env(args.tiles))
     from paper_2608_00746_amd import inputs as I
     ws = workload(args.workload, args.precision)
     precision = "mixed" if ws[0].opts.precision == I.PREC_MIXED else "fp64"
@@ -342,7 +366,7 @@ def main():
         summary, runs = precision_pair(args.workload, args, stream)
         comparison[args.workload] = summary
         ws, r = runs[precision]
-    tk = tiles_key(args, r["tiles"])
+    tk = tiles_key(args, ws, r["tiles"])
     bytes_stage = sum(8 * w.nU * w.ncells for w in ws) * (2 + 3 + 3) / 3.0
     stage_s = r["stage_ms"] / 1e3
     achieved = bytes_stage / stage_s / 1e9

@@ -206,6 +206,14 @@ __device__ __forceinline__ int xcd_item(int b, int G, int swz) {
   return x * q + (x < r ? x : r) + slot;
 }
 
+// Work item of a Phase-Field pass over chunks of cells: consecutive chunks
+// (rows and their neighbour rows, which the stencils read) run on one XCD and
+// share its L2.  Partial sums stay in the item's slot, so the order of every
+// reduction is that of the items.
+__device__ __forceinline__ int chunk_item() {
+  return xcd_item((int)blockIdx.x, (int)gridDim.x, 1);
+}
+
 __device__ __forceinline__ int bc_map(int i, int n, int lo, int hi) {
   if (i < 0) {
     if (lo == MP_BC_PERIODIC) return ((i % n) + n) % n;
@@ -1323,7 +1331,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_prep(const Desc* __restrict__ 
                                                        double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
   constexpr int NS = 1 + N * N + 2 * N;
-  const int2 it = locate(map, ninst, blockIdx.x);
+  const int2 it = locate(map, ninst, chunk_item());
   const Desc& d = descs[it.x];
   const int64_t nc = d.g.nc;
   const int64_t c0 = (int64_t)it.y * d.chunk;
@@ -1361,7 +1369,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_prep(const Desc* __restrict__ 
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double r = block_reduce(acc[k], sh, k == 0 ? 1 : 0);
-    if (threadIdx.x == 0) part[(int64_t)k * d.ps + blockIdx.x] = r;
+    if (threadIdx.x == 0) part[(int64_t)k * d.ps + chunk_item()] = r;
   }
 }
 
@@ -1445,7 +1453,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
                                                        const int2* __restrict__ map, int ninst,
                                                        double* __restrict__ part, int cold) {
   __shared__ double sh[kRedBlock];
-  const int2 it = locate(map, ninst, blockIdx.x);
+  const int2 it = locate(map, ninst, chunk_item());
   const Desc& d = descs[it.x];
   const Grid& g = d.g;
   const int64_t nc = g.nc;
@@ -1506,7 +1514,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_divj(const Desc* __restrict__ 
 #pragma unroll
   for (int k = 0; k < 3 * N; ++k) {
     const double r = block_reduce(acc[k], sh, 0);
-    if (threadIdx.x == 0) part[(int64_t)k * d.ps + blockIdx.x] = r;
+    if (threadIdx.x == 0) part[(int64_t)k * d.ps + chunk_item()] = r;
   }
 }
 
@@ -1591,7 +1599,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dir(const Desc* __restrict_
                                                          const int2* __restrict__ map, int ninst,
                                                          double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
-  const int2 it = locate(map, ninst, blockIdx.x);
+  const int2 it = locate(map, ninst, chunk_item());
   const Desc& d = descs[it.x];
   const Grid& g = d.g;
   const int64_t nc = g.nc;
@@ -1640,7 +1648,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dir(const Desc* __restrict_
   for (int p = 0; p < N; ++p) {
     if (!live[p]) continue;
     const double r = block_reduce(acc[p], sh, 0);
-    if (threadIdx.x == 0) part[(int64_t)p * d.ps + blockIdx.x] = r;
+    if (threadIdx.x == 0) part[(int64_t)p * d.ps + chunk_item()] = r;
   }
 }
 
@@ -1669,7 +1677,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_alpha(const Desc* __restric
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict__ descs,
                                                           const int2* __restrict__ map, int ninst) {
-  const int2 it = locate(map, ninst, blockIdx.x);
+  const int2 it = locate(map, ninst, chunk_item());
   const Desc& d = descs[it.x];
   const int64_t nc = d.g.nc;
   const gdouble* s = gptr(d.pfs);
@@ -1702,7 +1710,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dots(const Desc* __restrict
                                                           const int2* __restrict__ map, int ninst,
                                                           double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
-  const int2 it = locate(map, ninst, blockIdx.x);
+  const int2 it = locate(map, ninst, chunk_item());
   const Desc& d = descs[it.x];
   const int64_t nc = d.g.nc;
   const gdouble* s = gptr(d.pfs);
@@ -1736,7 +1744,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dots(const Desc* __restrict
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const double r = block_reduce(acc[k * N + p], sh, 0);
-      if (threadIdx.x == 0) part[(int64_t)(k * N + p) * d.ps + blockIdx.x] = r;
+      if (threadIdx.x == 0) part[(int64_t)(k * N + p) * d.ps + chunk_item()] = r;
     }
   }
 }
@@ -1891,7 +1899,7 @@ __device__ __forceinline__ float lapply(const Grid& g, const MgLevel& L, int p, 
 
 // per-level work items: (instance, chunk of 256 cells of that level)
 #define MG_PROLOGUE                                                         \
-  const int2 it = locate(map, ninst, blockIdx.x);                           \
+  const int2 it = locate(map, ninst, chunk_item());                         \
   const Desc& d = descs[it.x];                                              \
   const Grid& g = d.g;                                                      \
   const gdouble* s = gptr(d.pfs);                                           \
@@ -2233,7 +2241,7 @@ template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_pf_grad(const Desc* __restrict__ descs,
                                                        const int2* __restrict__ map, int ninst,
                                                        int clip) {
-  const int2 it = locate(map, ninst, blockIdx.x);
+  const int2 it = locate(map, ninst, chunk_item());
   const Desc& d = descs[it.x];
   const Grid& g = d.g;
   const int64_t nc = g.nc;
@@ -2296,7 +2304,10 @@ struct Group {
   int2* zmap[kYVar] = {};          // z sweep (3D): tiles of the y-sweep shapes
   int2* rmap = nullptr;
   int xv = 0, yv = 0;              // tile shapes in use (autotuned)
-  int swz = -1;                    // XCD order: -1 default rule, 0 off, 1 on
+  int swz = -1;                    // XCD order: 0 off, 1 on, -1 on for groups
+                                   // of several instances (measured: it keeps
+                                   // each small instance on one L2 and costs a
+                                   // few percent on a single grid)
   int* rstart = nullptr;           // reduction-chunk offsets on the device
   size_t part_off = 0;             // this group's reduction partials
   int nlev = 0;                    // multigrid levels (every instance has them all)
@@ -2311,6 +2322,17 @@ struct Bracket {
   int which = 0;                   // 0 none, 1 x sweep, 2 y sweep, 3 whole stage
   hipEvent_t ev[2] = {nullptr, nullptr};
 };
+
+// Entry g of a comma-separated list of integers ("1" or "0,2,1"); a list
+// shorter than g + 1 entries gives its last one.
+int env_entry(const char* s, int g) {
+  for (int k = 0; k < g; ++k) {
+    const char* c = std::strchr(s, ',');
+    if (!c) break;
+    s = c + 1;
+  }
+  return std::atoi(s);
+}
 
 using StageFn = void (*)(const Group&, int stage, int swz, hipStream_t);
 using RedFn = void (*)(const Group&, double* part, hipStream_t);
@@ -2621,10 +2643,6 @@ struct mp_weno_ctx {
   double* part = nullptr;     // reduction partials (kDiagSlots per chunk)
   double* diag = nullptr;     // n_inst * MP_DIAG_LEN
   double* pfs = nullptr;      // n_inst * kPfsLen Phase-Field scalars
-  int swz = -1;               // XCD-aware tile order: 1 on, 0 off, -1 on for
-                              // groups of several instances (measured: it
-                              // keeps each small instance on one L2 and costs
-                              // a few percent on a single grid)
   hipGraphExec_t graph[2] = {nullptr, nullptr};   // [external dt?]
   // kChain consecutive steps (device CFL step) captured as one graph
   static constexpr int kChain = 16;
@@ -2686,8 +2704,7 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
   const Bracket* b = (s < 3 && !pf) ? c->next_bracket(br) : nullptr;
   const int w = b ? b->which : 0;
   if (w == 1 || w == 3) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
-  auto swz = [c](const Group& G) {
-    if (c->swz >= 0) return c->swz;
+  auto swz = [](const Group& G) {
     if (G.swz >= 0) return G.swz;
     return G.ids.size() > 1 ? 1 : 0;
   };
@@ -3029,16 +3046,17 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
   if (!c) return MP_ERR_OOM;
   c->opt = *opt;
   c->stream = (hipStream_t)hip_stream;
+  // initial tile shapes and tile order from the environment (indices into
+  // kXS / kYX, kYY; 0 / 1 for the order), one value for every group or a
+  // comma-separated list with one entry per group in group order (d, then
+  // N, ascending; a short list repeats its last entry); later changed only
+  // by mp_weno_autotune.  The comparison schemes are built with the default
+  // shapes only.
   const char* sw = std::getenv("MPWENO_XCD_SWIZZLE");
-  if (sw) c->swz = std::atoi(sw) ? 1 : 0;
-  // initial tile shapes (indices into kXS / kYX, kYY; later changed only by
-  // mp_weno_autotune)
   const char* xsh = std::getenv("MPWENO_XSHAPE");
   const char* ysh = std::getenv("MPWENO_YSHAPE");
-  // (the comparison schemes are built with the default shapes only)
   const bool cmp = opt->recon >= MP_RECON_WENO_JS;
-  const int xv0 = xsh && !cmp ? std::min(std::max(std::atoi(xsh), 0), kXVar - 1) : 0;
-  const int yv0 = ysh && !cmp ? std::min(std::max(std::atoi(ysh), 0), kYVar - 1) : 0;
+  int ngroup = 0;
   const size_t n = (size_t)n_inst;
   if (hipMalloc(&c->dt, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&c->t, sizeof(double) * n) != hipSuccess ||
@@ -3272,8 +3290,12 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         zm[v] = tile_map(G.zs[v]);
         ok = ok && hipMalloc(&G.zmap[v], sizeof(int2) * std::max<size_t>(zm[v].size(), 1)) == hipSuccess;
       }
-      G.xv = N > kMaxNT ? 0 : xv0;
-      G.yv = N > kMaxNT ? 0 : yv0;
+      if (!cmp && N <= kMaxNT) {
+        G.xv = xsh ? std::min(std::max(env_entry(xsh, ngroup), 0), kXVar - 1) : 0;
+        G.yv = ysh ? std::min(std::max(env_entry(ysh, ngroup), 0), kYVar - 1) : 0;
+      }
+      if (sw) G.swz = env_entry(sw, ngroup) ? 1 : 0;
+      ++ngroup;
       c->groups.push_back(G);
       if (!ok) {
         mp_weno_destroy(c);
@@ -3625,12 +3647,19 @@ mp_status mp_weno_autotune(mp_weno_ctx* c, int32_t reps, int32_t* choice) {
             }
             tmin[xv][yv][sw] = std::min(tmin[xv][yv][sw], ms);
           }
+    // a later candidate must be faster by more than 1 %: near-ties keep the
+    // earlier one, so that repeated set-ups choose alike
     float best = INFINITY;
     int bx = 0, by = 0, bs = 0;
     for (int xv = 0; xv < nxv; ++xv)
       for (int yv = 0; yv < nyv; ++yv)
         for (int sw = 0; sw < 2; ++sw)
-          if (tmin[xv][yv][sw] < best) { best = tmin[xv][yv][sw]; bx = xv; by = yv; bs = sw; }
+          if (tmin[xv][yv][sw] < 0.99f * best) {
+            best = tmin[xv][yv][sw];
+            bx = xv;
+            by = yv;
+            bs = sw;
+          }
     G.xv = bx;
     G.yv = by;
     G.swz = bs;

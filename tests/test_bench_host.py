@@ -43,6 +43,33 @@ def test_stage_counters_lookup(tmp_path, monkeypatch):
     assert c["flops32"] == 360.0 and c["traffic"] == (90 + 20) * 1024.0
 
 
+def test_tiles_key_and_env():
+    """The tile choice as the bench line reports it and as --tiles takes it:
+    one entry when every group agrees, else one per group of (d, N) in
+    ascending order (the library's group order), whatever the instance
+    order."""
+    import numpy as np
+    from types import SimpleNamespace as NS
+    ws = [NS(ndim=2, N=3), NS(ndim=1, N=2), NS(ndim=2, N=2), NS(ndim=2, N=3)]
+    args = NS(tiles=None)
+    same = np.array([[128, 16, 16, 1]] * 3 + [[128, 16, 16, 1]])
+    same[1] = [128, 0, 0, 1]
+    # a 1D group has no y tile (0 x 0)
+    assert bench.tiles_key(args, ws, same) == "x128/y0x0/xcd,x128/y16x16/xcd,x128/y16x16/xcd"
+    t = np.array([[64, 32, 8, 0], [256, 0, 0, 1], [128, 16, 24, 1], [64, 32, 8, 0]])
+    key = bench.tiles_key(args, ws, t)
+    assert key == "x256/y0x0/xcd,x128/y16x24/xcd,x64/y32x8/plain"
+    env = bench.tiles_env(key)
+    assert env == {"MPWENO_XSHAPE": "0,1,2", "MPWENO_YSHAPE": "0,2,1",
+                   "MPWENO_XCD_SWIZZLE": "1,1,0"}
+    two = [NS(ndim=2, N=2), NS(ndim=2, N=3)]
+    assert bench.tiles_key(args, two, np.array([[128, 16, 16, 1]] * 2)) == "x128/y16x16/xcd"
+    assert bench.tiles_env("x128/y16x16/xcd") == {
+        "MPWENO_XSHAPE": "1", "MPWENO_YSHAPE": "0", "MPWENO_XCD_SWIZZLE": "1"}
+    assert bench.tiles_key(NS(tiles="x64/y16x16/plain"), two, None) == "x64/y16x16/plain"
+    assert bench.tiles_key(args, two, None) == "default"
+
+
 def test_stage_counters_without_table(monkeypatch, tmp_path):
     monkeypatch.setattr(bench, "COUNTER_TABLE", str(tmp_path / "missing.md"))
     assert bench.stage_counters("wl", "fp64", "x64/y16x16/plain")["traffic"] is None

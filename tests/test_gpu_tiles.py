@@ -1,5 +1,5 @@
-"""Tile shapes and the autotuner: every x-strip width and y-tile shape gives
-the same states bitwise (a shape changes which workgroup computes a cell,
+"""Tile shapes and the autotuner: every x-strip width and y-tile shape (one
+for all groups of instances, or one per group) gives the same states bitwise (a shape changes which workgroup computes a cell,
 never its arithmetic), and mp_weno_autotune keeps the states, the time and
 the step count, returns valid shapes, and the tuned solver reproduces the
 untuned one bitwise."""
@@ -43,14 +43,19 @@ def _run(ws, K, env):
     return out
 
 
-@pytest.mark.parametrize("xs,ys", [(1, 0), (0, 1), (1, 1), (2, 2)])
+@pytest.mark.parametrize("xs,ys", [(1, 0), (0, 1), (1, 1), (2, 2), ("2,1,0", "1,2")])
 @pytest.mark.parametrize("precision", [I.PREC_FP64, I.PREC_MIXED])
 def test_tile_shapes_bitwise(xs, ys, precision):
     ws = _cases()
     for w in ws:
         w.opts.precision = precision
     ref = _run(ws, 3, {"MPWENO_XSHAPE": 0, "MPWENO_YSHAPE": 0})
-    got = _run(ws, 3, {"MPWENO_XSHAPE": xs, "MPWENO_YSHAPE": ys})
+    env = {"MPWENO_XSHAPE": xs, "MPWENO_YSHAPE": ys}
+    if isinstance(xs, str):
+        # one entry per group ((d, N) = (1, 2), (2, 2), (2, 3)), a short list
+        # repeating its last entry, and the tile order per group too
+        env["MPWENO_XCD_SWIZZLE"] = "1,0"
+    got = _run(ws, 3, env)
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
 
