@@ -7,7 +7,8 @@
 // instance by binary search over per-instance tile offsets, so a batch of
 // uneven instances is one launch per sweep.  One RK stage of a d-dimensional
 // group is d launches:
-//   k_sweep_x : one workgroup per (instance, row, strip of up to 254 cells).
+//   k_sweep_x : one workgroup per (instance, strip of up to 254 cells of its
+//               rows laid end to end, each row with its ghost cells).
 //               Each lane converts one cell to primitives into an LDS row,
 //               reconstructs its cell along x from the five LDS neighbours,
 //               trades its minus-side face state with the left neighbour
@@ -47,7 +48,7 @@ constexpr int kMaxN = 8;          // phases built
 constexpr int kMaxNT = 5;         // phases built with every tile shape (above: the defaults)
 constexpr int kMaxN3 = 3;         // phases built in 3D
 // Tile shapes (chosen per group by mp_weno_autotune; index 0 is the default):
-// x sweep strips of kXS[v] lanes (kXS[v] - 2 output cells), y and z sweep
+// x sweep strips of kXS[v] lanes (at most kXS[v] - 2 output cells), y and z sweep
 // tiles of kYX[v] x kYY[v] lanes (kYY[v] - 2 output lines; one shape for both
 // in 3D).  The Phase-Field sweeps use
 // the defaults.
@@ -368,9 +369,6 @@ void k_sweep_x(const Desc* __restrict__ descs,
   const StageArgs a = stage_args(d, stage);
   // an instance whose step is 0 (retired at its end time) is left as it is
   if (a.mode == 1 && *a.dt == 0.0) return;
-  const int ns = (g.nx + BX - 3) / (BX - 2);
-  const int local = it.y;
-  const int y = local / ns;
   constexpr int NV = 2 * N + D + 1;
   constexpr int NU = NV;
   constexpr int NF = 2 * N + 2 * D + 4;
@@ -386,29 +384,60 @@ void k_sweep_x(const Desc* __restrict__ descs,
   double (*sprim)[BX + 4] = reinterpret_cast<double (*)[BX + 4]>(sraw);
   double (*sflux)[BX] = reinterpret_cast<double (*)[BX]>(sraw);
 
+  // The rows (ny nz of them) are laid end to end, each with its three ghost
+  // cells on either side (nx + 6 cells a row), and cut into strips of BX
+  // lanes that overlap by two: lane l of strip s holds cell v = s (BX - 2)
+  // - 1 + l of that sequence and its neighbours along x are lanes l -+ 1.
+  // Lanes 1 .. BX - 2 whose cell is a grid cell are the strip's outputs;
+  // ghost cells stand in for the end conditions (every lane's reconstruction
+  // of a grid or first ghost cell reads its own row only), and cells past
+  // the last row are computed and dropped.  So a row shorter than a strip
+  // leaves few of its lanes idle (six per row, two per strip).
   const int l = threadIdx.x;
-  const int x0 = (local - y * ns) * (BX - 2);
-  const int xi = x0 - 1 + l;
-  const int64_t row = (int64_t)y * g.nx;
+  const int lw = g.nx + 6;
   const int64_t nc = g.nc;
+  const int64_t v0 = (int64_t)it.y * (BX - 2) - 1;
+  // uniform over the strip: the row of its first cell, and the base row of
+  // its loads and stores (one row earlier, where the first ghost cells may
+  // lie), so that every lane addresses base + a 32-bit offset
+  const int64_t yb = v0 > 0 ? v0 / lw : 0;
+  const int dv0 = (int)(v0 - yb * lw);                  // in [-1, lw)
+  const int ylo = yb > 0 ? -1 : 0;                      // base row - yb
+  const int yhi = (int)std::min<int64_t>((int64_t)g.ny * g.nz - 1 - yb, INT32_MAX / 2);
+  const int64_t row = (yb + ylo) * g.nx;
+  // cell k of the strip (lanes 0 .. BX - 1 are k = 0 .. BX - 1, their
+  // ghost cells k = -2, -1, BX, BX + 1): its x and the offset of its row
+  // from the base row; the row is clamped to the grid (x then lies outside
+  // it, and the end conditions map it)
+  auto cell_of = [&](int k, int& rx) -> int {
+    const int dv = dv0 + k;                             // >= -3
+    int r = dv >= 0 ? (int)((unsigned)dv / (unsigned)lw) : -1;
+    r = r < -yb ? (int)-yb : (r > yhi ? yhi : r);
+    rx = dv - r * lw - 3;
+    return (r - ylo) * g.nx;
+  };
+  int xi;
+  const int roff = cell_of(l, xi);
 
-  auto put_prim = [&](int x, int slot) {
+  auto put_prim = [&](int k, int slot) {
+    int x;
+    const int ro = cell_of(k, x);
     const int xm = bc_map(x, g.nx, g.bcx0, g.bcx1);
     Cons<N, D> c;
-    load_cons<N, D>(a.Uk, nc, row + xm, c);
+    load_cons<N, D>(a.Uk, nc, row + (unsigned)(ro + xm), c);
     if (bc_mirror(x, g.nx, g.bcx0, g.bcx1)) c.mom[0] = -c.mom[0];
     Prim<N, D> v;
     cons_to_prim<N, D>(c, e, v);
 #pragma unroll
     for (int p = 0; p < N; ++p) { sprim[p][slot] = v.m[p]; sprim[N + p][slot] = v.a[p]; }
 #pragma unroll
-    for (int k = 0; k < D; ++k) sprim[2 * N + k][slot] = v.u[k];
+    for (int k2 = 0; k2 < D; ++k2) sprim[2 * N + k2][slot] = v.u[k2];
     sprim[2 * N + D][slot] = v.P;
   };
 
   const int xm = bc_map(xi, g.nx, g.bcx0, g.bcx1);
   Cons<N, D> ub;
-  load_cons<N, D>(a.Uk, nc, row + xm, ub);
+  load_cons<N, D>(a.Uk, nc, row + (unsigned)(roff + xm), ub);
   if (bc_mirror(xi, g.nx, g.bcx0, g.bcx1)) ub.mom[0] = -ub.mom[0];
   {
     Prim<N, D> v;
@@ -419,8 +448,8 @@ void k_sweep_x(const Desc* __restrict__ descs,
     for (int k = 0; k < D; ++k) sprim[2 * N + k][l + 2] = v.u[k];
     sprim[2 * N + D][l + 2] = v.P;
   }
-  if (l < 2) put_prim(x0 - 3 + l, l);
-  if (l >= BX - 2) put_prim(x0 - 1 + l + 2, l + 4);
+  if (l < 2) put_prim(l - 2, l);
+  if (l >= BX - 2) put_prim(l + 2, l + 4);
   __syncthreads();
 
   Face<N, D> fm, fp;
@@ -468,9 +497,9 @@ void k_sweep_x(const Desc* __restrict__ descs,
 #pragma unroll
       for (int p = 0; p < N; ++p) {
         const bool in = xq >= 0;
-        G[p] = in ? gptr(d.pf_g)[(int64_t)p * nc + row + xo] : 0.0;
-        kf[p] = in ? 0.5 * (gptr(d.pf_k)[(int64_t)p * nc + row + xo] +
-                            gptr(d.pf_k)[(int64_t)p * nc + row + xq]) : 0.0;
+        G[p] = in ? gptr(d.pf_g)[(int64_t)p * nc + row + (unsigned)(roff + xo)] : 0.0;
+        kf[p] = in ? 0.5 * (gptr(d.pf_k)[(int64_t)p * nc + row + (unsigned)(roff + xo)] +
+                            gptr(d.pf_k)[(int64_t)p * nc + row + (unsigned)(roff + xq)]) : 0.0;
       }
       pf_flux<N, D>(fp, R, G, kf, e, F);
     } else {
@@ -488,7 +517,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
     else return sflux[c][l - 1];
   };
 
-  if (l >= 1 && l < BX - 1 && xi < g.nx) {
+  if (l >= 1 && l < BX - 1 && xi >= 0 && xi < g.nx) {
     double L[NU];
     if constexpr (PFM == kPfFlux) {
 #pragma unroll
@@ -512,7 +541,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
 #pragma unroll
       for (int p = 0; p < N; ++p) L[N + D + 1 + p] += ub.a[p] * isa * opk[p] * du;
     }
-    const int64_t idx = row + xi;
+    const int64_t idx = row + (unsigned)(roff + xi);
     if constexpr (D == 1) {
       finish_cell<N, D>(a, nc, idx, ub, L);
     } else {
@@ -2334,6 +2363,13 @@ int env_entry(const char* s, int g) {
   return std::atoi(s);
 }
 
+// Strips of the x sweep over a grid: its ny nz rows of nx + 6 cells (the
+// grid cells and three ghost cells on either side) laid end to end, bx - 2
+// new cells a strip.
+int64_t x_strips(const Grid& g, int bx) {
+  return ((int64_t)g.ny * g.nz * (g.nx + 6) + bx - 3) / (bx - 2);
+}
+
 using StageFn = void (*)(const Group&, int stage, int swz, hipStream_t);
 using RedFn = void (*)(const Group&, double* part, hipStream_t);
 using DtFn = void (*)(const Group&, double* part, double cfl, int advance, hipStream_t);
@@ -2443,8 +2479,7 @@ __global__ void k_put_desc(Desc d, Desc* dst) {
 // the descriptor at desc (a group of one: no tile map is read)
 template <int N, int D, typename W, int PFM>
 void launch_rhs_single(const Desc* desc, const Grid& g, hipStream_t s) {
-  const int64_t nstrip = (g.nx + kXS[0] - 3) / (kXS[0] - 2);
-  hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM, kXS[0]>), dim3((unsigned)(nstrip * g.ny * g.nz)),
+  hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM, kXS[0]>), dim3((unsigned)x_strips(g, kXS[0])),
                      dim3(kXS[0]), 0, s, desc, nullptr, 1, 3, 0);
   if constexpr (D >= 2) {
     constexpr int oy = kYY[0] - 2;
@@ -3206,8 +3241,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
         int64_t top = G.rs.back() + (I.nc + d.chunk - 1) / d.chunk;
         G.rs.push_back((int)std::min<int64_t>(top, INT32_MAX));
         for (int v = 0; v < kXVar; ++v) {
-          const int64_t nstrip = (g.nx + kXS[v] - 3) / (kXS[v] - 2);
-          const int64_t nx = G.xs[v].back() + (int64_t)g.ny * g.nz * nstrip;
+          const int64_t nx = G.xs[v].back() + x_strips(g, kXS[v]);
           top = std::max(top, nx);
           G.xs[v].push_back((int)std::min<int64_t>(nx, INT32_MAX));
         }
