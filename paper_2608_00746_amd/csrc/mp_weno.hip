@@ -306,6 +306,47 @@ __device__ __forceinline__ void finish_cell(const StageArgs& a, int64_t nc,
 }
 
 // ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// sum_d (|u_d| + c) / dx_d of a cell: the CFL rate of its cell average
+// (contraction off: the x sweep's first stage computes it too, and the two
+// must agree to the bit)
+template <int N, int D>
+__device__ __forceinline__ double cfl_rate(const Prim<N, D>& v, const Eos& e, const Grid& g) {
+#pragma clang fp contract(off)
+  double rho = 0.0;
+#pragma unroll
+  for (int p = 0; p < N; ++p) rho += v.m[p];
+  double num, den;
+  mix_rc2_parts<N>(v.a, v.P, e, g.model, num, den);
+  const double cs = sound_speed(num, den, rho);
+  double s = (fabs(v.u[0]) + cs) * g.rdx;
+  if constexpr (D > 1) s += (fabs(v.u[1]) + cs) * g.rdy;
+  if constexpr (D > 2) s += (fabs(v.u[2]) + cs) * g.rdz;
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = -1.0;
+  if (threadIdx.x == 0) {
+    r = sh[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, sh[k]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
 // x sweep
 // ---------------------------------------------------------------------------
 // Waves per SIMD the sweeps are compiled for: one or two phases fit 3 (or 4)
@@ -361,14 +402,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, BX),
                           amdgpu_waves_per_eu(sweep_waves<N, D, W, PFM, true>(), 8)))
 void k_sweep_x(const Desc* __restrict__ descs,
                                                  const int2* __restrict__ map,
-                                                 int ninst, int stage, int swz) {
-  const int2 it = locate(map, ninst, xcd_item(blockIdx.x, gridDim.x, swz));
+                                                 int ninst, int stage, int swz,
+                                                 double* __restrict__ cflp) {
+  const int item = xcd_item(blockIdx.x, gridDim.x, swz);
+  const int2 it = locate(map, ninst, item);
   const Desc d = descs[it.x];   // by value: loaded once, kept in registers
   const Grid& g = d.g;
   const Eos& e = d.e;
   const StageArgs a = stage_args(d, stage);
-  // an instance whose step is 0 (retired at its end time) is left as it is
-  if (a.mode == 1 && *a.dt == 0.0) return;
+  // an instance whose step is 0 (retired at its end time) is left as it is;
+  // with cflp (the first stage of a step in 2D and 3D) the step is not known
+  // yet: the sweep reduces the CFL rate of its output cells (of U^n) into
+  // cflp[item], from which the step is taken before the transverse sweeps
+  if (!cflp && a.mode == 1 && *a.dt == 0.0) return;
   constexpr int NV = 2 * N + D + 1;
   constexpr int NU = NV;
   constexpr int NF = 2 * N + 2 * D + 4;
@@ -439,9 +485,12 @@ void k_sweep_x(const Desc* __restrict__ descs,
   Cons<N, D> ub;
   load_cons<N, D>(a.Uk, nc, row + (unsigned)(roff + xm), ub);
   if (bc_mirror(xi, g.nx, g.bcx0, g.bcx1)) ub.mom[0] = -ub.mom[0];
+  const bool own = l >= 1 && l < BX - 1 && xi >= 0 && xi < g.nx;   // an output cell
+  double rate = 0.0;
   {
     Prim<N, D> v;
     cons_to_prim<N, D>(ub, e, v);
+    if (cflp && own) rate = cfl_rate<N, D>(v, e, g);
 #pragma unroll
     for (int p = 0; p < N; ++p) { sprim[p][l + 2] = v.m[p]; sprim[N + p][l + 2] = v.a[p]; }
 #pragma unroll
@@ -450,6 +499,11 @@ void k_sweep_x(const Desc* __restrict__ descs,
   }
   if (l < 2) put_prim(l - 2, l);
   if (l >= BX - 2) put_prim(l + 2, l + 4);
+  if (cflp) {
+    __shared__ double scfl[BX / 64];
+    const double r = block_max(rate, scfl);
+    if (l == 0) cflp[item] = r;
+  }
   __syncthreads();
 
   Face<N, D> fm, fp;
@@ -517,7 +571,7 @@ void k_sweep_x(const Desc* __restrict__ descs,
     else return sflux[c][l - 1];
   };
 
-  if (l >= 1 && l < BX - 1 && xi >= 0 && xi < g.nx) {
+  if (own) {
     double L[NU];
     if constexpr (PFM == kPfFlux) {
 #pragma unroll
@@ -1003,29 +1057,6 @@ __global__ void k_amr_dt(const int* __restrict__ ids, int n, double* dt) {
   for (int k = 0; k < n; ++k) dt[ids[k]] = m;
 }
 
-// ---------------------------------------------------------------------------
-// reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ double block_max(double v, double* sh) {
-  v = wave_max(v);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  if (l == 0) sh[w] = v;
-  __syncthreads();
-  double r = -1.0;
-  if (threadIdx.x == 0) {
-    r = sh[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, sh[k]);
-  }
-  __syncthreads();
-  return r;
-}
-
 // Cells per reduction workgroup: a multiple of kRedBlock chosen per instance
 // (Desc::chunk) so that an instance has at most kMaxChunks chunks: small
 // grids still spread over many workgroups, and the per-instance finishers
@@ -1050,16 +1081,7 @@ __global__ __launch_bounds__(kRedBlock) void k_dt(const Desc* __restrict__ descs
     load_cons<N, D>(gptr(d.U), g.nc, i, c);
     Prim<N, D> v;
     cons_to_prim<N, D>(c, e, v);
-    double rho = 0.0;
-#pragma unroll
-    for (int p = 0; p < N; ++p) rho += v.m[p];
-    double num, den;
-    mix_rc2_parts<N>(v.a, v.P, e, g.model, num, den);
-    const double cs = sound_speed(num, den, rho);
-    double s = (fabs(v.u[0]) + cs) * g.rdx;
-    if constexpr (D > 1) s += (fabs(v.u[1]) + cs) * g.rdy;
-    if constexpr (D > 2) s += (fabs(v.u[2]) + cs) * g.rdz;
-    smax = fmax(smax, s);
+    smax = fmax(smax, cfl_rate<N, D>(v, e, g));
   }
   const double r = block_max(smax, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = r;
@@ -1068,15 +1090,26 @@ __global__ __launch_bounds__(kRedBlock) void k_dt(const Desc* __restrict__ descs
 // one workgroup per instance: dt = cfl / max, clipped to t_end - t; with
 // advance also the instance's time and step count move on (nothing in the
 // RK stages reads them)
-__global__ __launch_bounds__(kRedBlock) void k_dt_finish(
+// (a workgroup of kDtBlock lanes, four independent loads in flight per lane:
+// an instance's partials are one per x strip when the first x sweep of the
+// step reduces them, 10^5 and more on a large 3D grid)
+constexpr int kDtBlock = 1024;
+__global__ __launch_bounds__(kDtBlock) void k_dt_finish(
     const Desc* __restrict__ descs, const int* __restrict__ start,
     const double* __restrict__ part, double cfl, int advance) {
-  __shared__ double sh[kRedBlock / 64];
+  __shared__ double sh[kDtBlock / 64];
   const Desc& d = descs[blockIdx.x];
-  double m = 0.0;
-  for (int i = start[blockIdx.x] + threadIdx.x; i < start[blockIdx.x + 1]; i += kRedBlock)
-    m = fmax(m, part[i]);
-  const double r = block_max(m, sh);
+  const int b = start[blockIdx.x], n = start[blockIdx.x + 1];
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  int i = b + threadIdx.x;
+  for (; i + 3 * kDtBlock < n; i += 4 * kDtBlock) {
+    m0 = fmax(m0, part[i]);
+    m1 = fmax(m1, part[i + kDtBlock]);
+    m2 = fmax(m2, part[i + 2 * kDtBlock]);
+    m3 = fmax(m3, part[i + 3 * kDtBlock]);
+  }
+  for (; i < n; i += kDtBlock) m0 = fmax(m0, part[i]);
+  const double r = block_max(fmax(fmax(m0, m1), fmax(m2, m3)), sh);
   if (threadIdx.x == 0) {
     const double t = *gptr(d.t);
     double dt = cfl / r;
@@ -2338,6 +2371,8 @@ struct Group {
                                    // each small instance on one L2 and costs a
                                    // few percent on a single grid)
   int* rstart = nullptr;           // reduction-chunk offsets on the device
+  int* xstart[kXVar] = {};         // x-strip offsets per instance on the device
+  double* cflp = nullptr;          // CFL rate per x strip (first stage of a step)
   size_t part_off = 0;             // this group's reduction partials
   int nlev = 0;                    // multigrid levels (every instance has them all)
   int mg_fuse = 0;                 // first level run by the fused coarse cycle
@@ -2377,11 +2412,15 @@ using DtFn = void (*)(const Group&, double* part, double cfl, int advance, hipSt
 // finishers (rtol is used by the finishers that test convergence)
 using PfFn = void (*)(const Group&, double* part, int flag, double rtol, hipStream_t);
 
+// stage | kStageCfl: the x sweep also reduces the CFL rates of U^n per strip
+constexpr int kStageCfl = 8;
+
 template <int N, int D, typename W, int PFM, int V>
 void launch_x(const Group& G, int stage, int swz, hipStream_t s) {
   const int n = (int)G.ids.size();
+  double* cflp = (stage & kStageCfl) ? G.cflp : nullptr;
   hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM, kXS[V]>), dim3(G.xs[V][n]), dim3(kXS[V]), 0, s,
-                     G.desc, G.xmap[V], n, stage, swz);
+                     G.desc, G.xmap[V], n, stage & ~kStageCfl, swz, cflp);
 }
 
 // transverse sweep along DIR (1: y, 2: z) of a D-dimensional group
@@ -2443,7 +2482,7 @@ void launch_dt(const Group& G, double* part, double cfl, int advance, hipStream_
   const int n = (int)G.ids.size();
   hipLaunchKernelGGL((k_dt<N, D>), dim3(G.rs[n]), dim3(kRedBlock), 0, s, G.desc, G.rmap,
                      n, part + G.part_off);
-  hipLaunchKernelGGL(k_dt_finish, dim3(n), dim3(kRedBlock), 0, s, G.desc, G.rstart,
+  hipLaunchKernelGGL(k_dt_finish, dim3(n), dim3(kDtBlock), 0, s, G.desc, G.rstart,
                      part + G.part_off, cfl, advance);
 }
 
@@ -2480,7 +2519,7 @@ __global__ void k_put_desc(Desc d, Desc* dst) {
 template <int N, int D, typename W, int PFM>
 void launch_rhs_single(const Desc* desc, const Grid& g, hipStream_t s) {
   hipLaunchKernelGGL((k_sweep_x<N, D, W, PFM, kXS[0]>), dim3((unsigned)x_strips(g, kXS[0])),
-                     dim3(kXS[0]), 0, s, desc, nullptr, 1, 3, 0);
+                     dim3(kXS[0]), 0, s, desc, nullptr, 1, 3, 0, nullptr);
   if constexpr (D >= 2) {
     constexpr int oy = kYY[0] - 2;
     const int64_t ntx = (g.nx + kYX[0] - 1) / kYX[0];
@@ -2699,6 +2738,10 @@ struct mp_weno_ctx {
   int amr_maxcells = 0;       // largest fine grid (ghost-fill launch size)
   std::string err;
   int profile = 0;            // Bracket::which
+  // the step in progress takes its CFL step in its first stage (2D and 3D
+  // groups: from the rates the x sweeps reduce), with this time advance
+  bool cfl_pending = false;
+  int cfl_advance = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t ev_used = 0;
 
@@ -2746,8 +2789,20 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
   // the comparison schemes and the Phase-Field flux run the default shapes
   const int cmp = c->opt.recon >= MP_RECON_WENO_JS;
   const int v = pf ? kPfFlux : (cmp ? kRiemannCmp : kRiemann);
+  // the first stage of a step: 2D and 3D groups reduce the CFL rates of U^n
+  // in their x sweeps, and the step (and time advance) follows from them
+  // before the transverse sweeps, which are the first to use it
+  const bool cfl = s == 0 && !pf && c->cfl_pending;
   for (const Group& G : c->groups)
-    T.sx[v][G.N][G.D][prec][v ? 0 : G.xv](G, s, swz(G), c->stream);
+    T.sx[v][G.N][G.D][prec][v ? 0 : G.xv](G, s | (cfl && G.D >= 2 ? kStageCfl : 0), swz(G),
+                                         c->stream);
+  if (cfl) {
+    for (const Group& G : c->groups)
+      if (G.D >= 2)
+        hipLaunchKernelGGL(k_dt_finish, dim3(G.ids.size()), dim3(kDtBlock), 0, c->stream, G.desc,
+                           G.xstart[v ? 0 : G.xv], G.cflp, c->opt.cfl, c->cfl_advance);
+    c->cfl_pending = false;
+  }
   if (w == 1) HIPCHK(c, hipEventRecord(b->ev[1], c->stream));
   if (w == 2) HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
   for (const Group& G : c->groups) {
@@ -2762,9 +2817,10 @@ static mp_status enqueue_stage(mp_weno_ctx* c, int s, int pf = 0) {
 }
 
 // CFL step of every instance; advance: also move time and step count on
-static mp_status enqueue_dt(mp_weno_ctx* c, int advance) {
+static mp_status enqueue_dt(mp_weno_ctx* c, int advance, bool only_1d = false) {
   const Table& T = table();
-  for (const Group& G : c->groups) T.dt[G.N][G.D](G, c->part, c->opt.cfl, advance, c->stream);
+  for (const Group& G : c->groups)
+    if (!only_1d || G.D == 1) T.dt[G.N][G.D](G, c->part, c->opt.cfl, advance, c->stream);
   HIPCHK(c, hipGetLastError());
   return MP_OK;
 }
@@ -3023,8 +3079,9 @@ mp_status mp_weno_destroy(mp_weno_ctx* c) {
     (void)hipFree(I.pf); (void)hipFree(I.mgbuf); (void)hipFree(I.d_mg);
   }
   for (auto& G : c->groups) {
-    (void)hipFree(G.desc); (void)hipFree(G.rmap); (void)hipFree(G.rstart);
+    (void)hipFree(G.desc); (void)hipFree(G.rmap); (void)hipFree(G.rstart); (void)hipFree(G.cflp);
     for (auto* m : G.xmap) (void)hipFree(m);
+    for (auto* m : G.xstart) (void)hipFree(m);
     for (auto* m : G.ymap) (void)hipFree(m);
     for (auto* m : G.zmap) (void)hipFree(m);
     for (auto* m : G.lmap) (void)hipFree(m);
@@ -3314,10 +3371,14 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       bool ok = hipMalloc(&G.desc, sizeof(Desc) * m) == hipSuccess &&
                 hipMalloc(&G.rmap, sizeof(int2) * std::max<size_t>(rm.size(), 1)) == hipSuccess &&
                 hipMalloc(&G.rstart, sizeof(int) * (m + 1)) == hipSuccess;
+      size_t most = 1;
       for (int v = 0; v < kXVar; ++v) {
         xm[v] = tile_map(G.xs[v]);
-        ok = ok && hipMalloc(&G.xmap[v], sizeof(int2) * std::max<size_t>(xm[v].size(), 1)) == hipSuccess;
+        most = std::max(most, (size_t)G.xs[v].back());
+        ok = ok && hipMalloc(&G.xmap[v], sizeof(int2) * std::max<size_t>(xm[v].size(), 1)) == hipSuccess &&
+             hipMalloc(&G.xstart[v], sizeof(int) * (m + 1)) == hipSuccess;
       }
+      ok = ok && hipMalloc(&G.cflp, sizeof(double) * most) == hipSuccess;
       for (int v = 0; v < kYVar; ++v) {
         ym[v] = tile_map(G.ys[v]);
         ok = ok && hipMalloc(&G.ymap[v], sizeof(int2) * std::max<size_t>(ym[v].size(), 1)) == hipSuccess;
@@ -3342,7 +3403,9 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
       for (int v = 0; v < kXVar; ++v)
         okc = okc && (xm[v].empty() ||
                       hipMemcpy(H.xmap[v], xm[v].data(), sizeof(int2) * xm[v].size(),
-                                hipMemcpyHostToDevice) == hipSuccess);
+                                hipMemcpyHostToDevice) == hipSuccess) &&
+              hipMemcpy(H.xstart[v], H.xs[v].data(), sizeof(int) * (m + 1),
+                        hipMemcpyHostToDevice) == hipSuccess;
       for (int v = 0; v < kYVar; ++v)
         okc = okc && (ym[v].empty() ||
                       hipMemcpy(H.ymap[v], ym[v].data(), sizeof(int2) * ym[v].size(),
@@ -3738,8 +3801,15 @@ mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
 static mp_status enqueue_step(mp_weno_ctx* c, bool external_dt) {
   const bool early = !external_dt && !c->opt.phase_field && !c->amr_nlinks;
   if (!external_dt) {
-    mp_status s = enqueue_dt(c, early ? 1 : 0);
+    // without coupled instances, 2D and 3D groups take the step from their
+    // first x sweep (no pass of its own over U^n); 1D groups, whose x sweep
+    // finishes the stage, and coupled instances (which share the smallest
+    // step) take it here
+    const bool fuse = !c->amr_nlinks;
+    mp_status s = enqueue_dt(c, early ? 1 : 0, fuse);
     if (s != MP_OK) return s;
+    c->cfl_pending = fuse;
+    c->cfl_advance = early ? 1 : 0;
     if (c->amr_nlinks)
       hipLaunchKernelGGL(k_amr_dt, dim3(1), dim3(64), 0, c->stream, c->amr_ids, c->amr_nids,
                          c->dt);

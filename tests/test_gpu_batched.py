@@ -7,6 +7,7 @@ is one launch per (N, d) group over the tiles of all its instances.
   CFL steps, diagnostics): batching changes which workgroup computes a tile,
   never the arithmetic of a cell or the order of a reduction;
 * per-instance external time steps and per-instance end times;
+* the CFL step a step takes from its first x sweep equals mp_weno_dt's;
 * the 256-instance shock-bubble sweep stays finite and admissible, and its
   sampled instances match their solo runs bitwise.
 """
@@ -90,6 +91,35 @@ def test_batched_bitwise_vs_solo(precision, graph):
     b.close()
     for s in solos:
         s.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_cfl_step_of_the_first_sweep_equals_the_cfl_pass(graph):
+    """In 2D and 3D a step takes its CFL step from the rates its first x
+    sweep reduces (no pass of its own over U^n); mp_weno_dt takes it from a
+    pass over U^n.  Both evaluate the same rate per cell and a maximum, so a
+    run on its own steps and a run fed mp_weno_dt's steps agree bitwise
+    (states and times), over 16 steps (one captured run with graphs)."""
+    import torch
+    ws = _batch_fp64() + [I.shock_vessel_bubble_3d(40, 20, 20)]
+    ws[-1].t_end = 0.0
+    st = torch.cuda.Stream()
+    a = _solver(ws, stream=st, use_graph=graph)
+    b = _solver(ws, stream=st)
+    K = 16
+    t = np.zeros(len(ws))
+    a.advance(K)
+    for _ in range(K):
+        dt = b.dt()
+        t = t + dt
+        b.step(dt)
+    da = a.diag()
+    assert np.array_equal(da[:, 26], t)
+    for i, w in enumerate(ws):
+        assert np.array_equal(a.host(i), b.host(i)), (w.name, i)
+    assert (da[:, 27] == K).all()
+    a.close()
+    b.close()
 
 
 def test_batched_external_dt_and_end_time():
