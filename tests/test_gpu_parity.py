@@ -326,6 +326,9 @@ DEGENERATE = [
     ((1,), I.BC_PERIODIC), ((1,), I.BC_OUTFLOW), ((1,), I.BC_SYMMETRY), ((2,), I.BC_SYMMETRY),
     ((1, 1), I.BC_OUTFLOW), ((1, 1), I.BC_SYMMETRY), ((2, 1), I.BC_PERIODIC),
     ((1, 1, 1), I.BC_PERIODIC), ((2, 1, 3), I.BC_OUTFLOW), ((1, 2, 1), I.BC_SYMMETRY),
+    # rows of two and five cells: an x strip holds many rows end to end, each
+    # with its own ghost cells (mirror images at symmetry ends)
+    ((9, 2), I.BC_SYMMETRY), ((13, 5), I.BC_PERIODIC), ((4, 3, 2), I.BC_SYMMETRY),
 ]
 
 
