@@ -3800,6 +3800,7 @@ mp_status mp_weno_dt(mp_weno_ctx* c, double* dt, int32_t where) {
 // at the end, so a failed Phase-Field solve leaves it untouched.
 static mp_status enqueue_step(mp_weno_ctx* c, bool external_dt) {
   const bool early = !external_dt && !c->opt.phase_field && !c->amr_nlinks;
+  c->cfl_pending = false;          // (a step that failed may have left it set)
   if (!external_dt) {
     // without coupled instances, 2D and 3D groups take the step from their
     // first x sweep (no pass of its own over U^n); 1D groups, whose x sweep
