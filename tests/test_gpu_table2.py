@@ -38,7 +38,11 @@ def _run(model, pf, limiter, t_stop):
                                          phase_field=pf, energy_limiter=limiter))
     s = Solver([w], use_graph=not pf, stream=torch.cuda.Stream())
     worst, first_bad, broke, t = 0.0, None, None, 0.0
+    next_report = 0.0
     while t < t_stop * (1 - 1e-12):
+        if t >= next_report:         # progress for long runs (pytest -s)
+            print(f"  model {model} pf {pf} limiter {limiter}: t {t:.5f}", flush=True)
+            next_report = t + 0.001
         try:
             s.advance(1 if pf else 10)
         except MpWenoError as err:
