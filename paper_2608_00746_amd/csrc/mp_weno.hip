@@ -71,7 +71,7 @@ static_assert(kPartSlots >= kDiagSlots && kPartSlots >= 1 + kMaxN * kMaxN + 2 * 
 // residual at the previous start, the run's best recurrence residual and the
 // iteration it was reached at
 constexpr int kPfsLen = 96;
-constexpr int kPfFields = 8;      // Phase-Field work arrays of N fields each
+constexpr int kPfFields = 9;      // Phase-Field work arrays of N fields each
 // floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
 // is solvable for every right side of zero total and stays conditioned; only
 // cells with phi or 1 - phi below ~1e-6 see it
@@ -171,6 +171,7 @@ struct Desc {
   double* pf_ap;             // CG s = K p                         [N][cells]
   double* pf_w;              // CG w = K u                         [N][cells]
   double* pf_u;              // preconditioned residual u = M^-1 r [N][cells]
+  double* pf_qp;             // Q_p of the solve before the last   [N][cells]
   const struct MgLevel* mg;  // multigrid levels of the preconditioner
   int nlev;
   double* pf_g;              // dQ_p/dx_d at upper faces           [d][N][cells]
@@ -1767,6 +1768,33 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict
   }
 }
 
+// Start of the Q solve of a step (before its first start pass): with
+// extrapolate, Q = 2 Q - Q_prev (Q holds the last step's solution, Q_prev
+// the one before it: a linear extrapolation in time, so the solve starts
+// O(dt^2) from its solution where the warm start alone is O(dt) away);
+// then, in both cases, Q_prev = the last solution.
+template <int N, int D>
+__global__ __launch_bounds__(kRedBlock) void k_pf_guess(const Desc* __restrict__ descs,
+                                                        const int2* __restrict__ map, int ninst,
+                                                        int extrapolate) {
+  const int2 it = locate(map, ninst, chunk_item());
+  const Desc& d = descs[it.x];
+  const int64_t nc = d.g.nc;
+  const int64_t c0 = (int64_t)it.y * d.chunk;
+  const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
+  gdouble* Q = gptr(d.pf_q);
+  gdouble* Qp = gptr(d.pf_qp);
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+      const int64_t ip = (int64_t)p * nc + i;
+      const double q = Q[ip];
+      if (extrapolate) Q[ip] = fma(2.0, q, -Qp[ip]);
+      Qp[ip] = q;
+    }
+  }
+}
+
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_pf_cg_dots(const Desc* __restrict__ descs,
                                                           const int2* __restrict__ map, int ninst,
@@ -2446,6 +2474,7 @@ void launch_pf_cells(const Group& G, double* part, int flag, double, hipStream_t
   if constexpr (KIND == 3) hipLaunchKernelGGL((k_pf_cg_axpy<N, D>), grid, blk, 0, s, G.desc, G.rmap, n);
   if constexpr (KIND == 4) hipLaunchKernelGGL((k_pf_cg_dots<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, pt);
   if constexpr (KIND == 5) hipLaunchKernelGGL((k_pf_grad<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, flag);
+  if constexpr (KIND == 6) hipLaunchKernelGGL((k_pf_guess<N, D>), grid, blk, 0, s, G.desc, G.rmap, n, flag);
 }
 
 // multigrid passes over the work items of level l (kind: 0 level-0 weights,
@@ -2561,7 +2590,7 @@ struct Table {
   StageFn sz3[3][kMaxN3 + 1][2][kYVar] = {};    // 3D z sweep (finishes the stage)
   DtFn dt[kMaxN + 1][4] = {};
   RedFn diag[kMaxN + 1][4] = {};
-  PfFn pfc[6][kMaxN + 1][4] = {};          // per-cell PF passes: [kind][N][d]
+  PfFn pfc[7][kMaxN + 1][4] = {};          // per-cell PF passes: [kind][N][d]
   PfFn pfi[4][kMaxN + 1] = {};             // per-instance PF finishers
   MgFn mg[kMaxN + 1][4] = {};
   hipError_t (*mg_lds[kMaxN + 1][4])(int) = {};
@@ -2575,6 +2604,7 @@ void fill_pf(Table& t) {
   t.pfc[3][N][D] = launch_pf_cells<N, D, 3>;
   t.pfc[4][N][D] = launch_pf_cells<N, D, 4>;
   t.pfc[5][N][D] = launch_pf_cells<N, D, 5>;
+  t.pfc[6][N][D] = launch_pf_cells<N, D, 6>;
   t.mg[N][D] = launch_mg<N, D>;
   t.mg_lds[N][D] = mg_fused_lds<N, D>;
 }
@@ -2738,6 +2768,9 @@ struct mp_weno_ctx {
   int amr_maxcells = 0;       // largest fine grid (ghost-fill launch size)
   std::string err;
   int profile = 0;            // Bracket::which
+  // solutions of the Q solve kept in pf_q / pf_qp: 0 none, 1 the last one,
+  // 2 the last two (the next solve starts from their extrapolation)
+  int pf_hist = 0;
   // the step in progress takes its CFL step in its first stage (2D and 3D
   // groups: from the rates the x sweeps reduce), with this time advance
   bool cfl_pending = false;
@@ -2929,6 +2962,13 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
         if (c->pf_flags[i * kPfsLen + kPfsDone + p] == 0.0) { done = false; break; }
     return MP_OK;
   };
+  // the start of a warm solve: the last two solutions extrapolated in time
+  // (or the last one)
+  const int hist = c->pf_hist;
+  if (!cold)
+    for (const Group& G : c->groups)
+      T.pfc[6][G.N][G.D](G, c->part, hist >= 2 ? 1 : 0, rtol, c->stream);
+  c->pf_hist = 0;                  // until this solve has converged
   bool converged = false;
   int it = 0, restart = 0;
   for (; restart <= kMaxRestarts; ++restart) {
@@ -2974,6 +3014,9 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
                   "iterations and %d restarts", rmax, it, std::min(restart, kMaxRestarts));
     return fail(c, MP_ERR_SOLVER, msg);
   }
+  // a cold solve starts the history; a warm one has put the last solution
+  // (if there was one) in pf_qp
+  c->pf_hist = cold ? 1 : std::min(hist + 1, 2);
   return MP_OK;
 }
 
@@ -3284,6 +3327,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           d.pf_ap = I.pf + 5 * f;
           d.pf_w = I.pf + 6 * f;
           d.pf_u = I.pf + 7 * f;
+          d.pf_qp = I.pf + 8 * f;
           d.pf_g = I.pf + kPfFields * f;   // after the kPfFields arrays above
           d.mg = I.d_mg;
           d.nlev = (int)I.lv.size();
@@ -3873,6 +3917,7 @@ mp_status mp_weno_step(mp_weno_ctx* c, const double* dt_dev) {
   }
   // back to the state, time and step count before the step (check_bounds)
   auto restore = [&]() -> mp_status {
+    c->pf_hist = 0;                // Q belongs to the step taken back
     for (auto& I : c->inst)
       HIPCHK(c, hipMemcpyAsync(I.in.U, I.backup, sizeof(double) * I.nU * I.nc,
                                hipMemcpyDeviceToDevice, c->stream));
