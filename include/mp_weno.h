@@ -155,7 +155,8 @@ int32_t mp_weno_max_phases(void);
  * captures on the stream); every later call is ordered on it.
  * Allocates the scratch: two RK stage buffers and one direction accumulator
  * per instance (3 n_U doubles per cell) plus small reduction buffers; with
- * phase_field, (8 + d) N doubles per cell more (k_p, [div J_p], Q_p, the CG
+ * phase_field, (10 + d) N doubles per cell more (k_p, [div J_p], Q_p and the
+ * two solutions before it, the CG
  * vectors r, p, K p, w and u, and the face gradients) and the FP32
  * multigrid hierarchy (6 N floats per cell of every level, 7 N in 3D:
  * about 8 N floats per cell in 2D, 12 N in 1D and 8 N in 3D).
